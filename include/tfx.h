@@ -1,0 +1,158 @@
+/*
+ * tfx.h -- C ABI of the MI355X (gfx950) multichannel FIR / IIR-SOS filter
+ * chain library (libtfx.so).
+ *
+ * What the library computes is the filtering that TorchFX (arXiv 2504.08624)
+ * exposes: FIR filters and coefficient-driven IIR filters applied to
+ * multichannel [channels x samples] signals (Sec. 3, "Design principles and
+ * core features", and the multichannel focus stated in Sec. 1), chained in the
+ * order written (the pipe-operator example of Sec. 3).  The paper gives no
+ * equations; the operations are the textbook ones:
+ *
+ *   FIR  y[c,n] = sum_{k=0}^{min(M-1,n)} h[k] x[c,n-k]
+ *        (causal, zero history, output length N, true convolution)
+ *   SOS  cascade of second-order sections in transposed direct form II,
+ *        coefficient rows [b0 b1 b2 a1 a2] with a0 == 1:
+ *          y[n] = b0 x[n] + s1;  s1 = b1 x[n] - a1 y[n] + s2;  s2 = b2 x[n] - a2 y[n]
+ *        H(z) = (b0 + b1 z^-1 + b2 z^-2) / (1 + a1 z^-1 + a2 z^-2), sections in
+ *        array order, zero initial state unless a state is passed in.
+ *
+ * Conventions for every entry point
+ * ---------------------------------
+ *  - Signals are fp32, row-major: channel c, sample n at  ptr[c*ld + n],
+ *    ld >= N (elements).  Input and output must not overlap (TFX_E_ALIAS).
+ *  - Pointers are DEVICE pointers unless the comment says "host".  The caller
+ *    allocates and owns every buffer (signals, coefficients, states,
+ *    checkpoints, gradients, workspace).  The library keeps no pointer after
+ *    the call returns and allocates no device memory on these calls.
+ *  - `stream` is a hipStream_t (NULL = the legacy default stream).  Every call
+ *    only enqueues work on that stream and returns; results are ready when the
+ *    stream is synchronised.  The library never synchronises.
+ *  - `ws`/`ws_bytes`: caller-owned device workspace, at least the size the
+ *    matching *_workspace_size query returns (TFX_E_WORKSPACE otherwise);
+ *    256-byte alignment required.  One workspace must not be used by two
+ *    calls that may run concurrently.  Its contents need no initialisation
+ *    and are undefined afterwards.
+ *  - Coefficients are read on the device every call, so they may change
+ *    between calls (learned filters) without any re-planning.
+ *  - Errors: argument errors are detected on the host before anything is
+ *    enqueued and return a non-zero tfx_status; tfx_last_error() then gives
+ *    a message (thread-local).  A HIP launch failure returns TFX_E_HIP.
+ *    Asynchronous device faults surface at the caller's next synchronisation,
+ *    as with any HIP kernel.  Nothing aborts or throws across this ABI.
+ *  - Results are bit-identical from run to run for fixed arguments (no
+ *    floating-point atomics, fixed reduction orders).
+ *
+ * Limits: 1 <= C, 0 <= N < 2^40 (N == 0 is a no-op), 1 <= M <= 65536 taps,
+ * 0 <= S <= 256 sections per cascade.
+ */
+#ifndef TFX_H
+#define TFX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum tfx_status {
+    TFX_OK = 0,
+    TFX_E_INVALID_ARG = 1, /* null pointer, negative size, ld < N, bad enum  */
+    TFX_E_UNSUPPORTED = 2, /* valid request this build does not implement    */
+    TFX_E_WORKSPACE = 3,   /* ws NULL / too small / misaligned               */
+    TFX_E_UNSTABLE = 4,    /* host-checked filter with a pole on/outside |z|=1 */
+    TFX_E_ALIAS = 5,       /* output overlaps an input                        */
+    TFX_E_CAPTURE = 6,     /* call not allowed while the stream is captured   */
+    TFX_E_HIP = 7          /* a HIP runtime call failed                       */
+} tfx_status;
+
+/* Arithmetic of the FIR contraction.  Signals stay fp32 in memory for every
+ * mode; the IIR recursion is always fp32. */
+typedef enum tfx_compute {
+    TFX_COMPUTE_F32 = 0,    /* fp32 products, fp32 accumulation              */
+    TFX_COMPUTE_BF16 = 1,   /* bf16 operands on MFMA, fp32 accumulation      */
+    TFX_COMPUTE_F16 = 2,    /* fp16 operands on MFMA, fp32 accumulation      */
+    TFX_COMPUTE_BF16X3 = 3  /* split bf16 hi+lo, 3 MFMA products (~fp32)     */
+} tfx_compute;
+
+typedef enum tfx_fir_algo {
+    TFX_FIR_AUTO = 0,      /* pick by tap count and compute mode             */
+    TFX_FIR_DIRECT = 1,    /* LDS-tiled direct convolution (fp32 only)       */
+    TFX_FIR_TOEPLITZ = 2,  /* MFMA block-Toeplitz product (bf16/fp16/bf16x3) */
+    TFX_FIR_FFT = 3        /* overlap-save FFT (fp32 only)                   */
+} tfx_fir_algo;
+
+typedef enum tfx_stage_kind { TFX_STAGE_FIR = 0, TFX_STAGE_SOS = 1 } tfx_stage_kind;
+
+/* One stage of a chain (host array of these; `coef` is a device pointer).
+ *   FIR: coef = h[len] taps, len = M.
+ *   SOS: coef = [len][5] rows [b0 b1 b2 a1 a2], len = S sections. */
+typedef struct tfx_stage {
+    int32_t kind;
+    int32_t len;
+    const float *coef;
+} tfx_stage;
+
+/* ------------------------------------------------------------ diagnostics */
+
+const char *tfx_status_string(tfx_status s);
+/* Message of the last failing call on this host thread ("" if none). */
+const char *tfx_last_error(void);
+/* Library version as 10000*major + 100*minor + patch. */
+int32_t tfx_version(void);
+/* Samples per IIR tile: the granularity of checkpoints (see tfx_sos). */
+int64_t tfx_sos_tile_length(void);
+
+/* Host-side stability check of a cascade (host pointer, [S][5]): *stable = 1
+ * when every section's poles lie strictly inside the unit circle.  The device
+ * entry points cannot read coefficients on the host, so callers that need
+ * TFX_E_UNSTABLE semantics check here first.  Returns TFX_E_UNSTABLE when not
+ * stable. */
+tfx_status tfx_sos_check_stable(const float *sos_host, int32_t S, int32_t *stable);
+
+/* ------------------------------------------------------ workspace queries */
+
+tfx_status tfx_fir_workspace_size(int64_t C, int64_t N, int32_t M, tfx_compute cmp,
+                                  tfx_fir_algo algo, size_t *bytes);
+tfx_status tfx_sos_workspace_size(int64_t C, int64_t N, int32_t S, size_t *bytes);
+/* stages: host array as for tfx_chain. */
+tfx_status tfx_chain_workspace_size(int64_t C, int64_t N, const tfx_stage *stages,
+                                    int32_t nstages, tfx_compute cmp, size_t *bytes);
+
+/* ---------------------------------------------------------------- forward */
+
+/* FIR filter, every channel with the same taps h[M]. */
+tfx_status tfx_fir(const float *x, float *y, int64_t C, int64_t N, int64_t ldx, int64_t ldy,
+                   const float *h, int32_t M, tfx_compute cmp, tfx_fir_algo algo,
+                   void *ws, size_t ws_bytes, void *stream);
+
+/* SOS cascade sos[S][5], every channel with the same cascade, by a chunked
+ * parallel linear-recurrence scan.
+ *   state_in  : NULL (zero state) or [C][S][2] = (s1, s2) per section
+ *   state_out : NULL or [C][S][2], the state after sample N-1 (resume a
+ *               stream by passing it as the next call's state_in)
+ *   ckpt      : NULL or [C][ceil(N/T)][S][2] with T = tfx_sos_tile_length():
+ *               the state entering each section at the start of every tile,
+ *               used by tfx_sos_backward to recompute section signals.
+ * S == 0 copies x to y. */
+tfx_status tfx_sos(const float *x, float *y, int64_t C, int64_t N, int64_t ldx, int64_t ldy,
+                   const float *sos, int32_t S, const float *state_in, float *state_out,
+                   float *ckpt, void *ws, size_t ws_bytes, void *stream);
+
+/* Chain of stages applied left to right (replaces the paper's pipe
+ * operator).  LTI stages with zero initial state commute, so the library may
+ * regroup them: all FIR stages are merged into one tap vector (FP64 tap
+ * convolution on the device) applied first, and all SOS stages are
+ * concatenated into one cascade fused behind it in the same kernel.  Only
+ * rounding differs from the written order.
+ *   cmp  : arithmetic of the FIR part (TFX_COMPUTE_F32 for the plain chain)
+ *   ckpt : NULL or as for tfx_sos with S = total sections (for the backward). */
+tfx_status tfx_chain(const float *x, float *y, int64_t C, int64_t N, int64_t ldx, int64_t ldy,
+                     const tfx_stage *stages, int32_t nstages, tfx_compute cmp, float *ckpt,
+                     void *ws, size_t ws_bytes, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TFX_H */

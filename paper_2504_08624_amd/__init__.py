@@ -1,0 +1,10 @@
+"""MI355X-native multichannel FIR / IIR-SOS filter chains (TorchFX's hot path).
+
+The filtering runs in hand-written HIP kernels for gfx950 behind the C ABI of
+libtfx.so (include/tfx.h); this package is its Python binding.  Importing it
+loads nothing: the library is loaded on the first call and every call raises
+if it is not built (there is no CPU fallback).
+"""
+from .functional import chain, fir, sos, tile_length  # noqa: F401
+
+__all__ = ["fir", "sos", "chain", "tile_length"]

@@ -1,0 +1,264 @@
+// tfx_api.cpp -- the C ABI of libtfx: argument validation, status codes,
+// workspace sizing and dispatch to the HIP kernels.  Everything here runs on
+// the host; nothing is allocated and nothing synchronises.
+#include <hip/hip_runtime_api.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "../../include/tfx.h"
+#include "tfx_internal.h"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+tfx_status fail(tfx_status s, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return s;
+}
+
+tfx_status ok() {
+    g_last_error.clear();
+    return TFX_OK;
+}
+
+tfx_status hip_fail(hipError_t e, const char *where) {
+    return fail(TFX_E_HIP, "%s: %s", where, hipGetErrorString(e));
+}
+
+bool overlaps(const void *a, size_t abytes, const void *b, size_t bbytes) {
+    const char *pa = static_cast<const char *>(a), *pb = static_cast<const char *>(b);
+    return pa < pb + bbytes && pb < pa + abytes;
+}
+
+size_t span_bytes(int64_t C, int64_t N, int64_t ld) {
+    if (C <= 0 || N <= 0) return 0;
+    return (size_t)((C - 1) * ld + N) * sizeof(float);
+}
+
+tfx_status check_signal(const float *x, float *y, int64_t C, int64_t N, int64_t ldx, int64_t ldy) {
+    if (C < 1) return fail(TFX_E_INVALID_ARG, "C must be >= 1 (got %lld)", (long long)C);
+    if (N < 0 || N >= (int64_t(1) << 40)) return fail(TFX_E_INVALID_ARG, "N out of range (got %lld)", (long long)N);
+    if (ldx < N || ldy < N) return fail(TFX_E_INVALID_ARG, "row strides must be >= N (ldx %lld, ldy %lld, N %lld)",
+                                        (long long)ldx, (long long)ldy, (long long)N);
+    if (N > 0 && (!x || !y)) return fail(TFX_E_INVALID_ARG, "x and y must be non-null");
+    const int64_t ntiles = (N + tfx::T - 1) / tfx::T;
+    if (C * ntiles >= (int64_t(1) << 31)) return fail(TFX_E_UNSUPPORTED, "C * ceil(N/%d) too large", tfx::T);
+    if (N > 0 && overlaps(x, span_bytes(C, N, ldx), y, span_bytes(C, N, ldy)))
+        return fail(TFX_E_ALIAS, "output overlaps the input");
+    return TFX_OK;
+}
+
+tfx_status check_ws(void *ws, size_t ws_bytes, size_t need) {
+    if (need == 0) return TFX_OK;
+    if (!ws) return fail(TFX_E_WORKSPACE, "workspace of %zu bytes required, got NULL", need);
+    if (ws_bytes < need) return fail(TFX_E_WORKSPACE, "workspace too small: %zu < %zu bytes", ws_bytes, need);
+    if (reinterpret_cast<uintptr_t>(ws) % 256) return fail(TFX_E_WORKSPACE, "workspace must be 256-byte aligned");
+    return TFX_OK;
+}
+
+tfx_status check_fir_mode(int32_t M, tfx_compute cmp, tfx_fir_algo algo) {
+    if (M < 1 || M > tfx::MAX_TAPS) return fail(TFX_E_INVALID_ARG, "tap count M must be in [1, %d] (got %d)", tfx::MAX_TAPS, M);
+    if (cmp < TFX_COMPUTE_F32 || cmp > TFX_COMPUTE_BF16X3) return fail(TFX_E_INVALID_ARG, "unknown compute mode %d", (int)cmp);
+    if (algo < TFX_FIR_AUTO || algo > TFX_FIR_FFT) return fail(TFX_E_INVALID_ARG, "unknown FIR algorithm %d", (int)algo);
+    if (cmp != TFX_COMPUTE_F32) return fail(TFX_E_UNSUPPORTED, "compute mode %d not available in this build", (int)cmp);
+    if (algo != TFX_FIR_AUTO && algo != TFX_FIR_DIRECT)
+        return fail(TFX_E_UNSUPPORTED, "FIR algorithm %d not available in this build", (int)algo);
+    return TFX_OK;
+}
+
+struct Gathered {
+    tfx::StageList firs{}, sos{};
+    int32_t S = 0, Mtot = 0;
+};
+
+tfx_status gather(const tfx_stage *stages, int32_t nstages, Gathered &g) {
+    if (nstages < 0 || nstages > tfx::MAX_STAGES)
+        return fail(TFX_E_INVALID_ARG, "nstages must be in [0, %d]", tfx::MAX_STAGES);
+    if (nstages > 0 && !stages) return fail(TFX_E_INVALID_ARG, "stages is NULL");
+    for (int i = 0; i < nstages; ++i) {
+        const tfx_stage &st = stages[i];
+        if (!st.coef) return fail(TFX_E_INVALID_ARG, "stage %d has NULL coefficients", i);
+        if (st.kind == TFX_STAGE_FIR) {
+            if (st.len < 1 || st.len > tfx::MAX_TAPS) return fail(TFX_E_INVALID_ARG, "stage %d: bad tap count %d", i, st.len);
+            g.firs.ptr[g.firs.n] = st.coef;
+            g.firs.len[g.firs.n] = st.len;
+            g.Mtot += (g.firs.n == 0) ? st.len : st.len - 1;
+            g.firs.n++;
+        } else if (st.kind == TFX_STAGE_SOS) {
+            if (st.len < 0) return fail(TFX_E_INVALID_ARG, "stage %d: negative section count", i);
+            if (st.len == 0) continue;
+            g.sos.ptr[g.sos.n] = st.coef;
+            g.sos.len[g.sos.n] = st.len;
+            g.sos.n++;
+            g.S += st.len;
+        } else {
+            return fail(TFX_E_INVALID_ARG, "stage %d: unknown kind %d", i, st.kind);
+        }
+    }
+    if (g.S > tfx::MAX_SECTIONS) return fail(TFX_E_UNSUPPORTED, "more than %d sections in one chain", tfx::MAX_SECTIONS);
+    if (g.Mtot > tfx::MAX_TAPS) return fail(TFX_E_UNSUPPORTED, "merged FIR longer than %d taps", tfx::MAX_TAPS);
+    return TFX_OK;
+}
+
+tfx_status run(const tfx::ChainPlan &p) {
+    const hipError_t e = tfx::launch_chain(p);
+    if (e != hipSuccess) return hip_fail(e, "kernel launch");
+    return ok();
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *tfx_status_string(tfx_status s) {
+    switch (s) {
+        case TFX_OK: return "TFX_OK";
+        case TFX_E_INVALID_ARG: return "TFX_E_INVALID_ARG";
+        case TFX_E_UNSUPPORTED: return "TFX_E_UNSUPPORTED";
+        case TFX_E_WORKSPACE: return "TFX_E_WORKSPACE";
+        case TFX_E_UNSTABLE: return "TFX_E_UNSTABLE";
+        case TFX_E_ALIAS: return "TFX_E_ALIAS";
+        case TFX_E_CAPTURE: return "TFX_E_CAPTURE";
+        case TFX_E_HIP: return "TFX_E_HIP";
+    }
+    return "TFX_E_UNKNOWN";
+}
+
+const char *tfx_last_error(void) { return g_last_error.c_str(); }
+
+int32_t tfx_version(void) { return 100; }
+
+int64_t tfx_sos_tile_length(void) { return tfx::T; }
+
+tfx_status tfx_sos_check_stable(const float *sos_host, int32_t S, int32_t *stable) {
+    if (!stable || S < 0 || (S > 0 && !sos_host)) return fail(TFX_E_INVALID_ARG, "bad arguments");
+    *stable = 1;
+    for (int s = 0; s < S; ++s) {
+        const double a1 = sos_host[5 * s + 3], a2 = sos_host[5 * s + 4];
+        const double disc = a1 * a1 - 4.0 * a2;
+        double r;
+        if (disc < 0.0) {
+            r = std::sqrt(a2);
+        } else {
+            const double sq = std::sqrt(disc);
+            r = std::fmax(std::fabs(0.5 * (-a1 + sq)), std::fabs(0.5 * (-a1 - sq)));
+        }
+        if (!(r < 1.0)) {
+            *stable = 0;
+            return fail(TFX_E_UNSTABLE, "section %d has a pole of radius %.17g", s, r);
+        }
+    }
+    return ok();
+}
+
+tfx_status tfx_fir_workspace_size(int64_t C, int64_t N, int32_t M, tfx_compute cmp, tfx_fir_algo algo,
+                                  size_t *bytes) {
+    if (!bytes) return fail(TFX_E_INVALID_ARG, "bytes is NULL");
+    tfx_status s = check_fir_mode(M, cmp, algo);
+    if (s) return s;
+    if (C < 1 || N < 0) return fail(TFX_E_INVALID_ARG, "bad shape");
+    *bytes = 0;
+    return ok();
+}
+
+tfx_status tfx_sos_workspace_size(int64_t C, int64_t N, int32_t S, size_t *bytes) {
+    if (!bytes) return fail(TFX_E_INVALID_ARG, "bytes is NULL");
+    if (C < 1 || N < 0 || S < 0 || S > tfx::MAX_SECTIONS) return fail(TFX_E_INVALID_ARG, "bad shape");
+    *bytes = tfx::ws_layout(C, N, S, 0, 0).total;
+    return ok();
+}
+
+tfx_status tfx_chain_workspace_size(int64_t C, int64_t N, const tfx_stage *stages, int32_t nstages,
+                                    tfx_compute cmp, size_t *bytes) {
+    if (!bytes) return fail(TFX_E_INVALID_ARG, "bytes is NULL");
+    if (C < 1 || N < 0) return fail(TFX_E_INVALID_ARG, "bad shape");
+    Gathered g;
+    tfx_status s = gather(stages, nstages, g);
+    if (s) return s;
+    if (g.firs.n > 0 && (s = check_fir_mode(g.Mtot, cmp, TFX_FIR_AUTO))) return s;
+    *bytes = tfx::ws_layout(C, N, g.S, g.Mtot, g.firs.n).total;
+    return ok();
+}
+
+tfx_status tfx_fir(const float *x, float *y, int64_t C, int64_t N, int64_t ldx, int64_t ldy, const float *h,
+                   int32_t M, tfx_compute cmp, tfx_fir_algo algo, void *ws, size_t ws_bytes, void *stream) {
+    tfx_status s = check_signal(x, y, C, N, ldx, ldy);
+    if (s) return s;
+    if ((s = check_fir_mode(M, cmp, algo))) return s;
+    if (!h) return fail(TFX_E_INVALID_ARG, "taps h is NULL");
+    tfx::ChainPlan p{};
+    p.x = x; p.y = y; p.C = C; p.N = N; p.ldx = ldx; p.ldy = ldy;
+    p.firs.ptr[0] = h;
+    p.firs.len[0] = M;
+    p.firs.n = 1;
+    p.S = 0;
+    p.ws = ws;
+    p.ws_bytes = ws_bytes;
+    p.stream = static_cast<hipStream_t>(stream);
+    return run(p);
+}
+
+tfx_status tfx_sos(const float *x, float *y, int64_t C, int64_t N, int64_t ldx, int64_t ldy, const float *sos,
+                   int32_t S, const float *state_in, float *state_out, float *ckpt, void *ws, size_t ws_bytes,
+                   void *stream) {
+    tfx_status s = check_signal(x, y, C, N, ldx, ldy);
+    if (s) return s;
+    if (S < 0 || S > tfx::MAX_SECTIONS) return fail(TFX_E_INVALID_ARG, "S must be in [0, %d]", tfx::MAX_SECTIONS);
+    if (S > 0 && !sos) return fail(TFX_E_INVALID_ARG, "sos is NULL");
+    const tfx::WsLayout lay = tfx::ws_layout(C, N, S, 0, 0);
+    if ((s = check_ws(ws, ws_bytes, lay.total))) return s;
+    if (state_out && N > 0) {
+        const size_t sb = (size_t)C * S * 2 * sizeof(float);
+        if (overlaps(state_out, sb, x, span_bytes(C, N, ldx)) || overlaps(state_out, sb, y, span_bytes(C, N, ldy)))
+            return fail(TFX_E_ALIAS, "state_out overlaps a signal");
+    }
+    tfx::ChainPlan p{};
+    p.x = x; p.y = y; p.C = C; p.N = N; p.ldx = ldx; p.ldy = ldy;
+    p.S = S;
+    if (S > 0) {
+        p.sos.ptr[0] = sos;
+        p.sos.len[0] = S;
+        p.sos.n = 1;
+    }
+    p.state_in = state_in;
+    p.state_out = state_out;
+    p.ckpt = ckpt;
+    p.ws = ws;
+    p.ws_bytes = ws_bytes;
+    p.stream = static_cast<hipStream_t>(stream);
+    return run(p);
+}
+
+tfx_status tfx_chain(const float *x, float *y, int64_t C, int64_t N, int64_t ldx, int64_t ldy,
+                     const tfx_stage *stages, int32_t nstages, tfx_compute cmp, float *ckpt, void *ws,
+                     size_t ws_bytes, void *stream) {
+    tfx_status s = check_signal(x, y, C, N, ldx, ldy);
+    if (s) return s;
+    Gathered g;
+    if ((s = gather(stages, nstages, g))) return s;
+    if (g.firs.n > 0 && (s = check_fir_mode(g.Mtot, cmp, TFX_FIR_AUTO))) return s;
+    const tfx::WsLayout lay = tfx::ws_layout(C, N, g.S, g.Mtot, g.firs.n);
+    if ((s = check_ws(ws, ws_bytes, lay.total))) return s;
+    tfx::ChainPlan p{};
+    p.x = x; p.y = y; p.C = C; p.N = N; p.ldx = ldx; p.ldy = ldy;
+    p.firs = g.firs;
+    p.sos = g.sos;
+    p.S = g.S;
+    p.ckpt = ckpt;
+    p.ws = ws;
+    p.ws_bytes = ws_bytes;
+    p.stream = static_cast<hipStream_t>(stream);
+    return run(p);
+}
+
+}  // extern "C"

@@ -1,0 +1,87 @@
+"""C-ABI checks that need no GPU: the library loads, exports every function
+the header declares, and rejects bad arguments on the host before any HIP
+call is made."""
+import ctypes
+
+import pytest
+
+from paper_2504_08624_amd import lib
+
+
+def test_exports_every_declared_function():
+    L = lib.load()
+    names = lib.declared_functions()
+    assert "tfx_chain" in names and "tfx_sos" in names and "tfx_fir" in names
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def test_status_strings_and_version():
+    L = lib.load()
+    for code, name in lib.STATUS_NAMES.items():
+        assert L.tfx_status_string(code).decode() == name
+    assert L.tfx_version() >= 100
+    assert L.tfx_sos_tile_length() == 8192
+
+
+def _st(name, *args):
+    return lib.STATUS_NAMES[getattr(lib.load(), name)(*args)]
+
+
+FAKE = 1 << 40  # never dereferenced: every call below fails validation first
+
+
+def test_sos_argument_validation():
+    assert _st("tfx_sos", FAKE, FAKE + (1 << 30), 0, 10, 10, 10, FAKE, 1, None, None, None, None, 0, None) \
+        == "TFX_E_INVALID_ARG"                                   # C = 0
+    assert _st("tfx_sos", FAKE, FAKE + (1 << 30), 2, 10, 5, 10, FAKE, 1, None, None, None, None, 0, None) \
+        == "TFX_E_INVALID_ARG"                                   # ldx < N
+    assert _st("tfx_sos", FAKE, FAKE + (1 << 30), 2, 10, 10, 10, None, 1, None, None, None, None, 0, None) \
+        == "TFX_E_INVALID_ARG"                                   # sos NULL
+    assert _st("tfx_sos", FAKE, FAKE + 8, 2, 10, 10, 10, FAKE, 1, None, None, None, None, 0, None) \
+        == "TFX_E_ALIAS"
+    assert _st("tfx_sos", FAKE, FAKE + (1 << 30), 2, 10, 10, 10, FAKE, 1, None, None, None, None, 0, None) \
+        == "TFX_E_WORKSPACE"
+    assert _st("tfx_sos", FAKE, FAKE + (1 << 30), 2, 10, 10, 10, FAKE, 1, None, None, None, FAKE + 8,
+               1 << 20, None) == "TFX_E_WORKSPACE"                # misaligned
+    assert b"aligned" in lib.load().tfx_last_error()
+
+
+def test_fir_argument_validation():
+    assert _st("tfx_fir", FAKE, FAKE + (1 << 30), 2, 10, 10, 10, FAKE, 0, 0, 0, None, 0, None) == "TFX_E_INVALID_ARG"
+    assert _st("tfx_fir", FAKE, FAKE + (1 << 30), 2, 10, 10, 10, FAKE, 70000, 0, 0, None, 0, None) \
+        == "TFX_E_INVALID_ARG"
+    assert _st("tfx_fir", FAKE, FAKE + (1 << 30), 2, 10, 10, 10, FAKE, 5, 9, 0, None, 0, None) == "TFX_E_INVALID_ARG"
+
+
+def test_chain_stage_validation():
+    bad = lib.stage_array([(7, 3, FAKE)])
+    assert _st("tfx_chain", FAKE, FAKE + (1 << 30), 1, 10, 10, 10, bad, 1, 0, None, None, 0, None) \
+        == "TFX_E_INVALID_ARG"
+    null = lib.stage_array([(lib.STAGE_SOS, 2, None)])
+    assert _st("tfx_chain", FAKE, FAKE + (1 << 30), 1, 10, 10, 10, null, 1, 0, None, None, 0, None) \
+        == "TFX_E_INVALID_ARG"
+
+
+def test_workspace_sizes():
+    n = ctypes.c_size_t(0)
+    assert _st("tfx_sos_workspace_size", 8, 5_760_000, 6, ctypes.byref(n)) == "TFX_OK"
+    assert n.value > 0 and n.value % 256 == 0
+    z = ctypes.c_size_t(123)
+    assert _st("tfx_sos_workspace_size", 8, 100, 0, ctypes.byref(z)) == "TFX_OK" and z.value == 0
+
+
+def test_host_stability_check():
+    import numpy as np
+    good = np.array([[1, 0, 0, -1.8, 0.9]], np.float32)
+    bad = np.array([[1, 0, 0, -2.0, 1.0]], np.float32)
+    s = ctypes.c_int32(-1)
+    assert _st("tfx_sos_check_stable", good.ctypes.data, 1, ctypes.byref(s)) == "TFX_OK" and s.value == 1
+    assert _st("tfx_sos_check_stable", bad.ctypes.data, 1, ctypes.byref(s)) == "TFX_E_UNSTABLE" and s.value == 0
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    monkeypatch.setattr(lib, "_lib", None)
+    monkeypatch.setattr(lib, "LIB_PATH", str(tmp_path / "nope.so"))
+    with pytest.raises(RuntimeError, match="not built"):
+        lib.load()

@@ -1,0 +1,235 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Every case draws seeded inputs, runs libtfx on cuda:0 and compares element
+by element with the oracle on the same fp32 inputs promoted to float64.
+Tolerances (per-channel relative RMS): FP32 FIR 1e-5, FP32 IIR and chains
+1e-4.
+"""
+import numpy as np
+import pytest
+import torch
+
+import paper_2504_08624_amd as tfx
+from paper_2504_08624_amd import design, lib, signals, workloads
+from oracle import oracle as O
+from tests.metrics import TOL_FIR_F32, TOL_IIR_F32, assert_close
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+T = 8192
+
+
+def _x(C, N, key, sigma=0.1):
+    return signals.to_f32(np.stack([signals.white(N, (*key, c), sigma) for c in range(C)]).reshape(C, N))
+
+
+def _sections(S, key, r_hi=0.99):
+    return design.random_sections(signals.rng(*key), S, 0.5, r_hi).astype(np.float32)
+
+
+def _gpu(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def _cpu(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+# ------------------------------------------------------------------- SOS
+
+@pytest.mark.parametrize("S", [1, 2, 6, 8])
+@pytest.mark.parametrize("N", [1, 31, 32, 33, 8191, 8192, 8193, 3 * T + 17, 70000])
+def test_sos_parity(S, N):
+    C = 3
+    x = _x(C, N, (101, S, N))
+    sec = _sections(S, (102, S))
+    y = _cpu(tfx.sos(_gpu(x), _gpu(sec)))
+    assert_close(y, O.sos(x, sec), TOL_IIR_F32, "sos S=%d N=%d" % (S, N))
+
+
+def test_sos_many_tiles_lookback_windows():
+    # 200 tiles per channel: look-back crosses several 64-tile windows
+    C, N = 2, 200 * T + 5
+    x = _x(C, N, (103,))
+    sec = _sections(4, (104,), r_hi=0.995)
+    y = _cpu(tfx.sos(_gpu(x), _gpu(sec)))
+    assert_close(y, O.sos(x, sec), TOL_IIR_F32, "sos long")
+
+
+def test_sos_zero_sections_is_copy():
+    x = _x(2, 1000, (105,))
+    y = _cpu(tfx.sos(_gpu(x), np.zeros((0, 5), np.float32)))
+    assert np.array_equal(y, x)
+
+
+@pytest.mark.parametrize("N", [1, 100, T, 2 * T + 300])
+def test_sos_state_out_matches_oracle(N):
+    C, S = 2, 3
+    x = _x(C, N, (106, N))
+    sec = _sections(S, (107,))
+    si = (np.random.default_rng(N).standard_normal((C, S, 2)) * 0.1).astype(np.float32)
+    y, so = tfx.sos(_gpu(x), _gpu(sec), state_in=_gpu(si), return_state=True)
+    ref, rs = O.sos(x, sec, state_in=si, return_state=True)
+    assert_close(_cpu(y), ref, TOL_IIR_F32, "with state_in")
+    assert_close(_cpu(so).reshape(C, -1), rs.reshape(C, -1), TOL_IIR_F32, "state_out")
+
+
+def test_sos_split_and_resume():
+    C, S, N = 2, 4, 3 * T + 123
+    x = _x(C, N, (108,))
+    sec = _sections(S, (109,))
+    full = _cpu(tfx.sos(_gpu(x), _gpu(sec)))
+    k = T + 1000
+    y1, st = tfx.sos(_gpu(x[:, :k]), _gpu(sec), return_state=True)
+    y2 = tfx.sos(_gpu(x[:, k:]), _gpu(sec), state_in=st)
+    both = np.concatenate([_cpu(y1), _cpu(y2)], axis=1)
+    assert_close(both, O.sos(x, sec), TOL_IIR_F32, "split")
+    assert_close(both, full, TOL_IIR_F32, "split vs one-shot")
+
+
+def test_sos_checkpoints_are_tile_entering_states():
+    C, S, N = 2, 3, 4 * T + 77
+    x = _x(C, N, (110,))
+    sec = _sections(S, (111,))
+    _, ck = tfx.sos(_gpu(x), _gpu(sec), return_ckpt=True)
+    ck = _cpu(ck)
+    assert ck.shape == (C, 5, S, 2)
+    assert np.all(ck[:, 0] == 0)
+    for t in range(1, 5):
+        # state entering section s at sample t*T = state after t*T samples
+        _, st = O.sos(x[:, :t * T], sec, return_state=True)
+        scale = np.abs(st).max()
+        assert np.abs(ck[:, t] - st).max() <= 1e-4 * scale
+
+
+def test_sos_high_q_fp64_carry():
+    w = workloads.high_q(C=2, N=400_000)
+    sec = w.stages[0][1]
+    assert design.max_pole_radius(sec) > 0.999
+    y = _cpu(tfx.sos(_gpu(w.x), _gpu(sec)))
+    assert_close(y, O.sos(w.x, sec), TOL_IIR_F32, "high-Q")
+
+
+def test_sos_strided_rows():
+    C, N, ld = 3, 20000, 20480
+    big = _x(C, ld, (112,))
+    sec = _sections(2, (113,))
+    xt = _gpu(big)[:, :N]
+    assert xt.stride(0) == ld
+    y = _cpu(tfx.sos(xt, _gpu(sec)))
+    assert_close(y, O.sos(big[:, :N], sec), TOL_IIR_F32, "strided")
+
+
+def test_sos_deterministic():
+    x = _gpu(_x(4, 5 * T + 9, (114,)))
+    sec = _gpu(_sections(6, (115,)))
+    a = _cpu(tfx.sos(x, sec))
+    b = _cpu(tfx.sos(x, sec))
+    assert np.array_equal(a, b)
+
+
+def test_sos_nan_stays_in_its_channel():
+    x = _x(3, 2 * T, (116,))
+    x[1, 5000] = np.nan
+    sec = _sections(2, (117,))
+    y = _cpu(tfx.sos(_gpu(x), _gpu(sec)))
+    assert np.all(np.isfinite(y[0])) and np.all(np.isfinite(y[2]))
+    assert np.all(np.isfinite(y[1, :5000])) and np.isnan(y[1, 5000])
+    assert_close(y[[0, 2]], O.sos(x[[0, 2]], sec), TOL_IIR_F32, "other channels")
+
+
+# ------------------------------------------------------------------- FIR
+
+@pytest.mark.parametrize("M", [1, 2, 15, 16, 17, 101, 255, 1023, 1500])
+@pytest.mark.parametrize("N", [1, 100, T + 1, 3 * T - 5])
+def test_fir_direct_parity(M, N):
+    C = 2
+    x = _x(C, N, (120, M, N))
+    h = (np.random.default_rng(M).standard_normal(M) / np.sqrt(M)).astype(np.float32)
+    y = _cpu(tfx.fir(_gpu(x), _gpu(h), algo="direct"))
+    assert_close(y, O.fir(x, h), TOL_FIR_F32, "fir M=%d N=%d" % (M, N))
+
+
+def test_fir_longer_than_one_lds_pass():
+    C, N, M = 2, 2 * T + 3, 3000
+    x = _x(C, N, (121,))
+    h = (np.random.default_rng(7).standard_normal(M) / np.sqrt(M)).astype(np.float32)
+    y = _cpu(tfx.fir(_gpu(x), _gpu(h)))
+    assert_close(y, O.fir(x, h), TOL_FIR_F32, "fir 3000 taps")
+
+
+def test_fir_impulse_gives_taps():
+    h = np.random.default_rng(1).standard_normal(101).astype(np.float32)
+    x = np.zeros((1, 500), np.float32)
+    x[0, 0] = 1.0
+    y = _cpu(tfx.fir(_gpu(x), _gpu(h)))
+    assert np.array_equal(y[0, :101], h) and np.all(y[0, 101:] == 0)
+
+
+# ----------------------------------------------------------------- chains
+
+def test_chain_short_full_size():
+    w = workloads.chain_short()
+    y = _cpu(tfx.chain(_gpu(w.x), w.stages))
+    assert_close(y, O.chain(w.x, w.stages), TOL_IIR_F32, "chain_short")
+
+
+def test_chain_mid_reduced():
+    w = workloads.chain_mid(C=3, N=150_000)
+    y = _cpu(tfx.chain(_gpu(w.x), w.stages))
+    assert_close(y, O.chain(w.x, w.stages), TOL_IIR_F32, "chain_mid reduced")
+
+
+def test_chain_two_fir_stages_merge():
+    x = _x(2, 3 * T + 11, (122,))
+    h1 = design.fir_lowpass(31, 5000.0, 48000.0).astype(np.float32)
+    h2 = design.fir_lowpass(17, 9000.0, 48000.0).astype(np.float32)
+    sec = _sections(2, (123,))
+    stages = [("fir", h1), ("sos", sec), ("fir", h2)]
+    y = _cpu(tfx.chain(_gpu(x), stages))
+    assert_close(y, O.chain(x, stages), TOL_IIR_F32, "fir|sos|fir")
+
+
+def test_chain_checkpoints_are_section_states():
+    w = workloads.chain_short(C=2, N=3 * T + 5)
+    y, ck = tfx.chain(_gpu(w.x), w.stages, return_ckpt=True)
+    ck = _cpu(ck)
+    fir_out = O.fir(w.x, w.stages[0][1])
+    _, st = O.sos(fir_out[:, :2 * T], w.stages[1][1], return_state=True)
+    assert np.abs(ck[:, 2] - st).max() <= 1e-4 * np.abs(st).max()
+
+
+@pytest.mark.slow
+def test_chain_mid_full_size():
+    w = workloads.chain_mid()
+    y = _cpu(tfx.chain(_gpu(w.x), w.stages))
+    assert_close(y, O.chain(w.x, w.stages), TOL_IIR_F32, "chain_mid full")
+
+
+# ----------------------------------------------------------------- errors
+
+def test_alias_rejected():
+    x = _gpu(_x(2, 1000, (124,)))
+    ws = torch.empty(1 << 20, dtype=torch.uint8, device=DEV)
+    sec = _gpu(_sections(1, (125,)))
+    st = lib.load().tfx_sos(x.data_ptr(), x.data_ptr() + 400, 2, 1000, 1000, 1000, sec.data_ptr(), 1,
+                            None, None, None, ws.data_ptr(), ws.numel(), None)
+    assert lib.STATUS_NAMES[st] == "TFX_E_ALIAS"
+
+
+def test_workspace_too_small_rejected():
+    x = _gpu(_x(2, 1000, (126,)))
+    y = torch.empty_like(x)
+    ws = torch.empty(256, dtype=torch.uint8, device=DEV)
+    sec = _gpu(_sections(1, (127,)))
+    st = lib.load().tfx_sos(x.data_ptr(), y.data_ptr(), 2, 1000, 1000, 1000, sec.data_ptr(), 1,
+                            None, None, None, ws.data_ptr(), ws.numel(), None)
+    assert lib.STATUS_NAMES[st] == "TFX_E_WORKSPACE"
+    assert b"too small" in lib.load().tfx_last_error()
+
+
+def test_cpu_tensor_rejected():
+    with pytest.raises(TypeError):
+        tfx.sos(torch.zeros(2, 10), np.zeros((1, 5), np.float32))

@@ -1,0 +1,158 @@
+"""FP64 model of the chunked-scan decomposition the IIR kernel uses, checked
+against the oracle on the CPU.
+
+This is not the oracle and shares no code with it or with the HIP path: it
+restates the decomposition (per-chunk zero-state response, inclusive scan of
+chunk states with powers of the 2x2 chunk transition, wave and tile
+aggregates, look-back reduction over up to 64 predecessors with powers of the
+tile transition, fold into the chunk-entering state, zero-input correction)
+so that the algebra is verified before any kernel runs.  Sizes are scaled
+down (lanes, waves, chunk length) so the python loops stay fast; the algebra
+does not depend on them.
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+
+
+def _tables(coef, L, lanes, waves):
+    b0, b1, b2, a1, a2 = coef
+    A = np.array([[-a1, 1.0], [-a2, 0.0]])
+    g = np.zeros((L, 2))
+    P = np.eye(2)
+    for t in range(L):
+        g[t] = P[0]
+        P = P @ A
+    Phi = P                                       # A^L
+    fold = [np.linalg.matrix_power(Phi, k) for k in range(lanes)]
+    Psi = np.linalg.matrix_power(Phi, lanes)
+    psi = [np.linalg.matrix_power(Psi, w) for w in range(waves)]
+    PhiT = np.linalg.matrix_power(Psi, waves)
+    lb = [np.linalg.matrix_power(PhiT, 2 ** j) for j in range(7)]
+    apow = [np.linalg.matrix_power(A, t + 1) for t in range(L)]
+    return dict(g=g, fold=fold, psi=psi, lb=lb, apow=apow)
+
+
+def _zsr(coef, x):
+    b0, b1, b2, a1, a2 = coef
+    s1 = s2 = 0.0
+    y = np.empty_like(x)
+    states = np.empty((x.size, 2))
+    for n, xv in enumerate(x):
+        yv = b0 * xv + s1
+        s1 = b1 * xv - a1 * yv + s2
+        s2 = b2 * xv - a2 * yv
+        y[n] = yv
+        states[n] = (s1, s2)
+    return y, states
+
+
+def model_channel(x, sos, L, lanes, waves, rng, state_in=None):
+    """Runs the decomposition over one channel; returns (y, final state)."""
+    T = L * lanes * waves
+    N = x.size
+    nt = -(-N // T)
+    xp = np.concatenate([x, np.zeros(nt * T - N)])
+    v = xp.copy()
+    S = len(sos)
+    final = np.zeros((S, 2))
+    for s, coef in enumerate(sos):
+        tb = _tables(coef, L, lanes, waves)
+        agg = np.zeros((nt, 2))
+        inc = np.zeros((nt, 2))
+        for t in range(nt):
+            seg = v[t * T:(t + 1) * T].reshape(waves, lanes, L)
+            y0 = np.empty_like(seg)
+            z = np.empty((waves, lanes, 2))
+            cap = np.empty((waves, lanes, L, 2))
+            for w in range(waves):
+                for ln in range(lanes):
+                    y0[w, ln], st = _zsr(coef, seg[w, ln])
+                    z[w, ln] = st[-1]
+                    cap[w, ln] = st
+            # Kogge-Stone inclusive scan inside each wave
+            wsc = z.copy()
+            d = 1
+            while d < lanes:
+                prev = wsc.copy()
+                for ln in range(d, lanes):
+                    wsc[:, ln] = prev[:, ln] + prev[:, ln - d] @ tb["fold"][d].T
+                d *= 2
+            E = np.zeros(2)
+            Ew = []
+            for w in range(waves):
+                Ew.append(E.copy())
+                E = tb["psi"][1] @ E + wsc[w, -1] if waves > 1 else tb["lb"][0] @ E + wsc[w, -1]
+            # with one wave psi[1] does not exist; the tile transition is lb[0]
+            agg[t] = E
+            if t == 0:
+                P = np.zeros(2) if state_in is None else state_in[s]
+            else:
+                # look-back: predecessors randomly published only their
+                # aggregate; walk back in windows of 64
+                P = np.zeros(2)
+                M = np.eye(2)
+                base = t - 1
+                published_inc = rng.random(t) < 0.3
+                published_inc[0] = True
+                while True:
+                    vals = []
+                    stop = False
+                    for i in range(64):
+                        q = base - i
+                        if q < 0:
+                            break
+                        if published_inc[q]:
+                            vals.append(inc[q])
+                            stop = True
+                            break
+                        vals.append(agg[q])
+                    vals += [np.zeros(2)] * (64 - len(vals))
+                    vv = [np.array(a) for a in vals]
+                    for j in range(6):
+                        dd = 2 ** j
+                        vv = [vv[i] + (tb["lb"][j] @ vv[i + dd] if i + dd < 64 else 0) for i in range(64)]
+                    P = P + M @ vv[0]
+                    if stop:
+                        break
+                    M = M @ tb["lb"][6]
+                    base -= 64
+            inc[t] = tb["lb"][0] @ P + agg[t]
+            out = np.empty_like(seg)
+            for w in range(waves):
+                e = Ew[w] + tb["psi"][w] @ P
+                for ln in range(lanes):
+                    pv = wsc[w, ln - 1] if ln > 0 else np.zeros(2)
+                    si = pv + tb["fold"][ln] @ e
+                    out[w, ln] = y0[w, ln] + tb["g"] @ si
+                    pos = t * T + (w * lanes + ln) * L
+                    if pos <= N - 1 < pos + L:
+                        r = N - 1 - pos
+                        final[s] = tb["apow"][r] @ si + cap[w, ln, r]
+            v[t * T:(t + 1) * T] = out.reshape(-1)
+    return v[:N], final
+
+
+@pytest.mark.parametrize("N", [1, 7, 95, 96, 97, 500, 2000])
+def test_chunked_scan_model_matches_oracle(N):
+    rng = np.random.default_rng(N)
+    sos = np.array([[0.2, 0.4, 0.2, -1.2, 0.5], [1.0, -1.9, 1.0, -1.97, 0.99],
+                    [0.5, 0.1, -0.3, 0.3, 0.2]])
+    x = rng.standard_normal(N)
+    si = rng.standard_normal((3, 2))
+    y, fin = model_channel(x, sos, L=4, lanes=8, waves=3, rng=rng, state_in=si)
+    ref, st = O.sos(x[None], sos, state_in=si[None], return_state=True)
+    assert np.max(np.abs(y - ref[0])) < 1e-10 * max(1.0, np.max(np.abs(ref)))
+    assert np.max(np.abs(fin - st[0])) < 1e-10 * max(1.0, np.max(np.abs(st)))
+
+
+def test_chunked_scan_model_long_lookback():
+    # many tiles so that the look-back crosses more than one 64-tile window
+    rng = np.random.default_rng(3)
+    sos = np.array([[1.0, 0.0, 0.0, -1.8, 0.9]])
+    N = 8 * 150 + 3
+    x = rng.standard_normal(N)
+    y, _ = model_channel(x, sos, L=2, lanes=2, waves=2, rng=rng)
+    ref = O.sos(x[None], sos)[0]
+    assert np.max(np.abs(y - ref)) < 1e-9 * np.max(np.abs(ref))
