@@ -152,6 +152,21 @@ tfx_status tfx_chain(const float *x, float *y, int64_t C, int64_t N, int64_t ldx
                      const tfx_stage *stages, int32_t nstages, tfx_compute cmp, float *ckpt,
                      void *ws, size_t ws_bytes, void *stream);
 
+/* Two-phase form of tfx_chain for filters whose coefficients stay fixed over
+ * many calls (serving loops, captured graphs).  tfx_chain_prepare builds the
+ * per-section device tables (and the merged taps) into ws and initialises
+ * it; tfx_chain_run then filters with them, any number of times.  Both take
+ * the same C, N, stages and cmp; the stage coefficients must not change in
+ * between (call prepare again if they do).  tfx_chain_run launches one kernel,
+ * writes no memset and re-arms the workspace for the next run itself, so it
+ * may be captured into a hipGraph and replayed; runs sharing one ws must not
+ * overlap in time.  tfx_chain == prepare + run on the same stream. */
+tfx_status tfx_chain_prepare(int64_t C, int64_t N, const tfx_stage *stages, int32_t nstages,
+                             tfx_compute cmp, void *ws, size_t ws_bytes, void *stream);
+tfx_status tfx_chain_run(const float *x, float *y, int64_t C, int64_t N, int64_t ldx, int64_t ldy,
+                         const tfx_stage *stages, int32_t nstages, tfx_compute cmp, float *ckpt,
+                         void *ws, size_t ws_bytes, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

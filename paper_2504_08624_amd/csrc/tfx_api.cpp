@@ -110,10 +110,42 @@ tfx_status gather(const tfx_stage *stages, int32_t nstages, Gathered &g) {
     return TFX_OK;
 }
 
-tfx_status run(const tfx::ChainPlan &p) {
-    const hipError_t e = tfx::launch_chain(p);
-    if (e != hipSuccess) return hip_fail(e, "kernel launch");
+tfx_status prepare(const tfx::ChainPlan &p) {
+    const hipError_t e = tfx::launch_prepare(p);
+    if (e != hipSuccess) return hip_fail(e, "table kernel launch");
     return ok();
+}
+
+tfx_status execute(const tfx::ChainPlan &p) {
+    const hipError_t e = tfx::launch_run(p);
+    if (e != hipSuccess) return hip_fail(e, "filter kernel launch");
+    return ok();
+}
+
+tfx_status run(const tfx::ChainPlan &p) {
+    tfx_status s = prepare(p);
+    if (s) return s;
+    return execute(p);
+}
+
+// Shared validation of the chain entry points; fills the plan's stage part.
+tfx_status chain_plan(int64_t C, int64_t N, const tfx_stage *stages, int32_t nstages, tfx_compute cmp,
+                      void *ws, size_t ws_bytes, void *stream, tfx::ChainPlan &p) {
+    Gathered g;
+    tfx_status s = gather(stages, nstages, g);
+    if (s) return s;
+    if (g.firs.n > 0 && (s = check_fir_mode(g.Mtot, cmp, TFX_FIR_AUTO))) return s;
+    const tfx::WsLayout lay = tfx::ws_layout(C, N, g.S, g.Mtot, g.firs.n);
+    if ((s = check_ws(ws, ws_bytes, lay.total))) return s;
+    p.C = C;
+    p.N = N;
+    p.firs = g.firs;
+    p.sos = g.sos;
+    p.S = g.S;
+    p.ws = ws;
+    p.ws_bytes = ws_bytes;
+    p.stream = static_cast<hipStream_t>(stream);
+    return TFX_OK;
 }
 
 }  // namespace
@@ -244,21 +276,32 @@ tfx_status tfx_chain(const float *x, float *y, int64_t C, int64_t N, int64_t ldx
                      size_t ws_bytes, void *stream) {
     tfx_status s = check_signal(x, y, C, N, ldx, ldy);
     if (s) return s;
-    Gathered g;
-    if ((s = gather(stages, nstages, g))) return s;
-    if (g.firs.n > 0 && (s = check_fir_mode(g.Mtot, cmp, TFX_FIR_AUTO))) return s;
-    const tfx::WsLayout lay = tfx::ws_layout(C, N, g.S, g.Mtot, g.firs.n);
-    if ((s = check_ws(ws, ws_bytes, lay.total))) return s;
     tfx::ChainPlan p{};
-    p.x = x; p.y = y; p.C = C; p.N = N; p.ldx = ldx; p.ldy = ldy;
-    p.firs = g.firs;
-    p.sos = g.sos;
-    p.S = g.S;
+    if ((s = chain_plan(C, N, stages, nstages, cmp, ws, ws_bytes, stream, p))) return s;
+    p.x = x; p.y = y; p.ldx = ldx; p.ldy = ldy;
     p.ckpt = ckpt;
-    p.ws = ws;
-    p.ws_bytes = ws_bytes;
-    p.stream = static_cast<hipStream_t>(stream);
     return run(p);
+}
+
+tfx_status tfx_chain_prepare(int64_t C, int64_t N, const tfx_stage *stages, int32_t nstages, tfx_compute cmp,
+                             void *ws, size_t ws_bytes, void *stream) {
+    if (C < 1 || N < 0) return fail(TFX_E_INVALID_ARG, "bad shape");
+    tfx::ChainPlan p{};
+    tfx_status s = chain_plan(C, N, stages, nstages, cmp, ws, ws_bytes, stream, p);
+    if (s) return s;
+    return prepare(p);
+}
+
+tfx_status tfx_chain_run(const float *x, float *y, int64_t C, int64_t N, int64_t ldx, int64_t ldy,
+                         const tfx_stage *stages, int32_t nstages, tfx_compute cmp, float *ckpt, void *ws,
+                         size_t ws_bytes, void *stream) {
+    tfx_status s = check_signal(x, y, C, N, ldx, ldy);
+    if (s) return s;
+    tfx::ChainPlan p{};
+    if ((s = chain_plan(C, N, stages, nstages, cmp, ws, ws_bytes, stream, p))) return s;
+    p.x = x; p.y = y; p.ldx = ldx; p.ldy = ldy;
+    p.ckpt = ckpt;
+    return execute(p);
 }
 
 }  // extern "C"

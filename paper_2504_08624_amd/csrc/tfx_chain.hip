@@ -35,8 +35,14 @@
 
 namespace tfx {
 
+// Look-back flag word: (epoch << 2) | status.  The epoch advances once per
+// launch (the last workgroup to finish bumps it), so a run never has to clear
+// the flags left by the previous one and repeated runs need no memset.
 enum : uint32_t { FLAG_NONE = 0, FLAG_AGG = 1, FLAG_INC = 2 };
+constexpr uint32_t EPOCH_MASK = 0x3FFFFFFFu;
 constexpr int64_t SPIN_MAX = int64_t(1) << 24;
+// Workspace header words.
+enum { HDR_TILE = 0, HDR_ERROR = 1, HDR_EPOCH = 2, HDR_DONE = 3 };
 
 // LDS index with 4 floats of padding every 32: a lane's 32-sample chunk then
 // starts 144 bytes after its neighbour's, so 16-byte reads are conflict-free.
@@ -121,15 +127,17 @@ struct PrepArgs {
     uint32_t *hdr;
 };
 
-// Builds every section's tables, clears the look-back flags and the tile
-// counter.  Runs on the call's stream right before the chain kernel.
+// Builds every section's tables and initialises the look-back flags and the
+// workspace header.  Needed once per (workspace, coefficients).
 __global__ void prep_kernel(PrepArgs a) {
     const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = gid; i < a.nflags; i += stride) a.flags[i] = 0u;
     if (gid == 0) {
-        a.hdr[0] = 0u;
-        a.hdr[1] = 0u;
+        a.hdr[HDR_TILE] = 0u;
+        a.hdr[HDR_ERROR] = 0u;
+        a.hdr[HDR_EPOCH] = 1u;
+        a.hdr[HDR_DONE] = 0u;
     }
     if (gid < a.S) {
         int s = (int)gid, st = 0;
@@ -211,13 +219,13 @@ template <> struct Tab<double> {
 // tile aggregate, then returns the state entering the tile.
 template <typename CT>
 __device__ void lookback(const KArgs &a, const SecTab &tb, int64_t ch, int64_t tile, int s,
-                         int lane, CT agg0, CT agg1, CT &P0, CT &P1) {
+                         int lane, uint32_t epoch, CT agg0, CT agg1, CT &P0, CT &P1) {
     const int64_t S = a.S;
     const int64_t rself = (ch * a.ntiles + tile) * S + s;
     if (lane == 0) {
         a.recs[rself * 4 + 0] = (double)agg0;
         a.recs[rself * 4 + 1] = (double)agg1;
-        store_release(&a.flags[rself], FLAG_AGG);
+        store_release(&a.flags[rself], (epoch << 2) | FLAG_AGG);
     }
     CT acc0 = 0, acc1 = 0;
     CT M0 = 1, M1 = 0, M2 = 0, M3 = 1;  // PhiT^(64 * windows consumed)
@@ -228,9 +236,14 @@ __device__ void lookback(const KArgs &a, const SecTab &tb, int64_t ch, int64_t t
         if (q >= 0) {
             const int64_t r = (ch * a.ntiles + q) * S + s;
             int64_t spins = 0;
-            while ((f = load_acquire(&a.flags[r])) == FLAG_NONE) {
+            while (true) {
+                const uint32_t w = load_acquire(&a.flags[r]);
+                if ((w >> 2) == epoch && (w & 3u) != FLAG_NONE) {
+                    f = w & 3u;
+                    break;
+                }
                 if (++spins > SPIN_MAX) {  // never expected: report and finish
-                    atomicOr(&a.hdr[1], 1u);
+                    atomicOr(&a.hdr[HDR_ERROR], 1u);
                     f = FLAG_INC;
                     break;
                 }
@@ -275,6 +288,7 @@ __device__ void lookback(const KArgs &a, const SecTab &tb, int64_t ch, int64_t t
 
 struct TileCtx {
     int64_t tile, ch;
+    uint32_t epoch;
     int tid, lane, wave;
     bool is_last;
     int r_last, owner;
@@ -354,14 +368,14 @@ __device__ void run_section(const KArgs &a, const SecTab &tb, int s, float (&v)[
                 P1 = (CT)a.state_in[(c.ch * a.S + s) * 2 + 1];
             }
         } else {
-            lookback<CT>(a, tb, c.ch, c.tile, s, c.lane, E0, E1, P0, P1);
+            lookback<CT>(a, tb, c.ch, c.tile, s, c.lane, c.epoch, E0, E1, P0, P1);
         }
         if (c.lane == 0) {
             const CT *PT = Tab<CT>::lb(tb, 0);
             const int64_t r = (c.ch * a.ntiles + c.tile) * a.S + s;
             a.recs[r * 4 + 2] = (double)(PT[0] * P0 + PT[1] * P1 + E0);
             a.recs[r * 4 + 3] = (double)(PT[2] * P0 + PT[3] * P1 + E1);
-            store_release(&a.flags[r], FLAG_INC);
+            store_release(&a.flags[r], (c.epoch << 2) | FLAG_INC);
             s_pre[0] = (double)P0;
             s_pre[1] = (double)P1;
             if (a.ckpt) {
@@ -405,17 +419,22 @@ __global__ __launch_bounds__(WG) void chain_kernel(KArgs a) {
     __shared__ __align__(16) float xs[xs_len<HAS_FIR>()];
     __shared__ double s_agg[WAVES][2];
     __shared__ double s_pre[2];
-    __shared__ uint32_t s_id;
+    __shared__ uint32_t s_id, s_epoch;
 
     TileCtx c;
     c.tid = threadIdx.x;
     c.lane = c.tid & 63;
     c.wave = c.tid >> 6;
     uint64_t id;
+    c.epoch = 0;
     if (HAS_SOS) {
-        if (c.tid == 0) s_id = atomicAdd(&a.hdr[0], 1u);
+        if (c.tid == 0) {
+            s_id = atomicAdd(&a.hdr[HDR_TILE], 1u);
+            s_epoch = __hip_atomic_load(&a.hdr[HDR_EPOCH], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
         __syncthreads();
         id = s_id;
+        c.epoch = s_epoch;
     } else {
         id = blockIdx.x;
     }
@@ -502,6 +521,18 @@ __global__ __launch_bounds__(WG) void chain_kernel(KArgs a) {
         const int64_t n = n0 + i;
         if (n < a.N) yc[n] = xs[phys(i)];
     }
+    if (HAS_SOS && c.tid == 0) {
+        // every workgroup has taken its tile id and read the epoch once all
+        // have arrived here: the last one re-arms the header for the next run
+        const uint32_t done = atomicAdd(&a.hdr[HDR_DONE], 1u);
+        if (done == gridDim.x - 1) {
+            uint32_t ne = (c.epoch + 1u) & EPOCH_MASK;
+            if (ne == 0u) ne = 1u;
+            __hip_atomic_store(&a.hdr[HDR_TILE], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&a.hdr[HDR_DONE], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&a.hdr[HDR_EPOCH], ne, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
 }
 
 // ------------------------------------------------------------------- host
@@ -538,12 +569,48 @@ static hipError_t launch_main(const KArgs &k, int64_t nblocks, hipStream_t st) {
     return hipGetLastError();
 }
 
-hipError_t launch_chain(const ChainPlan &p) {
+static int32_t merged_taps(const StageList &f) {
     int32_t Mtot = 0;
-    for (int i = 0; i < p.firs.n; ++i) Mtot += (i == 0) ? p.firs.len[i] : p.firs.len[i] - 1;
+    for (int i = 0; i < f.n; ++i) Mtot += (i == 0) ? f.len[i] : f.len[i] - 1;
+    return Mtot;
+}
+
+hipError_t launch_prepare(const ChainPlan &p) {
+    const int32_t Mtot = merged_taps(p.firs);
     const WsLayout lay = ws_layout(p.C, p.N, p.S, Mtot, p.firs.n);
     char *ws = static_cast<char *>(p.ws);
     hipError_t e;
+    if (p.firs.n > 1) {
+        MergeArgs m;
+        m.firs = p.firs;
+        m.buf0 = reinterpret_cast<double *>(ws + lay.merge);
+        m.buf1 = m.buf0 + Mtot;
+        m.out = reinterpret_cast<float *>(ws + lay.taps);
+        hipLaunchKernelGGL(merge_taps_kernel, dim3(1), dim3(256), 0, p.stream, m);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    if (p.S > 0) {
+        PrepArgs pa;
+        pa.tab = reinterpret_cast<SecTab *>(ws + lay.tab);
+        pa.S = p.S;
+        pa.sos = p.sos;
+        pa.flags = reinterpret_cast<uint32_t *>(ws + lay.flags);
+        pa.nflags = p.C * lay.ntiles * p.S;
+        pa.hdr = reinterpret_cast<uint32_t *>(ws + lay.hdr);
+        const int64_t work = pa.nflags > p.S ? pa.nflags : p.S;
+        int64_t nb = (work + 255) / 256;
+        if (nb > 1024) nb = 1024;
+        if (nb < 1) nb = 1;
+        hipLaunchKernelGGL(prep_kernel, dim3((unsigned)nb), dim3(256), 0, p.stream, pa);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t launch_run(const ChainPlan &p) {
+    const int32_t Mtot = merged_taps(p.firs);
+    const WsLayout lay = ws_layout(p.C, p.N, p.S, Mtot, p.firs.n);
+    char *ws = static_cast<char *>(p.ws);
     if (p.N == 0) {
         if (p.state_out && p.S > 0) {
             const int64_t n = p.C * p.S * 2;
@@ -553,22 +620,6 @@ hipError_t launch_chain(const ChainPlan &p) {
         }
         return hipSuccess;
     }
-    const float *h = nullptr;
-    int32_t M = 0;
-    if (p.firs.n == 1) {
-        h = p.firs.ptr[0];
-        M = p.firs.len[0];
-    } else if (p.firs.n > 1) {
-        MergeArgs m;
-        m.firs = p.firs;
-        m.buf0 = reinterpret_cast<double *>(ws + lay.merge);
-        m.buf1 = m.buf0 + Mtot;
-        m.out = reinterpret_cast<float *>(ws + lay.taps);
-        hipLaunchKernelGGL(merge_taps_kernel, dim3(1), dim3(256), 0, p.stream, m);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-        h = m.out;
-        M = Mtot;
-    }
     KArgs k{};
     k.x = p.x;
     k.y = p.y;
@@ -576,11 +627,11 @@ hipError_t launch_chain(const ChainPlan &p) {
     k.N = p.N;
     k.ldx = p.ldx;
     k.ldy = p.ldy;
-    k.h = h;
-    k.M = M;
+    k.M = Mtot;
+    k.h = p.firs.n == 1 ? p.firs.ptr[0] : (p.firs.n > 1 ? reinterpret_cast<const float *>(ws + lay.taps) : nullptr);
     k.KBL = 0;
-    if (M > 0) {
-        const int32_t m16 = (M + KB - 1) / KB * KB;
+    if (Mtot > 0) {
+        const int32_t m16 = (Mtot + KB - 1) / KB * KB;
         k.KBL = m16 < KBLK_MAX ? m16 : KBLK_MAX;
     }
     k.S = p.S;
@@ -592,23 +643,8 @@ hipError_t launch_chain(const ChainPlan &p) {
     k.tab = reinterpret_cast<const SecTab *>(ws + lay.tab);
     k.flags = reinterpret_cast<uint32_t *>(ws + lay.flags);
     k.recs = reinterpret_cast<double *>(ws + lay.recs);
-    if (p.S > 0) {
-        PrepArgs pa;
-        pa.tab = reinterpret_cast<SecTab *>(ws + lay.tab);
-        pa.S = p.S;
-        pa.sos = p.sos;
-        pa.flags = k.flags;
-        pa.nflags = p.C * lay.ntiles * p.S;
-        pa.hdr = k.hdr;
-        int64_t work = pa.nflags > p.S ? pa.nflags : p.S;
-        int64_t nb = (work + 255) / 256;
-        if (nb > 1024) nb = 1024;
-        if (nb < 1) nb = 1;
-        hipLaunchKernelGGL(prep_kernel, dim3((unsigned)nb), dim3(256), 0, p.stream, pa);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-    }
     const int64_t nblocks = p.C * lay.ntiles;
-    const bool f = M > 0, s = p.S > 0;
+    const bool f = Mtot > 0, s = p.S > 0;
     if (f && s) return launch_main<true, true>(k, nblocks, p.stream);
     if (f) return launch_main<true, false>(k, nblocks, p.stream);
     if (s) return launch_main<false, true>(k, nblocks, p.stream);

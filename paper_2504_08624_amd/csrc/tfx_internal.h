@@ -73,7 +73,9 @@ struct WsLayout {
 };
 WsLayout ws_layout(int64_t C, int64_t N, int32_t S, int32_t M_merged, int32_t n_fir);
 
-// Enqueue the whole chain.  Returns hipSuccess or the launch error.
-hipError_t launch_chain(const ChainPlan &p);
+// Tables + workspace initialisation (once per workspace and coefficients).
+hipError_t launch_prepare(const ChainPlan &p);
+// The filtering itself; may be repeated on a prepared workspace.
+hipError_t launch_run(const ChainPlan &p);
 
 }  // namespace tfx
