@@ -161,10 +161,10 @@ def main():
                                "FIR 1023-tap band-pass | Chebyshev-I 8th order (4 SOS) | 2 peaking EQ",
                    "channels": C, "samples": N, "fir_taps": int(w.stages[0][1].size),
                    "sections": int(sum(s[1].shape[0] for s in w.stages if s[0] == "sos")),
-                   "fir_algo": "direct", "step": "tfx_chain_prepare + tfx_chain_run"},
+                   "fir_algo": "fft" if 48 < w.stages[0][1].size <= 1025 else "direct", "step": "tfx_chain_prepare + tfx_chain_run"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": "chain_kernel<true,true>", "kernel_us": round(kern_s * 1e6, 2),
+                     "kernel": "chain_kernel<FIR_FFT, true>", "kernel_us": round(kern_s * 1e6, 2),
                      "alg_bytes_per_launch": alg_bytes},
         "cpu_baseline": cpu,
         "max_rel_err_vs_oracle": err,

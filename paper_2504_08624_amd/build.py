@@ -24,7 +24,7 @@ ARCH = "gfx950"
 HIP_FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
              "-Wno-unused-command-line-argument"]
-CXX_FLAGS = ["-O2", "-std=c++17", "-fPIC"]
+CXX_FLAGS = ["-x", "c++", "-O2", "-std=c++17", "-fPIC", "-I", "/opt/rocm/include"]
 
 
 def sources():

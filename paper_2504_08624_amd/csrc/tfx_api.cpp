@@ -9,7 +9,7 @@
 #include <cstring>
 #include <string>
 
-#include "../../include/tfx.h"
+#include "tfx.h"
 #include "tfx_internal.h"
 
 namespace {
@@ -66,13 +66,18 @@ tfx_status check_ws(void *ws, size_t ws_bytes, size_t need) {
     return TFX_OK;
 }
 
-tfx_status check_fir_mode(int32_t M, tfx_compute cmp, tfx_fir_algo algo) {
+// Validates the FIR request and picks the kernel path (*mode).
+tfx_status check_fir_mode(int32_t M, tfx_compute cmp, tfx_fir_algo algo, int32_t *mode) {
     if (M < 1 || M > tfx::MAX_TAPS) return fail(TFX_E_INVALID_ARG, "tap count M must be in [1, %d] (got %d)", tfx::MAX_TAPS, M);
     if (cmp < TFX_COMPUTE_F32 || cmp > TFX_COMPUTE_BF16X3) return fail(TFX_E_INVALID_ARG, "unknown compute mode %d", (int)cmp);
     if (algo < TFX_FIR_AUTO || algo > TFX_FIR_FFT) return fail(TFX_E_INVALID_ARG, "unknown FIR algorithm %d", (int)algo);
     if (cmp != TFX_COMPUTE_F32) return fail(TFX_E_UNSUPPORTED, "compute mode %d not available in this build", (int)cmp);
-    if (algo != TFX_FIR_AUTO && algo != TFX_FIR_DIRECT)
-        return fail(TFX_E_UNSUPPORTED, "FIR algorithm %d not available in this build", (int)algo);
+    if (algo == TFX_FIR_TOEPLITZ) return fail(TFX_E_UNSUPPORTED, "the Toeplitz path needs a bf16/fp16 compute mode");
+    if (algo == TFX_FIR_FFT && M > tfx::FFT_MAX_TAPS)
+        return fail(TFX_E_UNSUPPORTED, "overlap-save FFT handles at most %d taps (got %d)", tfx::FFT_MAX_TAPS, M);
+    if (algo == TFX_FIR_DIRECT) *mode = tfx::FIR_DIRECT;
+    else if (algo == TFX_FIR_FFT) *mode = tfx::FIR_FFT;
+    else *mode = (M > 48 && M <= tfx::FFT_MAX_TAPS) ? tfx::FIR_FFT : tfx::FIR_DIRECT;
     return TFX_OK;
 }
 
@@ -134,9 +139,11 @@ tfx_status chain_plan(int64_t C, int64_t N, const tfx_stage *stages, int32_t nst
     Gathered g;
     tfx_status s = gather(stages, nstages, g);
     if (s) return s;
-    if (g.firs.n > 0 && (s = check_fir_mode(g.Mtot, cmp, TFX_FIR_AUTO))) return s;
-    const tfx::WsLayout lay = tfx::ws_layout(C, N, g.S, g.Mtot, g.firs.n);
+    int32_t mode = tfx::FIR_NONE;
+    if (g.firs.n > 0 && (s = check_fir_mode(g.Mtot, cmp, TFX_FIR_AUTO, &mode))) return s;
+    const tfx::WsLayout lay = tfx::ws_layout(C, N, g.S, g.Mtot, g.firs.n, mode);
     if ((s = check_ws(ws, ws_bytes, lay.total))) return s;
+    p.fir_mode = mode;
     p.C = C;
     p.N = N;
     p.firs = g.firs;
@@ -196,17 +203,18 @@ tfx_status tfx_sos_check_stable(const float *sos_host, int32_t S, int32_t *stabl
 tfx_status tfx_fir_workspace_size(int64_t C, int64_t N, int32_t M, tfx_compute cmp, tfx_fir_algo algo,
                                   size_t *bytes) {
     if (!bytes) return fail(TFX_E_INVALID_ARG, "bytes is NULL");
-    tfx_status s = check_fir_mode(M, cmp, algo);
+    int32_t mode = 0;
+    tfx_status s = check_fir_mode(M, cmp, algo, &mode);
     if (s) return s;
     if (C < 1 || N < 0) return fail(TFX_E_INVALID_ARG, "bad shape");
-    *bytes = 0;
+    *bytes = tfx::ws_layout(C, N, 0, M, 1, mode).total;
     return ok();
 }
 
 tfx_status tfx_sos_workspace_size(int64_t C, int64_t N, int32_t S, size_t *bytes) {
     if (!bytes) return fail(TFX_E_INVALID_ARG, "bytes is NULL");
     if (C < 1 || N < 0 || S < 0 || S > tfx::MAX_SECTIONS) return fail(TFX_E_INVALID_ARG, "bad shape");
-    *bytes = tfx::ws_layout(C, N, S, 0, 0).total;
+    *bytes = tfx::ws_layout(C, N, S, 0, 0, tfx::FIR_NONE).total;
     return ok();
 }
 
@@ -217,8 +225,9 @@ tfx_status tfx_chain_workspace_size(int64_t C, int64_t N, const tfx_stage *stage
     Gathered g;
     tfx_status s = gather(stages, nstages, g);
     if (s) return s;
-    if (g.firs.n > 0 && (s = check_fir_mode(g.Mtot, cmp, TFX_FIR_AUTO))) return s;
-    *bytes = tfx::ws_layout(C, N, g.S, g.Mtot, g.firs.n).total;
+    int32_t mode = tfx::FIR_NONE;
+    if (g.firs.n > 0 && (s = check_fir_mode(g.Mtot, cmp, TFX_FIR_AUTO, &mode))) return s;
+    *bytes = tfx::ws_layout(C, N, g.S, g.Mtot, g.firs.n, mode).total;
     return ok();
 }
 
@@ -226,9 +235,12 @@ tfx_status tfx_fir(const float *x, float *y, int64_t C, int64_t N, int64_t ldx, 
                    int32_t M, tfx_compute cmp, tfx_fir_algo algo, void *ws, size_t ws_bytes, void *stream) {
     tfx_status s = check_signal(x, y, C, N, ldx, ldy);
     if (s) return s;
-    if ((s = check_fir_mode(M, cmp, algo))) return s;
+    int32_t mode = 0;
+    if ((s = check_fir_mode(M, cmp, algo, &mode))) return s;
     if (!h) return fail(TFX_E_INVALID_ARG, "taps h is NULL");
+    if ((s = check_ws(ws, ws_bytes, tfx::ws_layout(C, N, 0, M, 1, mode).total))) return s;
     tfx::ChainPlan p{};
+    p.fir_mode = mode;
     p.x = x; p.y = y; p.C = C; p.N = N; p.ldx = ldx; p.ldy = ldy;
     p.firs.ptr[0] = h;
     p.firs.len[0] = M;
@@ -247,7 +259,7 @@ tfx_status tfx_sos(const float *x, float *y, int64_t C, int64_t N, int64_t ldx, 
     if (s) return s;
     if (S < 0 || S > tfx::MAX_SECTIONS) return fail(TFX_E_INVALID_ARG, "S must be in [0, %d]", tfx::MAX_SECTIONS);
     if (S > 0 && !sos) return fail(TFX_E_INVALID_ARG, "sos is NULL");
-    const tfx::WsLayout lay = tfx::ws_layout(C, N, S, 0, 0);
+    const tfx::WsLayout lay = tfx::ws_layout(C, N, S, 0, 0, tfx::FIR_NONE);
     if ((s = check_ws(ws, ws_bytes, lay.total))) return s;
     if (state_out && N > 0) {
         const size_t sb = (size_t)C * S * 2 * sizeof(float);

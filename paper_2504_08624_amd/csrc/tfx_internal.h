@@ -1,4 +1,4 @@
-// Internal declarations shared by the kernel translation unit and the C ABI.
+// Internal declarations shared by the kernel translation units and the C ABI.
 #pragma once
 #include <hip/hip_runtime_api.h>
 #include <stddef.h>
@@ -6,41 +6,50 @@
 
 namespace tfx {
 
-// ---- IIR tiling -------------------------------------------------------------
-// A workgroup of WG lanes owns one tile of T = WG * L consecutive samples of one
-// channel; lane i owns the chunk [i*L, (i+1)*L) of the tile and keeps it in
-// registers for the whole chain (FIR output -> every section -> store).
-constexpr int WG = 256;
-constexpr int WAVES = WG / 64;
-constexpr int L = 32;
-constexpr int T = WG * L;
+// ---- tiling ------------------------------------------------------------------
+// A channel group of GL = 128 lanes owns one tile of T = GL * L consecutive
+// samples of one channel; lane i of the group owns chunk [i*L, (i+1)*L) and keeps
+// it in registers from the FIR output through every section to the store.  A
+// workgroup holds GROUPS = 2 channel groups (an even/odd channel pair), which is
+// also the pair the two-channel complex FFT filters together.
+constexpr int L = 24;
+constexpr int GL = 128;
+constexpr int GWAVES = GL / 64;
+constexpr int GROUPS = 2;
+constexpr int WG = GL * GROUPS;
+constexpr int T = GL * L;  // 3072
 
-// ---- direct FIR tiling -----------------------------------------------------
+// ---- direct FIR ----------------------------------------------------------------
 constexpr int KB = 16;          // taps per register block
 constexpr int KBLK_MAX = 1024;  // taps staged per LDS pass
+
+// ---- overlap-save FFT FIR --------------------------------------------------------
+constexpr int NFFT = 4096;              // complex points, 16 x 16 x 16
+constexpr int FFT_DISCARD = NFFT - T;   // 1024 leading outputs dropped per block
+constexpr int FFT_MAX_TAPS = FFT_DISCARD + 1;
 
 constexpr int MAX_STAGES = 64;
 constexpr int MAX_SECTIONS = 256;
 constexpr int MAX_TAPS = 65536;
+
+enum FirMode { FIR_NONE = 0, FIR_DIRECT = 1, FIR_FFT = 2 };
 
 // Per-section tables built on the device from the fp32 coefficients (in FP64,
 // then rounded).  2x2 matrices are row-major {m00, m01, m10, m11}.
 //   A    = [[-a1, 1], [-a2, 0]]     one-sample state transition (TDF-II)
 //   Phi  = A^L                       chunk transition
 //   Psi  = Phi^64                    wave transition
-//   PhiT = Psi^WAVES = A^T           tile transition
+//   PhiT = Psi^GWAVES = A^T          tile transition
 struct alignas(16) SecTab {
     float coef[5];
     int32_t hiq;             // 1: pole radius > 0.999 -> carry in FP64
     int32_t pad[2];
-    float g[L][2];           // first row of A^t (zero-input response), t < L
     float fold[64][4];       // Phi^k, k = 0..63
-    float psi[WAVES][4];     // Psi^w, w = 0..WAVES-1
-    float lb[7][4];          // PhiT^(2^j), j = 0..5, and PhiT^64
-    float apow[L][4];        // A^(t+1), t < L
+    float psi[GWAVES][4];    // Psi^w, w < GWAVES
+    float lb[9][4];          // PhiT^(2^j), j = 0..8
     double fold_d[64][4];
-    double psi_d[WAVES][4];
-    double lb_d[7][4];
+    double psi_d[GWAVES][4];
+    double lb_d[9][4];
 };
 
 struct StageList {
@@ -53,9 +62,8 @@ struct ChainPlan {
     const float *x;
     float *y;
     int64_t C, N, ldx, ldy;
-    const float *h;   // merged taps (device), nullptr if no FIR
-    int32_t M;
     int32_t S;        // total sections
+    int32_t fir_mode; // FirMode of the merged FIR
     StageList sos;    // SOS stages in order (device pointers)
     StageList firs;   // FIR stages in order (merged when more than one)
     const float *state_in;
@@ -66,12 +74,12 @@ struct ChainPlan {
     hipStream_t stream;
 };
 
-// Workspace layout of a chain/SOS call.
+// Workspace layout of a chain/SOS/FIR call.
 struct WsLayout {
-    size_t hdr, tab, flags, recs, taps, merge, total;
-    int64_t ntiles;
+    size_t hdr, tab, recs, taps, merge, twid, hspec, tw64, total;
+    int64_t ntiles, cpad;
 };
-WsLayout ws_layout(int64_t C, int64_t N, int32_t S, int32_t M_merged, int32_t n_fir);
+WsLayout ws_layout(int64_t C, int64_t N, int32_t S, int32_t M_merged, int32_t n_fir, int32_t fir_mode);
 
 // Tables + workspace initialisation (once per workspace and coefficients).
 hipError_t launch_prepare(const ChainPlan &p);

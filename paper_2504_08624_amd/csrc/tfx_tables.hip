@@ -1,0 +1,215 @@
+// tfx_tables.hip -- the prepare step: per-section scan tables, FFT twiddles and
+// tap spectrum, merged taps, workspace initialisation.  Everything is formed
+// in FP64 from the fp32 coefficients the filter kernel will see, and rounded
+// once.  These kernels run once per (workspace, coefficients); the filter
+// kernel (tfx_chain.hip) only reads what they leave in the workspace.
+#include <hip/hip_runtime.h>
+
+#include "tfx_internal.h"
+
+namespace tfx {
+
+__device__ void mat2_mul(const double *A, const double *B, double *C) {
+    const double c0 = A[0] * B[0] + A[1] * B[2];
+    const double c1 = A[0] * B[1] + A[1] * B[3];
+    const double c2 = A[2] * B[0] + A[3] * B[2];
+    const double c3 = A[2] * B[1] + A[3] * B[3];
+    C[0] = c0;
+    C[1] = c1;
+    C[2] = c2;
+    C[3] = c3;
+}
+
+__device__ void put4(float *f, double *d, const double *m) {
+    for (int i = 0; i < 4; ++i) {
+        f[i] = (float)m[i];
+        if (d) d[i] = m[i];
+    }
+}
+
+// Transition powers of one TDF-II section.  With state s = (s1, s2) the
+// section is s' = A s + B x, y = s1 + b0 x, A = [[-a1, 1], [-a2, 0]], so a
+// state s entering a chunk becomes A^L s after L samples.
+__device__ void build_section(SecTab *tb, const float *co) {
+    const double a1 = co[3], a2 = co[4];
+    for (int i = 0; i < 5; ++i) tb->coef[i] = co[i];
+    tb->pad[0] = tb->pad[1] = 0;
+    const double A[4] = {-a1, 1.0, -a2, 0.0};
+    double P[4] = {A[0], A[1], A[2], A[3]};
+    for (int t = 1; t < L; ++t) mat2_mul(P, A, P);
+    const double Phi[4] = {P[0], P[1], P[2], P[3]};
+    double F[4] = {1.0, 0.0, 0.0, 1.0};
+    for (int k = 0; k < 64; ++k) {
+        put4(tb->fold[k], tb->fold_d[k], F);
+        mat2_mul(F, Phi, F);
+    }
+    const double Psi[4] = {F[0], F[1], F[2], F[3]};
+    double W[4] = {1.0, 0.0, 0.0, 1.0};
+    for (int w = 0; w < GWAVES; ++w) {
+        put4(tb->psi[w], tb->psi_d[w], W);
+        mat2_mul(W, Psi, W);
+    }
+    double B[4] = {W[0], W[1], W[2], W[3]};  // PhiT = A^T
+    for (int j = 0; j < 9; ++j) {
+        put4(tb->lb[j], tb->lb_d[j], B);
+        mat2_mul(B, B, B);
+    }
+    const double disc = a1 * a1 - 4.0 * a2;
+    double r;
+    if (disc < 0.0) {
+        r = sqrt(a2);
+    } else {
+        const double sq = sqrt(disc);
+        r = fmax(fabs(0.5 * (-a1 + sq)), fabs(0.5 * (-a1 - sq)));
+    }
+    tb->hiq = r > 0.999 ? 1 : 0;
+}
+
+struct PrepArgs {
+    SecTab *tab;
+    int32_t S;
+    StageList sos;
+    uint64_t *recs;
+    int64_t nwords;
+    uint32_t *hdr;
+};
+
+// Section tables; clears the look-back records (tag 0 never matches an
+// epoch); arms the header (epoch 1).
+__global__ void prep_kernel(PrepArgs a) {
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = gid; i < a.nwords; i += stride) a.recs[i] = 0ull;
+    if (gid == 0) {
+        a.hdr[1] = 0u;  // error word
+        a.hdr[2] = 1u;  // epoch
+    }
+    if (gid < a.S) {
+        int s = (int)gid, st = 0;
+        while (s >= a.sos.len[st]) {
+            s -= a.sos.len[st];
+            ++st;
+        }
+        build_section(&a.tab[gid], a.sos.ptr[st] + 5 * s);
+    }
+}
+
+struct MergeArgs {
+    StageList firs;
+    double *buf0, *buf1;
+    float *out;
+};
+
+// Convolves the tap vectors of several FIR stages into one (FP64, one block).
+__global__ void merge_taps_kernel(MergeArgs a) {
+    int Mcur = a.firs.len[0];
+    for (int k = threadIdx.x; k < Mcur; k += blockDim.x) a.buf0[k] = a.firs.ptr[0][k];
+    __syncthreads();
+    double *cur = a.buf0, *nxt = a.buf1;
+    for (int st = 1; st < a.firs.n; ++st) {
+        const int Mi = a.firs.len[st];
+        const float *hi = a.firs.ptr[st];
+        const int Mn = Mcur + Mi - 1;
+        for (int k = threadIdx.x; k < Mn; k += blockDim.x) {
+            const int jlo = k - Mi + 1 > 0 ? k - Mi + 1 : 0;
+            const int jhi = k < Mcur - 1 ? k : Mcur - 1;
+            double acc = 0.0;
+            for (int j = jlo; j <= jhi; ++j) acc += cur[j] * (double)hi[k - j];
+            nxt[k] = acc;
+        }
+        __syncthreads();
+        double *t = cur;
+        cur = nxt;
+        nxt = t;
+        Mcur = Mn;
+    }
+    for (int k = threadIdx.x; k < Mcur; k += blockDim.x) a.out[k] = (float)cur[k];
+}
+
+// twid[k] = e^{-2 pi i k / 4096} in fp32 (filter kernel) and fp64 (spectrum)
+__global__ void fft_twiddle_kernel(float2 *twid, double2 *tw64) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= NFFT) return;
+    double s, c;
+    sincospi(-2.0 * (double)k / NFFT, &s, &c);
+    twid[k] = make_float2((float)c, (float)s);
+    tw64[k] = make_double2(c, s);
+}
+
+// hspec[k] = (sum_j h[j] e^{-2 pi i j k / 4096}) / 4096, the direct DFT of the
+// zero-padded taps in FP64 (exact twiddle indices j k mod 4096).  One block
+// of 256 lanes per 16 bins: lane (kk, jj) sums taps j = jj (mod 16) of bin
+// 16 blk + kk, then the 16 partial sums are added in a fixed order.
+__global__ void fft_spectrum_kernel(const float *h, int32_t M, const double2 *tw64, float2 *hspec) {
+    __shared__ double pr[16][17], pi[16][17];
+    const int kk = threadIdx.x >> 4, jj = threadIdx.x & 15;
+    const int k = blockIdx.x * 16 + kk;
+    double hr = 0.0, hi = 0.0;
+    for (int j = jj; j < M; j += 16) {
+        const double2 w = tw64[(j * k) & (NFFT - 1)];
+        hr += (double)h[j] * w.x;
+        hi += (double)h[j] * w.y;
+    }
+    pr[kk][jj] = hr;
+    pi[kk][jj] = hi;
+    __syncthreads();
+    if (jj == 0) {
+        double sr = 0.0, si = 0.0;
+        for (int u = 0; u < 16; ++u) {
+            sr += pr[kk][u];
+            si += pi[kk][u];
+        }
+        hspec[k] = make_float2((float)(sr / NFFT), (float)(si / NFFT));
+    }
+}
+
+__global__ void state_passthrough_kernel(const float *in, float *out, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = in ? in[i] : 0.f;
+}
+
+hipError_t launch_tables(const ChainPlan &p, const WsLayout &lay, const float *h, int32_t M) {
+    char *ws = static_cast<char *>(p.ws);
+    hipError_t e;
+    if (p.firs.n > 1) {
+        MergeArgs m;
+        m.firs = p.firs;
+        m.buf0 = reinterpret_cast<double *>(ws + lay.merge);
+        m.buf1 = m.buf0 + M;
+        m.out = reinterpret_cast<float *>(ws + lay.taps);
+        hipLaunchKernelGGL(merge_taps_kernel, dim3(1), dim3(256), 0, p.stream, m);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    if (p.firs.n > 0 && p.fir_mode == FIR_FFT) {
+        double2 *tw64 = reinterpret_cast<double2 *>(ws + lay.tw64);
+        hipLaunchKernelGGL(fft_twiddle_kernel, dim3(NFFT / 256), dim3(256), 0, p.stream,
+                           reinterpret_cast<float2 *>(ws + lay.twid), tw64);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        hipLaunchKernelGGL(fft_spectrum_kernel, dim3(NFFT / 16), dim3(256), 0, p.stream, h, M, tw64,
+                           reinterpret_cast<float2 *>(ws + lay.hspec));
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    if (p.S > 0) {
+        PrepArgs pa;
+        pa.tab = reinterpret_cast<SecTab *>(ws + lay.tab);
+        pa.S = p.S;
+        pa.sos = p.sos;
+        pa.recs = reinterpret_cast<uint64_t *>(ws + lay.recs);
+        pa.nwords = lay.cpad * lay.ntiles * p.S * 4;
+        pa.hdr = reinterpret_cast<uint32_t *>(ws + lay.hdr);
+        const int64_t work = pa.nwords > p.S ? pa.nwords : p.S;
+        int64_t nb = (work + 255) / 256;
+        if (nb > 1024) nb = 1024;
+        if (nb < 1) nb = 1;
+        hipLaunchKernelGGL(prep_kernel, dim3((unsigned)nb), dim3(256), 0, p.stream, pa);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t launch_state_passthrough(const float *in, float *out, int64_t n, hipStream_t st) {
+    hipLaunchKernelGGL(state_passthrough_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, in, out, n);
+    return hipGetLastError();
+}
+
+}  // namespace tfx

@@ -21,7 +21,7 @@ def test_status_strings_and_version():
     for code, name in lib.STATUS_NAMES.items():
         assert L.tfx_status_string(code).decode() == name
     assert L.tfx_version() >= 100
-    assert L.tfx_sos_tile_length() == 8192
+    assert L.tfx_sos_tile_length() == 3072
 
 
 def _st(name, *args):

@@ -17,7 +17,7 @@ from tests.metrics import TOL_FIR_F32, TOL_IIR_F32, assert_close
 pytestmark = pytest.mark.gpu
 
 DEV = "cuda:0"
-T = 8192
+T = 3072  # samples per IIR tile (tfx_sos_tile_length)
 
 
 def _x(C, N, key, sigma=0.1):
@@ -158,6 +158,28 @@ def test_fir_direct_parity(M, N):
     assert_close(y, O.fir(x, h), TOL_FIR_F32, "fir M=%d N=%d" % (M, N))
 
 
+@pytest.mark.parametrize("M", [1, 2, 49, 101, 255, 1023, 1024, 1025])
+@pytest.mark.parametrize("C,N", [(1, 1), (2, 100), (3, T + 1), (4, 5 * T - 5), (1, 20000)])
+def test_fir_fft_parity(M, C, N):
+    x = _x(C, N, (131, M, C, N))
+    h = (np.random.default_rng(M + 7).standard_normal(M) / np.sqrt(M)).astype(np.float32)
+    y = _cpu(tfx.fir(_gpu(x), _gpu(h), algo="fft"))
+    assert_close(y, O.fir(x, h), TOL_FIR_F32, "fft fir M=%d C=%d N=%d" % (M, C, N))
+
+
+def test_fir_fft_lowpass_designed_taps():
+    w = workloads.chain_mid(C=3, N=4 * T + 17)
+    h = w.stages[0][1]
+    y = _cpu(tfx.fir(_gpu(w.x), _gpu(h), algo="fft"))
+    assert_close(y, O.fir(w.x, h), TOL_FIR_F32, "fft band-pass 1023")
+
+
+def test_fir_fft_rejects_long_filters():
+    x = _gpu(_x(1, 100, (132,)))
+    with pytest.raises(lib.TfxError, match="UNSUPPORTED"):
+        tfx.fir(x, np.ones(1026, np.float32), algo="fft")
+
+
 def test_fir_longer_than_one_lds_pass():
     C, N, M = 2, 2 * T + 3, 3000
     x = _x(C, N, (121,))
@@ -170,8 +192,11 @@ def test_fir_impulse_gives_taps():
     h = np.random.default_rng(1).standard_normal(101).astype(np.float32)
     x = np.zeros((1, 500), np.float32)
     x[0, 0] = 1.0
-    y = _cpu(tfx.fir(_gpu(x), _gpu(h)))
+    y = _cpu(tfx.fir(_gpu(x), _gpu(h), algo="direct"))      # bit-exact: one product per output
     assert np.array_equal(y[0, :101], h) and np.all(y[0, 101:] == 0)
+    yf = _cpu(tfx.fir(_gpu(x), _gpu(h), algo="fft"))        # FFT: exact up to rounding
+    assert np.max(np.abs(yf[0, :101] - h)) < 1e-6 * np.abs(h).max()
+    assert np.max(np.abs(yf[0, 101:])) < 1e-6 * np.abs(h).max()
 
 
 # ----------------------------------------------------------------- chains
@@ -186,6 +211,23 @@ def test_chain_mid_reduced():
     w = workloads.chain_mid(C=3, N=150_000)
     y = _cpu(tfx.chain(_gpu(w.x), w.stages))
     assert_close(y, O.chain(w.x, w.stages), TOL_IIR_F32, "chain_mid reduced")
+
+
+@pytest.mark.parametrize("C", [1, 2, 5])
+def test_chain_fft_fused_odd_and_even_channels(C):
+    w = workloads.chain_short(C=C, N=7 * T + 123)
+    y = _cpu(tfx.chain(_gpu(w.x), w.stages))
+    assert_close(y, O.chain(w.x, w.stages), TOL_IIR_F32, "chain_short C=%d" % C)
+
+
+def test_chain_direct_fir_with_sections():
+    # 40 taps -> the direct path is picked; fused with a 3-section cascade
+    x = _x(3, 4 * T + 9, (133,))
+    h = design.fir_lowpass(40, 6000.0, 48000.0).astype(np.float32)
+    sec = _sections(3, (134,))
+    stages = [("fir", h), ("sos", sec)]
+    y = _cpu(tfx.chain(_gpu(x), stages))
+    assert_close(y, O.chain(x, stages), TOL_IIR_F32, "direct fir | sos")
 
 
 def test_chain_two_fir_stages_merge():
@@ -267,4 +309,4 @@ def test_chain_run_replays_on_prepared_workspace():
                                   ws.data_ptr(), ws.numel(), sp), "run")
         assert_close(_cpu(y), refs[i % 2], TOL_IIR_F32, "replay %d" % i)
     hdr = _cpu(ws[:16].view(torch.int32))
-    assert hdr[0] == 0 and hdr[1] == 0 and hdr[2] == 8 and hdr[3] == 0  # re-armed, no spin timeouts
+    assert hdr[1] == 0 and hdr[2] == 8  # epoch advanced once per run, no spin timeouts
