@@ -167,6 +167,49 @@ tfx_status tfx_chain_run(const float *x, float *y, int64_t C, int64_t N, int64_t
                          const tfx_stage *stages, int32_t nstages, tfx_compute cmp, float *ckpt,
                          void *ws, size_t ws_bytes, void *stream);
 
+/* --------------------------------------------------------------- adjoint */
+
+/* Gradients of a scalar loss L through the forward calls above, given
+ * gy = dL/dy (fp32, [C][N], row stride ldg):
+ *   gx    = dL/dx                      ([C][N], row stride ldgx; required)
+ *   taps  dL/dh[k] = sum_{c,n} gy'[c,n] x[c,n-k]            (FIR stage)
+ *   SOS   dL/d[b0 b1 b2 a1 a2] of every section, summed over channels
+ * The FIR adjoint is the correlation gx[n] = sum_k h[k] g[n+k]; the SOS
+ * adjoint runs the state-space adjoint recursion of each section in reverse
+ * time (lambda_n = A^T lambda_{n+1} + (g_n, 0)), by the same chunked scan as
+ * the forward with the transition transposed.  Section signals are rebuilt
+ * tile by tile from the forward's checkpoints `ckpt` (the tile-entering
+ * states written by the forward call with the same x, coefficients and
+ * state_in), so nothing is stored per sample.  Coefficient gradients are
+ * reduced in FP64 in a fixed order (bit-identical from run to run); gradient
+ * buffers are overwritten, not accumulated into.  The gradient with respect
+ * to state_in is not produced.
+ * Limits: at most 16 sections in the cascade (TFX_E_UNSUPPORTED beyond). */
+tfx_status tfx_chain_backward_workspace_size(int64_t C, int64_t N, const tfx_stage *stages,
+                                             int32_t nstages, tfx_compute cmp, size_t *bytes);
+/* grads: NULL (no coefficient gradients) or a host array of nstages device
+ * pointers, grads[i] shaped like stages[i].coef (NULL entries are skipped). */
+tfx_status tfx_chain_backward(const float *x, const float *gy, float *gx, int64_t C, int64_t N,
+                              int64_t ldx, int64_t ldg, int64_t ldgx, const tfx_stage *stages,
+                              int32_t nstages, tfx_compute cmp, const float *ckpt,
+                              float *const *grads, void *ws, size_t ws_bytes, void *stream);
+
+tfx_status tfx_fir_backward_workspace_size(int64_t C, int64_t N, int32_t M, tfx_compute cmp,
+                                           tfx_fir_algo algo, size_t *bytes);
+/* gh: NULL or [M] device buffer for dL/dh. */
+tfx_status tfx_fir_backward(const float *x, const float *gy, float *gx, int64_t C, int64_t N,
+                            int64_t ldx, int64_t ldg, int64_t ldgx, const float *h, int32_t M,
+                            float *gh, tfx_compute cmp, tfx_fir_algo algo, void *ws,
+                            size_t ws_bytes, void *stream);
+
+tfx_status tfx_sos_backward_workspace_size(int64_t C, int64_t N, int32_t S, size_t *bytes);
+/* ckpt: from the forward tfx_sos call (required when S > 0).  gsos: NULL or
+ * [S][5] device buffer. */
+tfx_status tfx_sos_backward(const float *x, const float *gy, float *gx, int64_t C, int64_t N,
+                            int64_t ldx, int64_t ldg, int64_t ldgx, const float *sos, int32_t S,
+                            const float *ckpt, float *gsos, void *ws, size_t ws_bytes,
+                            void *stream);
+
 #ifdef __cplusplus
 }
 #endif

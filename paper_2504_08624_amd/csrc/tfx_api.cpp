@@ -71,13 +71,16 @@ tfx_status check_fir_mode(int32_t M, tfx_compute cmp, tfx_fir_algo algo, int32_t
     if (M < 1 || M > tfx::MAX_TAPS) return fail(TFX_E_INVALID_ARG, "tap count M must be in [1, %d] (got %d)", tfx::MAX_TAPS, M);
     if (cmp < TFX_COMPUTE_F32 || cmp > TFX_COMPUTE_BF16X3) return fail(TFX_E_INVALID_ARG, "unknown compute mode %d", (int)cmp);
     if (algo < TFX_FIR_AUTO || algo > TFX_FIR_FFT) return fail(TFX_E_INVALID_ARG, "unknown FIR algorithm %d", (int)algo);
-    if (cmp != TFX_COMPUTE_F32) return fail(TFX_E_UNSUPPORTED, "compute mode %d not available in this build", (int)cmp);
+    if (cmp != TFX_COMPUTE_F32) {  // low-precision operands: only the matrix-core path
+        if (algo == TFX_FIR_DIRECT || algo == TFX_FIR_FFT)
+            return fail(TFX_E_UNSUPPORTED, "the direct and FFT paths compute in fp32 only");
+        *mode = tfx::FIR_TOEPLITZ;
+        return TFX_OK;
+    }
     if (algo == TFX_FIR_TOEPLITZ) return fail(TFX_E_UNSUPPORTED, "the Toeplitz path needs a bf16/fp16 compute mode");
-    if (algo == TFX_FIR_FFT && M > tfx::FFT_MAX_TAPS)
-        return fail(TFX_E_UNSUPPORTED, "overlap-save FFT handles at most %d taps (got %d)", tfx::FFT_MAX_TAPS, M);
     if (algo == TFX_FIR_DIRECT) *mode = tfx::FIR_DIRECT;
     else if (algo == TFX_FIR_FFT) *mode = tfx::FIR_FFT;
-    else *mode = (M > 48 && M <= tfx::FFT_MAX_TAPS) ? tfx::FIR_FFT : tfx::FIR_DIRECT;
+    else *mode = M > 48 ? tfx::FIR_FFT : tfx::FIR_DIRECT;
     return TFX_OK;
 }
 
@@ -144,6 +147,7 @@ tfx_status chain_plan(int64_t C, int64_t N, const tfx_stage *stages, int32_t nst
     const tfx::WsLayout lay = tfx::ws_layout(C, N, g.S, g.Mtot, g.firs.n, mode);
     if ((s = check_ws(ws, ws_bytes, lay.total))) return s;
     p.fir_mode = mode;
+    p.cmp = cmp;
     p.C = C;
     p.N = N;
     p.firs = g.firs;
@@ -153,6 +157,49 @@ tfx_status chain_plan(int64_t C, int64_t N, const tfx_stage *stages, int32_t nst
     p.ws_bytes = ws_bytes;
     p.stream = static_cast<hipStream_t>(stream);
     return TFX_OK;
+}
+
+// Validation shared by the adjoint entry points; fills bp (all but the
+// gradient lists).
+tfx_status bwd_plan(const float *x, const float *gy, float *gx, int64_t C, int64_t N, int64_t ldx, int64_t ldg,
+                    int64_t ldgx, const Gathered &g, int32_t mode, const float *ckpt, void *ws, size_t ws_bytes,
+                    void *stream, tfx::BwdPlan &bp) {
+    tfx_status s = check_signal(x, gx, C, N, ldx, ldgx);
+    if (s) return s;
+    if (ldg < N) return fail(TFX_E_INVALID_ARG, "ldg must be >= N");
+    if (N > 0 && !gy) return fail(TFX_E_INVALID_ARG, "gy is NULL");
+    if (N > 0 && overlaps(gy, span_bytes(C, N, ldg), gx, span_bytes(C, N, ldgx)))
+        return fail(TFX_E_ALIAS, "gx overlaps gy");
+    if (mode == tfx::FIR_TOEPLITZ) return fail(TFX_E_UNSUPPORTED, "the adjoint computes in fp32 only");
+    if (g.S > tfx::BWD_MAX_SECTIONS)
+        return fail(TFX_E_UNSUPPORTED, "the adjoint handles at most %d sections (got %d)", tfx::BWD_MAX_SECTIONS, g.S);
+    if (g.S > 0 && N > 0 && !ckpt) return fail(TFX_E_INVALID_ARG, "ckpt (the forward's checkpoints) is required");
+    const tfx::BwdLayout lay = tfx::bwd_layout(C, N, g.S, g.Mtot, g.firs.n, mode);
+    if ((s = check_ws(ws, ws_bytes, lay.total))) return s;
+    tfx::ChainPlan &p = bp.fwd;
+    p.x = x;
+    p.C = C;
+    p.N = N;
+    p.ldx = ldx;
+    p.S = g.S;
+    p.fir_mode = mode;
+    p.sos = g.sos;
+    p.firs = g.firs;
+    p.ckpt = const_cast<float *>(ckpt);
+    p.ws = ws;
+    p.ws_bytes = ws_bytes;
+    p.stream = static_cast<hipStream_t>(stream);
+    bp.gy = gy;
+    bp.gx = gx;
+    bp.ldg = ldg;
+    bp.ldgx = ldgx;
+    return TFX_OK;
+}
+
+tfx_status backward(const tfx::BwdPlan &bp) {
+    const hipError_t e = tfx::launch_backward(bp);
+    if (e != hipSuccess) return hip_fail(e, "adjoint kernel launch");
+    return ok();
 }
 
 }  // namespace
@@ -241,6 +288,7 @@ tfx_status tfx_fir(const float *x, float *y, int64_t C, int64_t N, int64_t ldx, 
     if ((s = check_ws(ws, ws_bytes, tfx::ws_layout(C, N, 0, M, 1, mode).total))) return s;
     tfx::ChainPlan p{};
     p.fir_mode = mode;
+    p.cmp = cmp;
     p.x = x; p.y = y; p.C = C; p.N = N; p.ldx = ldx; p.ldy = ldy;
     p.firs.ptr[0] = h;
     p.firs.len[0] = M;
@@ -314,6 +362,114 @@ tfx_status tfx_chain_run(const float *x, float *y, int64_t C, int64_t N, int64_t
     p.x = x; p.y = y; p.ldx = ldx; p.ldy = ldy;
     p.ckpt = ckpt;
     return execute(p);
+}
+
+tfx_status tfx_chain_backward_workspace_size(int64_t C, int64_t N, const tfx_stage *stages, int32_t nstages,
+                                             tfx_compute cmp, size_t *bytes) {
+    if (!bytes) return fail(TFX_E_INVALID_ARG, "bytes is NULL");
+    if (C < 1 || N < 0) return fail(TFX_E_INVALID_ARG, "bad shape");
+    Gathered g;
+    tfx_status s = gather(stages, nstages, g);
+    if (s) return s;
+    int32_t mode = tfx::FIR_NONE;
+    if (g.firs.n > 0 && (s = check_fir_mode(g.Mtot, cmp, TFX_FIR_AUTO, &mode))) return s;
+    *bytes = tfx::bwd_layout(C, N, g.S, g.Mtot, g.firs.n, mode).total;
+    return ok();
+}
+
+tfx_status tfx_chain_backward(const float *x, const float *gy, float *gx, int64_t C, int64_t N, int64_t ldx,
+                              int64_t ldg, int64_t ldgx, const tfx_stage *stages, int32_t nstages, tfx_compute cmp,
+                              const float *ckpt, float *const *grads, void *ws, size_t ws_bytes, void *stream) {
+    Gathered g;
+    tfx_status s = gather(stages, nstages, g);
+    if (s) return s;
+    int32_t mode = tfx::FIR_NONE;
+    if (g.firs.n > 0 && (s = check_fir_mode(g.Mtot, cmp, TFX_FIR_AUTO, &mode))) return s;
+    tfx::BwdPlan bp{};
+    if ((s = bwd_plan(x, gy, gx, C, N, ldx, ldg, ldgx, g, mode, ckpt, ws, ws_bytes, stream, bp))) return s;
+    // gradient pointers in the order of the gathered stage lists
+    for (int i = 0; i < nstages; ++i) {
+        const tfx_stage &st = stages[i];
+        float *gp = grads ? grads[i] : nullptr;
+        if (st.kind == TFX_STAGE_FIR) {
+            bp.gfir.ptr[bp.gfir.n] = gp;
+            bp.gfir.len[bp.gfir.n] = st.len;
+            bp.gfir.n++;
+        } else if (st.len > 0) {
+            bp.gsos.ptr[bp.gsos.n] = gp;
+            bp.gsos.len[bp.gsos.n] = st.len;
+            bp.gsos.n++;
+        }
+    }
+    return backward(bp);
+}
+
+tfx_status tfx_fir_backward_workspace_size(int64_t C, int64_t N, int32_t M, tfx_compute cmp, tfx_fir_algo algo,
+                                           size_t *bytes) {
+    if (!bytes) return fail(TFX_E_INVALID_ARG, "bytes is NULL");
+    int32_t mode = 0;
+    tfx_status s = check_fir_mode(M, cmp, algo, &mode);
+    if (s) return s;
+    if (C < 1 || N < 0) return fail(TFX_E_INVALID_ARG, "bad shape");
+    *bytes = tfx::bwd_layout(C, N, 0, M, 1, mode).total;
+    return ok();
+}
+
+tfx_status tfx_fir_backward(const float *x, const float *gy, float *gx, int64_t C, int64_t N, int64_t ldx,
+                            int64_t ldg, int64_t ldgx, const float *h, int32_t M, float *gh, tfx_compute cmp,
+                            tfx_fir_algo algo, void *ws, size_t ws_bytes, void *stream) {
+    int32_t mode = 0;
+    tfx_status s = check_fir_mode(M, cmp, algo, &mode);
+    if (s) return s;
+    if (!h) return fail(TFX_E_INVALID_ARG, "taps h is NULL");
+    Gathered g;
+    g.firs.ptr[0] = h;
+    g.firs.len[0] = M;
+    g.firs.n = 1;
+    g.Mtot = M;
+    tfx::BwdPlan bp{};
+    if ((s = bwd_plan(x, gy, gx, C, N, ldx, ldg, ldgx, g, mode, nullptr, ws, ws_bytes, stream, bp))) return s;
+    bp.gfir.ptr[0] = gh;
+    bp.gfir.len[0] = M;
+    bp.gfir.n = 1;
+    return backward(bp);
+}
+
+tfx_status tfx_sos_backward_workspace_size(int64_t C, int64_t N, int32_t S, size_t *bytes) {
+    if (!bytes) return fail(TFX_E_INVALID_ARG, "bytes is NULL");
+    if (C < 1 || N < 0 || S < 0 || S > tfx::MAX_SECTIONS) return fail(TFX_E_INVALID_ARG, "bad shape");
+    *bytes = tfx::bwd_layout(C, N, S, 0, 0, tfx::FIR_NONE).total;
+    return ok();
+}
+
+tfx_status tfx_sos_backward(const float *x, const float *gy, float *gx, int64_t C, int64_t N, int64_t ldx,
+                            int64_t ldg, int64_t ldgx, const float *sos, int32_t S, const float *ckpt, float *gsos,
+                            void *ws, size_t ws_bytes, void *stream) {
+    if (S < 0 || S > tfx::MAX_SECTIONS) return fail(TFX_E_INVALID_ARG, "S must be in [0, %d]", tfx::MAX_SECTIONS);
+    if (S > 0 && !sos) return fail(TFX_E_INVALID_ARG, "sos is NULL");
+    Gathered g;
+    if (S > 0) {
+        g.sos.ptr[0] = sos;
+        g.sos.len[0] = S;
+        g.sos.n = 1;
+        g.S = S;
+    }
+    tfx::BwdPlan bp{};
+    tfx_status s = bwd_plan(x, gy, gx, C, N, ldx, ldg, ldgx, g, tfx::FIR_NONE, ckpt, ws, ws_bytes, stream, bp);
+    if (s) return s;
+    if (S > 0) {
+        bp.gsos.ptr[0] = gsos;
+        bp.gsos.len[0] = S;
+        bp.gsos.n = 1;
+    }
+    if (S == 0) {  // identity: gx = gy
+        if (N == 0) return ok();
+        const hipError_t e = hipMemcpy2DAsync(gx, ldgx * sizeof(float), gy, ldg * sizeof(float), N * sizeof(float),
+                                              C, hipMemcpyDeviceToDevice, static_cast<hipStream_t>(stream));
+        if (e != hipSuccess) return hip_fail(e, "copy");
+        return ok();
+    }
+    return backward(bp);
 }
 
 }  // extern "C"

@@ -1,0 +1,573 @@
+// tfx_backward.hip -- adjoint of the FIR / IIR-SOS chain (gradients with
+// respect to the chain input, the FIR taps and the section coefficients).
+//
+// SOS section, forward s_{n+1} = A s_n + B x_n, y_n = C s_n + D x_n with
+// A = [[-a1, 1], [-a2, 0]], B = (b1 - a1 b0, b2 - a2 b0), C = (1, 0), D = b0
+// (transposed direct form II).  For upstream gradient g = dL/dy the adjoint
+// state lambda_n = dL/ds_n obeys, backwards in time,
+//     lambda_n = A^T lambda_{n+1} + C^T g_n,      lambda_N = 0,
+//     dL/dx_n  = D g_n + B^T lambda_{n+1},
+// and the coefficient gradients are sums over samples (and channels):
+//     dL/dA = sum lambda_{n+1} s_n^T,  dL/dB = sum lambda_{n+1} x_n,
+//     dL/dD = sum g_n x_n,
+// mapped to (b0, b1, b2, a1, a2) through the definitions of A, B, D.  Since
+// A^T has the same form as A, the adjoint recursion is the same 2x2 linear
+// recurrence run in reverse time, and this kernel reuses the forward's
+// chunked scan: lane l of a channel group owns chunk 127 - l of the tile (so
+// lane order is reverse time), tiles are dispatched last first, and the scan
+// tables are used transposed.  Section signals are recomputed per tile from
+// the forward's checkpointed tile-entering states (no per-sample storage):
+// one forward pass over the tile records every chunk-entering state of every
+// section, and the input of section s is then rebuilt in each lane's
+// registers from those states.
+//
+// FIR, y = h * x: dL/dx[n] = sum_k h[k] g[n + k] (the forward kernel's
+// correlation mode) and dL/dh[k] = sum_{c,n} g[c,n] x[c,n-k], computed per
+// tile as a circular cross-correlation with 4096-point FFTs (a channel pair
+// packed as one complex signal: the real part of conj(FFT(g)) FFT(x) sums both
+// channels' correlations).  Coefficient gradients are per-tile partial sums
+// reduced in a fixed order in FP64, so results are bit-identical run to run.
+#include <hip/hip_runtime.h>
+
+#include "tfx_device.h"
+
+namespace tfx {
+
+struct BArgs {
+    const float *f;   // cascade input (the chain input, or its FIR output)
+    const float *g;   // gradient of the cascade output
+    float *gf;        // gradient of the cascade input
+    int64_t C, N, ldf, ldg, ldo;
+    const SecTab *tab;
+    int32_t S;
+    const float *ckpt;  // [C][ntiles][S][2] forward tile-entering states
+    double *part;       // [S][5][cpad * ntiles] per group-tile partial sums
+    uint64_t *recs;     // adjoint look-back records [cpad][ntiles][S]
+    uint32_t *hdr;
+    int64_t ntiles, cpad;
+    int32_t vecf, vecg, veco;
+};
+
+// TDF-II section over a lane's chunk from state (s1, s2), in place.
+__device__ __forceinline__ void tdf2_chunk(float (&v)[L], const float *co, float s1, float s2) {
+    const float b0 = co[0], b1 = co[1], b2 = co[2], a1 = co[3], a2 = co[4];
+#pragma unroll
+    for (int r = 0; r < L; ++r) {
+        const float xv = v[r];
+        const float yv = fmaf(b0, xv, s1);
+        s1 = fmaf(b1, xv, fmaf(-a1, yv, s2));
+        s2 = fmaf(b2, xv, -a2 * yv);
+        v[r] = yv;
+    }
+}
+
+__global__ __launch_bounds__(WG) void sos_bwd_kernel(BArgs a) {
+    __shared__ __align__(16) float stg_all[GROUPS * STG_FLOATS];
+    __shared__ float2 sig[GROUPS][BWD_MAX_SECTIONS][GL];  // chunk-entering forward states
+    __shared__ double s_agg[2 * GROUPS][GWAVES][2];
+    __shared__ double s_pre[2 * GROUPS][2];
+    __shared__ double s_red[2][GROUPS][GWAVES][5];
+    __shared__ uint32_t s_epoch;
+
+    const int tid = threadIdx.x, lane = tid & 63, grp = tid / GL, gl = tid % GL, gw = gl >> 6;
+    if (tid == 0) s_epoch = load_epoch(a.hdr, HDR_EPOCH);
+    const uint64_t npairs = (uint64_t)(a.cpad / 2);
+    const int64_t pos = (int64_t)(blockIdx.x / npairs);  // reverse-time processing position
+    const int64_t tile = a.ntiles - 1 - pos;
+    const int64_t pair = (int64_t)(blockIdx.x % npairs);
+    const int64_t ch = 2 * pair + grp;
+    const bool valid = ch < a.C;
+    const int64_t n0 = tile * T;
+    const int S = a.S;
+    float *stg = stg_all + grp * STG_FLOATS;
+    const int mc = GL - 1 - gl;  // the chunk this lane owns in reverse time
+
+    // 1. stage f; lanes take their forward chunk (gl) and their reverse-time
+    //    chunk (mc)
+    stage_tile(stg, a.f + ch * a.ldf + n0, a.N - n0, valid, a.vecf != 0, gl);
+    __syncthreads();
+    const uint32_t epoch = s_epoch;
+    float v[L], fr[L];
+    load_chunk(stg, gl, v);
+    load_chunk(stg, mc, fr);
+
+    // 2. forward recompute from the checkpointed tile-entering states,
+    //    recording every section's chunk-entering state
+    for (int s = 0; s < S; ++s) {
+        const SecTab &tb = a.tab[s];
+        const float b0 = tb.coef[0], b1 = tb.coef[1], b2 = tb.coef[2], a1 = tb.coef[3], a2 = tb.coef[4];
+        float s1 = 0.f, s2 = 0.f;
+#pragma unroll
+        for (int r = 0; r < L; ++r) {
+            const float xv = v[r];
+            const float yv = fmaf(b0, xv, s1);
+            s1 = fmaf(b1, xv, fmaf(-a1, yv, s2));
+            s2 = fmaf(b2, xv, -a2 * yv);
+            v[r] = yv;
+        }
+        CarryCtx cc;
+        cc.lane = lane;
+        cc.gw = gw;
+        cc.grp = grp;
+        cc.lookback = false;
+        cc.pos = tile;
+        cc.recs = nullptr;
+        cc.rec0 = 0;
+        cc.rstride = 0;
+        cc.epoch = 0;
+        cc.hdr = a.hdr;
+        cc.known0 = valid ? a.ckpt[((ch * a.ntiles + tile) * S + s) * 2 + 0] : 0.0;
+        cc.known1 = valid ? a.ckpt[((ch * a.ntiles + tile) * S + s) * 2 + 1] : 0.0;
+        cc.prefix_out = nullptr;
+        float z1, z2;
+        if (tb.hiq)
+            carry<double, false>(tb, cc, s1, s2, z1, z2, s_agg, s_pre, (s & 1) * GROUPS + grp);
+        else
+            carry<float, false>(tb, cc, s1, s2, z1, z2, s_agg, s_pre, (s & 1) * GROUPS + grp);
+        sig[grp][s][gl] = make_float2(z1, z2);
+        if (s + 1 < S) {
+#pragma unroll
+            for (int r = 0; r < L; ++r) {
+                v[r] += z1;
+                const float n1 = fmaf(-a1, z1, z2);
+                z2 = -a2 * z1;
+                z1 = n1;
+            }
+        }
+    }
+    // 3. stage g (over f); lanes take their reverse-time chunk
+    __syncthreads();
+    stage_tile(stg, a.g + ch * a.ldg + n0, a.N - n0, valid, a.vecg != 0, gl);
+    __syncthreads();
+    float gr[L];
+    load_chunk(stg, mc, gr);
+
+    // 4. sections in reverse order
+    for (int s = S - 1; s >= 0; --s) {
+        const SecTab &tb = a.tab[s];
+        const float b0 = tb.coef[0], b1 = tb.coef[1], b2 = tb.coef[2], a1 = tb.coef[3], a2 = tb.coef[4];
+        const float B0 = fmaf(-a1, b0, b1), B1 = fmaf(-a2, b0, b2);
+        // (a) input of section s over chunk mc, and s1 before every sample
+        float xs[L], sf[L];
+#pragma unroll
+        for (int r = 0; r < L; ++r) xs[r] = fr[r];
+        for (int j = 0; j < s; ++j) {
+            const float2 st = sig[grp][j][mc];
+            tdf2_chunk(xs, a.tab[j].coef, st.x, st.y);
+        }
+        {
+            const float2 st = sig[grp][s][mc];
+            float s1 = st.x, s2 = st.y;
+#pragma unroll
+            for (int r = 0; r < L; ++r) {
+                const float xv = xs[r];
+                sf[r] = s1;
+                const float yv = fmaf(b0, xv, s1);
+                s1 = fmaf(b1, xv, fmaf(-a1, yv, s2));
+                s2 = fmaf(b2, xv, -a2 * yv);
+            }
+        }
+        // (b) adjoint zero-state response of the chunk, last sample first
+        float m0 = 0.f, m1 = 0.f;
+#pragma unroll
+        for (int r = L - 1; r >= 0; --r) {
+            const float n0v = fmaf(-a1, m0, fmaf(-a2, m1, gr[r]));
+            m1 = m0;
+            m0 = n0v;
+        }
+        // (c) carry in reverse time: the adjoint state entering the chunk from
+        //     its end
+        CarryCtx cc;
+        cc.lane = lane;
+        cc.gw = gw;
+        cc.grp = grp;
+        cc.lookback = true;
+        cc.pos = pos;
+        cc.recs = a.recs;
+        cc.rec0 = ch * a.ntiles * S + s;
+        cc.rstride = S;
+        cc.epoch = epoch;
+        cc.hdr = a.hdr;
+        cc.known0 = cc.known1 = 0.0;  // lambda_N = 0
+        cc.prefix_out = nullptr;
+        float e0, e1;
+        const int buf = ((S - 1 - s) & 1) * GROUPS + grp;
+        if (tb.hiq)
+            carry<double, true>(tb, cc, m0, m1, e0, e1, s_agg, s_pre, buf);
+        else
+            carry<float, true>(tb, cc, m0, m1, e0, e1, s_agg, s_pre, buf);
+        // (d) the adjoint recursion from the true state: input gradient and
+        //     coefficient-gradient sums
+        double dA00 = 0.0, dA10 = 0.0, dB0 = 0.0, dB1 = 0.0, dD = 0.0;
+        m0 = e0;
+        m1 = e1;  // lambda_{n+1}
+#pragma unroll
+        for (int r = L - 1; r >= 0; --r) {
+            const float gv = gr[r];
+            const float gx = fmaf(b0, gv, fmaf(B0, m0, B1 * m1));
+            dA00 = fma((double)m0, (double)sf[r], dA00);
+            dA10 = fma((double)m1, (double)sf[r], dA10);
+            dB0 = fma((double)m0, (double)xs[r], dB0);
+            dB1 = fma((double)m1, (double)xs[r], dB1);
+            dD = fma((double)gv, (double)xs[r], dD);
+            const float n0v = fmaf(-a1, m0, fmaf(-a2, m1, gv));
+            m1 = m0;
+            m0 = n0v;
+            gr[r] = gx;
+        }
+        // (e) group sums, in a fixed order
+        double red[5] = {dA00, dA10, dB0, dB1, dD};
+#pragma unroll
+        for (int k = 0; k < 5; ++k) {
+#pragma unroll
+            for (int d = 32; d >= 1; d >>= 1) red[k] += __shfl_xor(red[k], d);
+        }
+        const int rb = (S - 1 - s) & 1;
+        if (lane == 0) {
+#pragma unroll
+            for (int k = 0; k < 5; ++k) s_red[rb][grp][gw][k] = red[k];
+        }
+        __syncthreads();
+        if (gl == 0 && valid) {
+#pragma unroll
+            for (int k = 0; k < 5; ++k) {
+                double t = 0.0;
+#pragma unroll
+                for (int w = 0; w < GWAVES; ++w) t += s_red[rb][grp][w][k];
+                a.part[((int64_t)s * 5 + k) * (a.cpad * a.ntiles) + ch * a.ntiles + tile] = t;
+            }
+        }
+    }
+    // 5. gradient of the cascade input
+    __syncthreads();
+    store_chunk(stg, mc, gr);
+    __syncthreads();
+    if (valid) store_tile(a.gf + ch * a.ldo + n0, stg, a.N - n0, a.veco != 0, gl);
+}
+
+// Section-coefficient gradients from the per-tile partial sums.  One block
+// per section: each of the five sums is reduced in FP64 in a fixed order
+// (lane-strided partial sums, then a fixed tree), then mapped to the
+// gradients [b0 b1 b2 a1 a2] of the section's stage row.
+struct SosGradArgs {
+    const double *part;
+    const SecTab *tab;
+    int32_t S;
+    int64_t C, ntiles, cpad;
+    GradList out;
+};
+
+constexpr int RED_THREADS = 256;
+
+__device__ double block_sum_fixed(double v, double *sh) {
+    const int t = threadIdx.x;
+    sh[t] = v;
+    __syncthreads();
+    for (int w = RED_THREADS / 2; w >= 1; w >>= 1) {
+        if (t < w) sh[t] += sh[t + w];
+        __syncthreads();
+    }
+    const double r = sh[0];
+    __syncthreads();
+    return r;
+}
+
+__global__ __launch_bounds__(RED_THREADS) void sos_grad_reduce_kernel(SosGradArgs a) {
+    __shared__ double sh[RED_THREADS];
+    const int s = blockIdx.x;
+    const int64_t stride = a.cpad * a.ntiles;
+    const int64_t n = a.C * a.ntiles;  // entries ch * ntiles + tile, ch < C
+    double d[5];
+    for (int k = 0; k < 5; ++k) {
+        const double *p = a.part + ((int64_t)s * 5 + k) * stride;
+        double t = 0.0;
+        for (int64_t i = threadIdx.x; i < n; i += RED_THREADS) t += p[i];
+        d[k] = block_sum_fixed(t, sh);
+    }
+    if (threadIdx.x != 0) return;
+    const double b0 = a.tab[s].coef[0], a1 = a.tab[s].coef[3], a2 = a.tab[s].coef[4];
+    const double dA00 = d[0], dA10 = d[1], dB0 = d[2], dB1 = d[3], dD = d[4];
+    int st = 0, j = s;
+    while (j >= a.out.len[st]) {
+        j -= a.out.len[st];
+        ++st;
+    }
+    float *o = a.out.ptr[st];
+    if (!o) return;
+    o[5 * j + 0] = (float)(dD - a1 * dB0 - a2 * dB1);  // b0 enters D and both entries of B
+    o[5 * j + 1] = (float)dB0;
+    o[5 * j + 2] = (float)dB1;
+    o[5 * j + 3] = (float)(-dA00 - b0 * dB0);  // a1 enters A[0][0] and B[0]
+    o[5 * j + 4] = (float)(-dA10 - b0 * dB1);  // a2 enters A[1][0] and B[1]
+}
+
+// Tap-gradient partials.  Block (pair, tile group, lag block kb): for the
+// lags k in [1025 kb, 1025 kb + 1025) and the tiles of the group,
+//   part[blk][k] = sum over the pair's two channels, the tiles' samples n of
+//                  g[n] x[n - k],
+// one 4096-point circular cross-correlation per tile: with z the x block
+// starting 1024 + 1025 kb samples before the tile and w the tile's g (zero
+// past it), Re IFFT(conj(W) Z)[d] at d = 1024 - (k - 1025 kb) is that sum
+// (no wrap-around, as d + 3071 < 4096), both channels at once.
+struct GhArgs {
+    const float *x, *g;
+    int64_t C, N, ldx, ldg;
+    int32_t M;
+    int64_t ntiles, cpad, tpb;
+    const float2 *twid;
+    float *part;  // [npairs * ntg][M]
+};
+
+__global__ __launch_bounds__(WG) void fir_gh_part_kernel(GhArgs a) {
+    __shared__ __align__(16) float lds[2 * NFFT];
+    const int tid = threadIdx.x;
+    const int64_t npairs = a.cpad / 2;
+    const int64_t tg = blockIdx.x / npairs, pair = blockIdx.x % npairs;
+    const int64_t k0 = (int64_t)blockIdx.y * FFT_PART;
+    const int64_t chA = 2 * pair, chB = chA + 1;
+    const float *xA = a.x + chA * a.ldx, *xB = chB < a.C ? a.x + chB * a.ldx : nullptr;
+    const float *gA = a.g + chA * a.ldg, *gB = chB < a.C ? a.g + chB * a.ldg : nullptr;
+    float acc[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) acc[q] = 0.f;
+    const int64_t t1 = min(a.ntiles, (tg + 1) * a.tpb);
+    for (int64_t tile = tg * a.tpb; tile < t1; ++tile) {
+        const int64_t n0 = tile * T;
+        float zr[16], zi[16], wr[16], wi[16];
+        load_pair_block(zr, zi, xA, xB, n0 - FFT_DISCARD - k0, a.N, a.N, tid);
+        __syncthreads();  // previous tile's last LDS reads
+        fft4096_forward(zr, zi, lds, a.twid, tid);
+        load_pair_block(wr, wi, gA, gB, n0, a.N, n0 + T, tid);
+        __syncthreads();
+        fft4096_forward(wr, wi, lds, a.twid, tid);
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {  // conj(W) Z
+            const float r = wr[k] * zr[k] + wi[k] * zi[k];
+            const float i = wr[k] * zi[k] - wi[k] * zr[k];
+            zr[k] = r;
+            zi[k] = i;
+        }
+        fft4096_inverse(zr, zi, lds, a.twid, tid);
+#pragma unroll
+        for (int q = 0; q < 16; ++q) acc[q] += zr[q];
+    }
+    // lane tid holds d = 256 q + tid
+    float *out = a.part + (int64_t)blockIdx.x * a.M;
+#pragma unroll
+    for (int q = 0; q < 5; ++q) {
+        const int d = 256 * q + tid;
+        const int64_t k = k0 + FFT_DISCARD - d;
+        if (d <= FFT_DISCARD && k < a.M) out[k] = acc[q] * (1.0f / NFFT);
+    }
+}
+
+// dst[k] = sum of the partials in block order, FP64.
+__global__ void fir_gh_reduce_kernel(const float *part, int32_t M, int64_t nparts, float *dst) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= M) return;
+    double t = 0.0;
+    for (int64_t p = 0; p < nparts; ++p) t += (double)part[p * M + k];
+    dst[k] = (float)t;
+}
+
+// out = a (*) b, FP64 (a == null stands for the unit impulse).
+__global__ void conv_f64_kernel(const double *a, int32_t na, const float *b, int32_t nb, double *out) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (a == nullptr) {
+        if (k < nb) out[k] = b[k];
+        return;
+    }
+    if (k >= na + nb - 1) return;
+    const int jlo = k - nb + 1 > 0 ? k - nb + 1 : 0;
+    const int jhi = k < na - 1 ? k : na - 1;
+    double acc = 0.0;
+    for (int j = jlo; j <= jhi; ++j) acc += a[j] * (double)b[k - j];
+    out[k] = acc;
+}
+
+// Gradient of one of several merged FIR stages: with H = h_i (*) O (O the
+// convolution of the other stages' taps), dL/dh_i[k] = sum_j O[j] gH[j + k].
+__global__ void stage_tap_grad_kernel(const double *O, int32_t nO, const float *gH, int32_t Mi, float *out) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= Mi) return;
+    double acc = 0.0;
+    for (int j = 0; j < nO; ++j) acc += O[j] * (double)gH[j + k];
+    out[k] = (float)acc;
+}
+
+// ------------------------------------------------------------------- host
+
+// kernels of the prepare step (tfx_tables.hip)
+hipError_t launch_twiddles(float2 *twid, double2 *tw64, hipStream_t st);
+hipError_t launch_state_passthrough(const float *in, float *out, int64_t n, hipStream_t st);
+
+static size_t al256(size_t b) { return (b + 255) & ~size_t(255); }
+
+BwdLayout bwd_layout(int64_t C, int64_t N, int32_t S, int32_t M_merged, int32_t n_fir, int32_t fir_mode) {
+    BwdLayout b{};
+    b.fwd = ws_layout(C, N, S, M_merged, n_fir, fir_mode);
+    const int64_t ntiles = b.fwd.ntiles, cpad = b.fwd.cpad, npairs = cpad / 2;
+    // the forward layout ends with a 256-aligned total (or 0 when it needs nothing)
+    size_t off = b.fwd.total ? b.fwd.total : 256;
+    if (b.fwd.total == 0) b.fwd.hdr = 0;
+    b.part_sos = off;
+    off += al256((size_t)S * 5 * cpad * ntiles * sizeof(double));
+    const bool both = n_fir > 0 && S > 0;
+    b.fbuf = off;
+    if (both) off += al256((size_t)C * N * sizeof(float));
+    b.gfbuf = off;
+    if (both) off += al256((size_t)C * N * sizeof(float));
+    b.tpb = b.ntg = b.nlag = 0;
+    b.part_gh = b.gH = b.obuf = b.twid = b.tw64 = off;
+    if (n_fir > 0 && ntiles > 0) {
+        b.nlag = (M_merged + FFT_PART - 1) / FFT_PART;
+        const int64_t want = 2048;  // blocks to fill the chip
+        b.tpb = (npairs * ntiles * b.nlag + want - 1) / want;
+        if (b.tpb < 1) b.tpb = 1;
+        b.ntg = (ntiles + b.tpb - 1) / b.tpb;
+        off += al256((size_t)npairs * b.ntg * M_merged * sizeof(float));
+        b.gH = off;
+        off += al256((size_t)M_merged * sizeof(float));
+        b.obuf = off;
+        if (n_fir > 1) off += al256((size_t)M_merged * 2 * sizeof(double));
+        b.twid = b.tw64 = off;
+        if (fir_mode != FIR_FFT) {
+            off += al256(NFFT * sizeof(float2));
+            b.tw64 = off;
+            off += al256(NFFT * sizeof(double2));
+        }
+    }
+    b.total = off;
+    return b;
+}
+
+hipError_t launch_backward(const BwdPlan &bp) {
+    const ChainPlan &p = bp.fwd;
+    const int32_t M = merged_taps(p.firs);
+    const BwdLayout lay = bwd_layout(p.C, p.N, p.S, M, p.firs.n, p.fir_mode);
+    char *ws = static_cast<char *>(p.ws);
+    hipStream_t st = p.stream;
+    hipError_t e;
+    if (p.N == 0) {  // every gradient sum is empty
+        for (int i = 0; i < bp.gsos.n; ++i)
+            if (bp.gsos.ptr[i] && (e = launch_state_passthrough(nullptr, bp.gsos.ptr[i], 5 * (int64_t)bp.gsos.len[i], st)))
+                return e;
+        for (int i = 0; i < bp.gfir.n; ++i)
+            if (bp.gfir.ptr[i] && (e = launch_state_passthrough(nullptr, bp.gfir.ptr[i], bp.gfir.len[i], st)))
+                return e;
+        return hipSuccess;
+    }
+    const bool has_fir = p.firs.n > 0, has_sos = p.S > 0;
+    const float *h = has_fir ? (p.firs.n == 1 ? p.firs.ptr[0] : reinterpret_cast<const float *>(ws + lay.fwd.taps))
+                             : nullptr;
+    // tables, merged taps, spectrum; clears the look-back records
+    if ((e = launch_tables(p, lay.fwd, h, M)) != hipSuccess) return e;
+    // the cascade input f and the gradient of the cascade input gf
+    const float *f = p.x;
+    int64_t ldf = p.ldx;
+    float *gf = bp.gx;
+    int64_t ldgf = bp.ldgx;
+    if (has_fir && has_sos) {
+        float *fb = reinterpret_cast<float *>(ws + lay.fbuf);
+        if ((e = launch_fir_pass(p, lay.fwd, p.x, p.ldx, fb, p.N, false)) != hipSuccess) return e;
+        f = fb;
+        ldf = p.N;
+        gf = reinterpret_cast<float *>(ws + lay.gfbuf);
+        ldgf = p.N;
+    }
+    const int64_t ntiles = lay.fwd.ntiles, cpad = lay.fwd.cpad, npairs = cpad / 2;
+    if (has_sos) {
+        BArgs b{};
+        b.f = f;
+        b.g = bp.gy;
+        b.gf = has_fir ? gf : bp.gx;
+        b.C = p.C;
+        b.N = p.N;
+        b.ldf = ldf;
+        b.ldg = bp.ldg;
+        b.ldo = has_fir ? ldgf : bp.ldgx;
+        b.tab = reinterpret_cast<const SecTab *>(ws + lay.fwd.tab);
+        b.S = p.S;
+        b.ckpt = p.ckpt;
+        b.part = reinterpret_cast<double *>(ws + lay.part_sos);
+        b.recs = reinterpret_cast<uint64_t *>(ws + lay.fwd.recs);
+        b.hdr = reinterpret_cast<uint32_t *>(ws + lay.fwd.hdr);
+        b.ntiles = ntiles;
+        b.cpad = cpad;
+        b.vecf = (reinterpret_cast<uintptr_t>(b.f) % 16 == 0 && b.ldf % 4 == 0) ? 1 : 0;
+        b.vecg = (reinterpret_cast<uintptr_t>(b.g) % 16 == 0 && b.ldg % 4 == 0) ? 1 : 0;
+        b.veco = (reinterpret_cast<uintptr_t>(b.gf) % 16 == 0 && b.ldo % 4 == 0) ? 1 : 0;
+        hipLaunchKernelGGL(sos_bwd_kernel, dim3((unsigned)(npairs * ntiles)), dim3(WG), 0, st, b);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        SosGradArgs r{};
+        r.part = b.part;
+        r.tab = b.tab;
+        r.S = p.S;
+        r.C = p.C;
+        r.ntiles = ntiles;
+        r.cpad = cpad;
+        r.out = bp.gsos;
+        hipLaunchKernelGGL(sos_grad_reduce_kernel, dim3((unsigned)p.S), dim3(RED_THREADS), 0, st, r);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    if (!has_fir) return hipSuccess;
+    const float *gfc = has_sos ? gf : bp.gy;
+    const int64_t ldgfc = has_sos ? ldgf : bp.ldg;
+    // input gradient: correlation of the cascade-input gradient with the taps
+    if ((e = launch_fir_pass(p, lay.fwd, gfc, ldgfc, bp.gx, bp.ldgx, true)) != hipSuccess) return e;
+    // gradient of the merged taps
+    bool any = false;
+    for (int i = 0; i < bp.gfir.n; ++i) any = any || bp.gfir.ptr[i] != nullptr;
+    if (!any) return hipSuccess;
+    GhArgs g{};
+    g.x = p.x;
+    g.g = gfc;
+    g.C = p.C;
+    g.N = p.N;
+    g.ldx = p.ldx;
+    g.ldg = ldgfc;
+    g.M = M;
+    g.ntiles = ntiles;
+    g.cpad = cpad;
+    g.tpb = lay.tpb;
+    g.twid = reinterpret_cast<const float2 *>(ws + lay.fwd.twid);
+    g.part = reinterpret_cast<float *>(ws + lay.part_gh);
+    if (p.fir_mode != FIR_FFT) {  // the direct path's prepare leaves no twiddles
+        g.twid = reinterpret_cast<const float2 *>(ws + lay.twid);
+        if ((e = launch_twiddles(reinterpret_cast<float2 *>(ws + lay.twid), reinterpret_cast<double2 *>(ws + lay.tw64),
+                                 st)) != hipSuccess)
+            return e;
+    }
+    hipLaunchKernelGGL(fir_gh_part_kernel, dim3((unsigned)(npairs * lay.ntg), (unsigned)lay.nlag), dim3(WG), 0, st,
+                       g);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    float *gH = p.firs.n == 1 ? bp.gfir.ptr[0] : reinterpret_cast<float *>(ws + lay.gH);
+    hipLaunchKernelGGL(fir_gh_reduce_kernel, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, st,
+                       static_cast<const float *>(g.part), M, npairs * lay.ntg, gH);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (p.firs.n == 1) return hipSuccess;
+    // several FIR stages: chain rule through the tap convolution
+    double *o0 = reinterpret_cast<double *>(ws + lay.obuf), *o1 = o0 + M;
+    for (int i = 0; i < p.firs.n; ++i) {
+        if (!bp.gfir.ptr[i]) continue;
+        const double *cur = nullptr;
+        int32_t nc = 0;
+        for (int j = 0; j < p.firs.n; ++j) {
+            if (j == i) continue;
+            double *dst = (cur == o0) ? o1 : o0;
+            const int32_t nn = cur ? nc + p.firs.len[j] - 1 : p.firs.len[j];
+            hipLaunchKernelGGL(conv_f64_kernel, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, st, cur, nc,
+                               p.firs.ptr[j], p.firs.len[j], dst);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+            cur = dst;
+            nc = nn;
+        }
+        const int32_t Mi = p.firs.len[i];
+        hipLaunchKernelGGL(stage_tap_grad_kernel, dim3((unsigned)((Mi + 255) / 256)), dim3(256), 0, st, cur, nc,
+                           static_cast<const float *>(gH), Mi, bp.gfir.ptr[i]);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+}  // namespace tfx

@@ -1,0 +1,525 @@
+// tfx_device.h -- device building blocks shared by the forward (tfx_chain.hip)
+// and adjoint (tfx_backward.hip) kernels: look-back records, DPP moves, the
+// 4096-point FFT, and the chunk-carry engine of the linear-recurrence scan.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "tfx_internal.h"
+
+namespace tfx {
+
+// ------------------------------------------------------------------ records
+// Look-back records.  Every (channel, tile, section) owns 4 64-bit words: the
+// tile aggregate (2 floats) and the inclusive prefix (2 floats), each word
+// (epoch << 32) | float bits, written and read with relaxed agent-scope
+// atomics: every word validates itself, so no acquire/release fence is
+// needed.  (Each XCD of the chip has its own L2, and an agent-scope fence
+// writes back or invalidates the whole L2; fences in a spin loop would thrash
+// it for every tile on the XCD.)  The cross-tile values are fp32 even for
+// sections carried in fp64 inside the tile: across tiles the state is damped
+// by PhiT = A^3072, so rounding there accumulates over a few tiles only.  The
+// epoch advances once per launch (a one-thread kernel behind every run), so a
+// run never clears the words the previous run left and needs no memset.
+constexpr uint32_t EPOCH_MASK = 0x3FFFFFFFu;
+constexpr int64_t SPIN_MAX = int64_t(1) << 22;
+constexpr int REC_WORDS = 4;
+// header words of a workspace
+enum { HDR_ERROR = 1, HDR_EPOCH = 2 };
+
+__device__ __forceinline__ uint64_t ld_word(const uint64_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_word(uint64_t *p, uint64_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint32_t load_epoch(const uint32_t *hdr, int word) {
+    return __hip_atomic_load(hdr + word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Lanes 0, 1 of a wave store the tagged pair (f0, f1) (wave-uniform) into
+// slot 0 (aggregate) or 1 (inclusive prefix) of record r.
+__device__ __forceinline__ void publish(uint64_t *recs, int64_t r, int slot, uint32_t epoch, float f0, float f1,
+                                       int lane) {
+    if (lane < 2)
+        st_word(&recs[r * REC_WORDS + slot * 2 + lane],
+                ((uint64_t)epoch << 32) | (uint32_t)__float_as_uint(lane == 0 ? f0 : f1));
+}
+
+// Decodes the 4 words w of a record.  Returns 2 when the inclusive prefix is
+// out (f0, f1 = prefix), 1 when only the aggregate is (f0, f1 = aggregate),
+// else 0.
+__device__ __forceinline__ int decode_record(const uint64_t (&w)[4], uint32_t epoch, float &f0, float &f1) {
+    const uint64_t e = epoch;
+    const bool inc = (w[2] >> 32) == e && (w[3] >> 32) == e;
+    const bool agg = (w[0] >> 32) == e && (w[1] >> 32) == e;
+    f0 = __uint_as_float((uint32_t)(inc ? w[2] : w[0]));
+    f1 = __uint_as_float((uint32_t)(inc ? w[3] : w[1]));
+    return inc ? 2 : (agg ? 1 : 0);
+}
+
+// ---------------------------------------------------------------- lane moves
+// DPP lane move of a float / double (dpp_ctrl CTRL, rows ROWS written, lanes
+// reading outside their row get 0).
+template <int CTRL, int ROWS = 0xF>
+__device__ __forceinline__ float dpp(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROWS, 0xF, true));
+}
+template <int CTRL, int ROWS = 0xF>
+__device__ __forceinline__ double dpp(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xFFFFFFFF), CTRL, ROWS, 0xF, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROWS, 0xF, true);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+constexpr int DPP_ROW_SHR = 0x110;    // + n: lane - n within a row of 16
+constexpr int DPP_WAVE_SHR1 = 0x138;  // lane - 1 across the wave
+constexpr int DPP_ROW_BCAST15 = 0x142;
+constexpr int DPP_ROW_BCAST31 = 0x143;
+
+// Element (i, j) of a 2x2 row-major matrix, or of its transpose (TR).
+template <bool TR, typename CT>
+__device__ __forceinline__ CT m2(const CT *P, int i, int j) {
+    return TR ? P[2 * j + i] : P[2 * i + j];
+}
+// w += P t (P or its transpose)
+template <bool TR, typename CT>
+__device__ __forceinline__ void madd2(CT &w0, CT &w1, const CT *P, CT t0, CT t1) {
+    const CT n0 = m2<TR>(P, 0, 0) * t0 + m2<TR>(P, 0, 1) * t1 + w0;
+    const CT n1 = m2<TR>(P, 1, 0) * t0 + m2<TR>(P, 1, 1) * t1 + w1;
+    w0 = n0;
+    w1 = n1;
+}
+
+template <typename CT> struct Tab;
+template <> struct Tab<float> {
+    static __device__ __forceinline__ const float *fold(const SecTab &t, int k) { return t.fold[k]; }
+    static __device__ __forceinline__ const float *psi(const SecTab &t, int w) { return t.psi[w]; }
+    static __device__ __forceinline__ const float *lb(const SecTab &t, int j) { return t.lb[j]; }
+};
+template <> struct Tab<double> {
+    static __device__ __forceinline__ const double *fold(const SecTab &t, int k) { return t.fold_d[k]; }
+    static __device__ __forceinline__ const double *psi(const SecTab &t, int w) { return t.psi_d[w]; }
+    static __device__ __forceinline__ const double *lb(const SecTab &t, int j) { return t.lb_d[j]; }
+};
+
+// ------------------------------------------------------------------ staging
+// LDS layout of lane chunks: 24 samples then 4 floats of padding, so a lane's
+// chunk starts 112 bytes after its neighbour's and 16-byte reads of 16 lanes
+// hit distinct banks.
+constexpr int CSTRIDE = L + 4;
+constexpr int STG_FLOATS = GL * CSTRIDE;
+__device__ __forceinline__ int cphys(int i) { return (i / L) * CSTRIDE + (i % L); }
+
+__device__ __forceinline__ void load_chunk(const float *stg, int gl, float (&v)[L]) {
+#pragma unroll
+    for (int q = 0; q < L / 4; ++q) {
+        const float4 t4 = *reinterpret_cast<const float4 *>(&stg[gl * CSTRIDE + 4 * q]);
+        v[4 * q + 0] = t4.x;
+        v[4 * q + 1] = t4.y;
+        v[4 * q + 2] = t4.z;
+        v[4 * q + 3] = t4.w;
+    }
+}
+__device__ __forceinline__ void store_chunk(float *stg, int gl, const float (&v)[L]) {
+#pragma unroll
+    for (int q = 0; q < L / 4; ++q)
+        *reinterpret_cast<float4 *>(&stg[gl * CSTRIDE + 4 * q]) =
+            make_float4(v[4 * q + 0], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]);
+}
+
+// One group (GL lanes) stages T samples src[0..rem) (zeros past rem) into stg
+// in the chunk layout.  vec: src is 16-byte aligned.
+__device__ __forceinline__ void stage_tile(float *stg, const float *src, int64_t rem, bool valid, bool vec, int gl) {
+    if (vec && rem >= T) {
+        float4 t4[T / (4 * GL)];
+#pragma unroll
+        for (int k = 0; k < T / (4 * GL); ++k)
+            t4[k] = valid ? reinterpret_cast<const float4 *>(src)[gl + GL * k] : make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+        for (int k = 0; k < T / (4 * GL); ++k) *reinterpret_cast<float4 *>(&stg[cphys(4 * (gl + GL * k))]) = t4[k];
+    } else {  // ragged last tile or unaligned rows
+#pragma unroll 4
+        for (int k = 0; k < T / GL; ++k) {
+            const int i = gl + GL * k;
+            stg[cphys(i)] = (valid && i < rem) ? src[i] : 0.f;
+        }
+    }
+}
+
+// One group writes its staged tile (chunk layout) to dst[0..rem).
+__device__ __forceinline__ void store_tile(float *dst, const float *stg, int64_t rem, bool vec, int gl) {
+    if (vec && rem >= T) {
+#pragma unroll
+        for (int k = 0; k < T / (4 * GL); ++k) {
+            const int f = gl + GL * k;
+            reinterpret_cast<float4 *>(dst)[f] = *reinterpret_cast<const float4 *>(&stg[cphys(4 * f)]);
+        }
+    } else {
+#pragma unroll 4
+        for (int k = 0; k < T / GL; ++k) {
+            const int i = gl + GL * k;
+            if (i < rem) dst[i] = stg[cphys(i)];
+        }
+    }
+}
+
+// --------------------------------------------------------------------- FFT
+// 16-point DFT constants: cos / sin of 2 pi m / 16, m = 0..9.
+constexpr float c16[10] = {1.0f, 0.92387953251128674f, 0.70710678118654752f, 0.38268343236508978f, 0.0f,
+                           -0.38268343236508978f, -0.70710678118654752f, -0.92387953251128674f, -1.0f,
+                           -0.92387953251128674f};
+constexpr float s16[10] = {0.0f, 0.38268343236508978f, 0.70710678118654752f, 0.92387953251128674f, 1.0f,
+                           0.92387953251128674f, 0.70710678118654752f, 0.38268343236508978f, 0.0f,
+                           -0.38268343236508978f};
+
+// X_k = sum_n a_n w^{nk}, w = SIGN * i
+template <int SIGN>
+__device__ __forceinline__ void dft4(float &r0, float &i0, float &r1, float &i1, float &r2, float &i2, float &r3,
+                                     float &i3) {
+    const float sr02 = r0 + r2, si02 = i0 + i2, dr02 = r0 - r2, di02 = i0 - i2;
+    const float sr13 = r1 + r3, si13 = i1 + i3, dr13 = r1 - r3, di13 = i1 - i3;
+    const float wr = SIGN < 0 ? di13 : -di13;
+    const float wi = SIGN < 0 ? -dr13 : dr13;
+    r0 = sr02 + sr13;
+    i0 = si02 + si13;
+    r1 = dr02 + wr;
+    i1 = di02 + wi;
+    r2 = sr02 - sr13;
+    i2 = si02 - si13;
+    r3 = dr02 - wr;
+    i3 = di02 - wi;
+}
+
+// In-register 16-point DFT, X_k = sum_n v_n e^{SIGN 2 pi i n k / 16}, as a
+// 4 x 4 decomposition (n = 4 n1 + n2, k = k1 + 4 k2).
+template <int SIGN>
+__device__ __forceinline__ void dft16(float (&zr)[16], float (&zi)[16]) {
+#pragma unroll
+    for (int n2 = 0; n2 < 4; ++n2)
+        dft4<SIGN>(zr[n2], zi[n2], zr[4 + n2], zi[4 + n2], zr[8 + n2], zi[8 + n2], zr[12 + n2], zi[12 + n2]);
+#pragma unroll
+    for (int k1 = 1; k1 < 4; ++k1)
+#pragma unroll
+        for (int n2 = 1; n2 < 4; ++n2) {
+            const int m = n2 * k1;
+            const float c = c16[m], s = SIGN < 0 ? -s16[m] : s16[m];
+            const float r = zr[4 * k1 + n2], i = zi[4 * k1 + n2];
+            zr[4 * k1 + n2] = r * c - i * s;
+            zi[4 * k1 + n2] = r * s + i * c;
+        }
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1)
+        dft4<SIGN>(zr[4 * k1], zi[4 * k1], zr[4 * k1 + 1], zi[4 * k1 + 1], zr[4 * k1 + 2], zi[4 * k1 + 2],
+                   zr[4 * k1 + 3], zi[4 * k1 + 3]);
+    float tr[16], ti[16];
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1)
+#pragma unroll
+        for (int k2 = 0; k2 < 4; ++k2) {
+            tr[k1 + 4 * k2] = zr[4 * k1 + k2];
+            ti[k1 + 4 * k2] = zi[4 * k1 + k2];
+        }
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        zr[k] = tr[k];
+        zi[k] = ti[k];
+    }
+}
+
+// (r, i) *= w, or *= conj(w) (CONJ)
+template <bool CONJ>
+__device__ __forceinline__ void cmul_tw(float &r, float &i, float2 w) {
+    const float ws = CONJ ? -w.y : w.y;
+    const float nr = r * w.x - i * ws;
+    const float ni = r * ws + i * w.x;
+    r = nr;
+    i = ni;
+}
+
+// Swizzled LDS addresses of the two FFT exchanges: bijections onto [0, 4096),
+// bank-conflict-free for the lane orders used (checked on the CPU).
+__device__ __forceinline__ int ex1(int k1, int b, int c) { return 256 * k1 + 16 * ((b + k1) & 15) + c; }
+__device__ __forceinline__ int ex2(int k1, int k2, int c) { return 256 * k1 + 16 * ((k2 + k1) & 15) + (c ^ k1); }
+
+// Forward 4096-point DFT (e^{-2 pi i n k / 4096}) of the values held by the
+// 256 lanes of a workgroup.  In: lane t holds z[256 a + t], a = 0..15.  Out:
+// lane t holds Z[t + 256 k3], k3 = 0..15.  Three radix-16 passes with two LDS
+// exchanges through lds[0 .. 8192) floats.  Ends with the data in registers
+// and every lane past its last LDS read (callers may reuse lds after a
+// barrier).
+__device__ __forceinline__ void fft4096_forward(float (&zr)[16], float (&zi)[16], float *lds, const float2 *twid,
+                                                int tid) {
+    float *Lr = lds, *Li = lds + NFFT;
+    dft16<-1>(zr, zi);
+#pragma unroll
+    for (int k1 = 1; k1 < 16; ++k1) cmul_tw<false>(zr[k1], zi[k1], twid[(tid * k1) & (NFFT - 1)]);
+    {
+        const int b = tid >> 4, c = tid & 15;
+#pragma unroll
+        for (int k1 = 0; k1 < 16; ++k1) {
+            Lr[ex1(k1, b, c)] = zr[k1];
+            Li[ex1(k1, b, c)] = zi[k1];
+        }
+    }
+    __syncthreads();
+    {
+        const int k1 = tid >> 4, c = tid & 15;
+#pragma unroll
+        for (int b = 0; b < 16; ++b) {
+            zr[b] = Lr[ex1(k1, b, c)];
+            zi[b] = Li[ex1(k1, b, c)];
+        }
+        dft16<-1>(zr, zi);
+#pragma unroll
+        for (int k2 = 1; k2 < 16; ++k2) cmul_tw<false>(zr[k2], zi[k2], twid[(16 * c * k2) & (NFFT - 1)]);
+        __syncthreads();
+#pragma unroll
+        for (int k2 = 0; k2 < 16; ++k2) {
+            Lr[ex2(k1, k2, c)] = zr[k2];
+            Li[ex2(k1, k2, c)] = zi[k2];
+        }
+    }
+    __syncthreads();
+    {
+        const int k1 = tid & 15, k2 = tid >> 4;
+#pragma unroll
+        for (int c = 0; c < 16; ++c) {
+            zr[c] = Lr[ex2(k1, k2, c)];
+            zi[c] = Li[ex2(k1, k2, c)];
+        }
+        dft16<-1>(zr, zi);
+    }
+}
+
+// Inverse of fft4096_forward without the 1/4096 factor (e^{+2 pi i n k /
+// 4096}): in the forward's output layout, out in its input layout.  Begins
+// with a barrier before its first LDS write.
+__device__ __forceinline__ void fft4096_inverse(float (&zr)[16], float (&zi)[16], float *lds, const float2 *twid,
+                                                int tid) {
+    float *Lr = lds, *Li = lds + NFFT;
+    {
+        const int k1 = tid & 15, k2 = tid >> 4;
+        dft16<1>(zr, zi);
+#pragma unroll
+        for (int c = 1; c < 16; ++c) cmul_tw<true>(zr[c], zi[c], twid[(16 * c * k2) & (NFFT - 1)]);
+        __syncthreads();
+#pragma unroll
+        for (int c = 0; c < 16; ++c) {
+            Lr[ex2(k1, k2, c)] = zr[c];
+            Li[ex2(k1, k2, c)] = zi[c];
+        }
+    }
+    __syncthreads();
+    {
+        const int k1 = tid >> 4, c = tid & 15;
+#pragma unroll
+        for (int k2 = 0; k2 < 16; ++k2) {
+            zr[k2] = Lr[ex2(k1, k2, c)];
+            zi[k2] = Li[ex2(k1, k2, c)];
+        }
+        dft16<1>(zr, zi);
+#pragma unroll
+        for (int b = 0; b < 16; ++b) cmul_tw<true>(zr[b], zi[b], twid[((16 * b + c) * k1) & (NFFT - 1)]);
+        __syncthreads();
+#pragma unroll
+        for (int b = 0; b < 16; ++b) {
+            Lr[ex1(k1, b, c)] = zr[b];
+            Li[ex1(k1, b, c)] = zi[b];
+        }
+    }
+    __syncthreads();
+    {
+        const int b = tid >> 4, c = tid & 15;
+#pragma unroll
+        for (int k1 = 0; k1 < 16; ++k1) {
+            zr[k1] = Lr[ex1(k1, b, c)];
+            zi[k1] = Li[ex1(k1, b, c)];
+        }
+        dft16<1>(zr, zi);
+    }
+}
+
+// Loads the complex block z[m] = xa[base + m] + i xb[base + m], m = 256 q + tid
+// (zeros outside [0, N); xb may be null) into the forward FFT input layout.
+__device__ __forceinline__ void load_pair_block(float (&zr)[16], float (&zi)[16], const float *xa, const float *xb,
+                                                int64_t base, int64_t N, int64_t limit, int tid) {
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        const int64_t n = base + 256 * q + tid;
+        const bool in = n >= 0 && n < N && n < limit;
+        zr[q] = in ? xa[n] : 0.f;
+        zi[q] = (in && xb) ? xb[n] : 0.f;
+    }
+}
+
+// ------------------------------------------------------------ chunk carry
+// The recurrence  s_{k+1} = Phi s_k + z_k  over the chunks of a tile (Phi =
+// A^24 of one section, or its transpose for the adjoint), carried across
+// tiles by a decoupled look-back or started from a known tile prefix.
+
+struct CarryCtx {
+    int lane, gw, grp;
+    bool lookback;        // prefix by look-back (else `known`)
+    int64_t pos;          // tile position in processing order
+    uint64_t *recs;       // records of this channel/section: rec(q) = rec0 + q * rstride
+    int64_t rec0, rstride;
+    uint32_t epoch;
+    uint32_t *hdr;
+    double known0, known1;  // prefix when !lookback, or at pos == 0
+    float *prefix_out;      // optional: receives the tile prefix (2 floats)
+};
+
+// Decoupled look-back of one tile by one full wave.  Publishes the tile
+// aggregate (agg), then returns the state entering the tile.  Lane l watches
+// predecessor pos-1-l (a window of 64 tiles per step); a lane stops
+// re-reading its record once the aggregate or the prefix is out, so the spin
+// costs one 32-byte read per still-missing predecessor.
+template <typename CT, bool TR>
+__device__ void lookback(const SecTab &tb, const CarryCtx &cc, CT agg0, CT agg1, CT &P0, CT &P1) {
+    const int lane = cc.lane;
+    publish(cc.recs, cc.rec0 + cc.pos * cc.rstride, 0, cc.epoch, (float)agg0, (float)agg1, lane);
+    CT acc0 = 0, acc1 = 0;
+    CT M00 = 1, M01 = 0, M10 = 0, M11 = 1;  // (PhiT)^(64 * windows consumed)
+    int64_t base = cc.pos - 1;
+    while (true) {
+        const int64_t q = base - lane;
+        int st = q < 0 ? 3 : 0;  // 0 missing, 1 aggregate, 2 prefix, 3 before the first tile
+        float r0 = 0.f, r1 = 0.f;
+        int64_t spins = 0;
+        while (true) {
+            if (st == 0) {
+                const uint64_t *p = cc.recs + (cc.rec0 + q * cc.rstride) * REC_WORDS;
+                uint64_t w[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) w[i] = ld_word(p + i);
+                st = decode_record(w, cc.epoch, r0, r1);
+            }
+            const unsigned long long fm = __ballot(st == 2);
+            const int first = fm ? (__ffsll(fm) - 1) : 63;
+            if (!__ballot(st == 0 && lane <= first)) break;
+            if (++spins > SPIN_MAX) {  // never expected: report and finish
+                atomicOr(&cc.hdr[HDR_ERROR], 1u);
+                break;
+            }
+            __builtin_amdgcn_s_sleep(4);
+        }
+        const unsigned long long fm = __ballot(st == 2);
+        const int first = fm ? (__ffsll(fm) - 1) : 64;
+        CT v0 = 0, v1 = 0;
+        if (lane <= first && (st == 1 || st == 2)) {
+            v0 = (CT)r0;
+            v1 = (CT)r1;
+        }
+        CT R0, R1;
+        if (first == 0) {
+            R0 = __shfl(v0, 0);
+            R1 = __shfl(v1, 0);
+        } else {
+            // lane 0 <- sum_l PhiT^l v_l
+#pragma unroll
+            for (int k = 0; k < 6; ++k) {
+                const int d = 1 << k;
+                const CT t0 = __shfl_down(v0, d), t1 = __shfl_down(v1, d);
+                if (lane + d < 64) madd2<TR>(v0, v1, Tab<CT>::lb(tb, k), t0, t1);
+            }
+            R0 = __shfl(v0, 0);
+            R1 = __shfl(v1, 0);
+        }
+        acc0 += M00 * R0 + M01 * R1;
+        acc1 += M10 * R0 + M11 * R1;
+        if (fm) break;
+        const CT *B = Tab<CT>::lb(tb, 6);  // PhiT^64
+        const CT n00 = M00 * m2<TR>(B, 0, 0) + M01 * m2<TR>(B, 1, 0);
+        const CT n01 = M00 * m2<TR>(B, 0, 1) + M01 * m2<TR>(B, 1, 1);
+        const CT n10 = M10 * m2<TR>(B, 0, 0) + M11 * m2<TR>(B, 1, 0);
+        const CT n11 = M10 * m2<TR>(B, 0, 1) + M11 * m2<TR>(B, 1, 1);
+        M00 = n00;
+        M01 = n01;
+        M10 = n10;
+        M11 = n11;
+        base -= 64;
+    }
+    P0 = acc0;
+    P1 = acc1;
+}
+
+// Given the lane's chunk state z (the chunk's final state from a zero
+// entering state), returns the state entering the lane's chunk.  Inclusive
+// scan over the wave's 64 chunks (DPP row shifts within rows of 16 lanes,
+// then row broadcasts weighted by the lane's own power of Phi), the group's
+// wave aggregates combined through LDS with Psi = Phi^64, the tile prefix by
+// look-back (publishing the inclusive prefix) or from `known`, then folded
+// into every chunk with the table of Phi^k.  Contains two workgroup
+// barriers; s_agg / s_pre slot `buf` must not be in use by a neighbouring
+// call (callers alternate two slots).
+template <typename CT, bool TR>
+__device__ void carry(const SecTab &tb, const CarryCtx &cc, float z0, float z1, float &e0, float &e1,
+                      double (*s_agg)[GWAVES][2], double (*s_pre)[2], int buf) {
+    const int lane = cc.lane;
+    CT w0 = (CT)z0, w1 = (CT)z1;
+    {
+        CT t0 = dpp<DPP_ROW_SHR + 1>(w0), t1 = dpp<DPP_ROW_SHR + 1>(w1);
+        madd2<TR>(w0, w1, Tab<CT>::fold(tb, 1), t0, t1);
+        t0 = dpp<DPP_ROW_SHR + 2>(w0);
+        t1 = dpp<DPP_ROW_SHR + 2>(w1);
+        madd2<TR>(w0, w1, Tab<CT>::fold(tb, 2), t0, t1);
+        t0 = dpp<DPP_ROW_SHR + 4>(w0);
+        t1 = dpp<DPP_ROW_SHR + 4>(w1);
+        madd2<TR>(w0, w1, Tab<CT>::fold(tb, 4), t0, t1);
+        t0 = dpp<DPP_ROW_SHR + 8>(w0);
+        t1 = dpp<DPP_ROW_SHR + 8>(w1);
+        madd2<TR>(w0, w1, Tab<CT>::fold(tb, 8), t0, t1);
+        t0 = dpp<DPP_ROW_BCAST15, 0xA>(w0);  // rows 1, 3 take lane 15 of rows 0, 2
+        t1 = dpp<DPP_ROW_BCAST15, 0xA>(w1);
+        madd2<TR>(w0, w1, Tab<CT>::fold(tb, (lane & 15) + 1), t0, t1);
+        t0 = dpp<DPP_ROW_BCAST31, 0xC>(w0);  // rows 2, 3 take lane 31
+        t1 = dpp<DPP_ROW_BCAST31, 0xC>(w1);
+        madd2<TR>(w0, w1, Tab<CT>::fold(tb, (lane & 31) + 1), t0, t1);
+    }
+    if (lane == 63) {
+        s_agg[buf][cc.gw][0] = (double)w0;
+        s_agg[buf][cc.gw][1] = (double)w1;
+    }
+    __syncthreads();
+    // wave-entering states for a zero tile-entering state; E ends as the
+    // tile aggregate
+    const CT *Psi = Tab<CT>::psi(tb, 1);
+    CT E0 = 0, E1 = 0, ew0 = 0, ew1 = 0;
+#pragma unroll
+    for (int w = 0; w < GWAVES; ++w) {
+        if (w == cc.gw) {
+            ew0 = E0;
+            ew1 = E1;
+        }
+        CT g0 = (CT)s_agg[buf][w][0], g1 = (CT)s_agg[buf][w][1];
+        madd2<TR>(g0, g1, Psi, E0, E1);
+        E0 = g0;
+        E1 = g1;
+    }
+    if (cc.gw == 0) {
+        CT P0 = (CT)cc.known0, P1 = (CT)cc.known1;
+        if (cc.lookback) {
+            if (cc.pos > 0) lookback<CT, TR>(tb, cc, E0, E1, P0, P1);
+            CT i0 = E0, i1 = E1;
+            madd2<TR>(i0, i1, Tab<CT>::lb(tb, 0), P0, P1);  // PhiT P + E
+            publish(cc.recs, cc.rec0 + cc.pos * cc.rstride, 1, cc.epoch, (float)i0, (float)i1, lane);
+        }
+        if (lane == 0) {
+            s_pre[buf][0] = (double)P0;
+            s_pre[buf][1] = (double)P1;
+            if (cc.prefix_out) {
+                cc.prefix_out[0] = (float)P0;
+                cc.prefix_out[1] = (float)P1;
+            }
+        }
+    }
+    __syncthreads();
+    CT x0 = ew0, x1 = ew1;  // wave-entering state
+    madd2<TR>(x0, x1, Tab<CT>::psi(tb, cc.gw), (CT)s_pre[buf][0], (CT)s_pre[buf][1]);
+    CT s0 = dpp<DPP_WAVE_SHR1>(w0), s1 = dpp<DPP_WAVE_SHR1>(w1);  // lane 0 reads 0
+    madd2<TR>(s0, s1, Tab<CT>::fold(tb, lane), x0, x1);
+    e0 = (float)s0;
+    e1 = (float)s1;
+}
+
+}  // namespace tfx

@@ -26,13 +26,15 @@ constexpr int KBLK_MAX = 1024;  // taps staged per LDS pass
 // ---- overlap-save FFT FIR --------------------------------------------------------
 constexpr int NFFT = 4096;              // complex points, 16 x 16 x 16
 constexpr int FFT_DISCARD = NFFT - T;   // 1024 leading outputs dropped per block
-constexpr int FFT_MAX_TAPS = FFT_DISCARD + 1;
+constexpr int FFT_PART = FFT_DISCARD + 1;  // taps per partition of a long filter
+__host__ __device__ constexpr int fft_parts(int M) { return (M + FFT_PART - 1) / FFT_PART; }
 
 constexpr int MAX_STAGES = 64;
 constexpr int MAX_SECTIONS = 256;
 constexpr int MAX_TAPS = 65536;
+constexpr int BWD_MAX_SECTIONS = 16;  // adjoint: chunk states of every section stay in LDS
 
-enum FirMode { FIR_NONE = 0, FIR_DIRECT = 1, FIR_FFT = 2 };
+enum FirMode { FIR_NONE = 0, FIR_DIRECT = 1, FIR_FFT = 2, FIR_TOEPLITZ = 3 };
 
 // Per-section tables built on the device from the fp32 coefficients (in FP64,
 // then rounded).  2x2 matrices are row-major {m00, m01, m10, m11}.
@@ -64,6 +66,7 @@ struct ChainPlan {
     int64_t C, N, ldx, ldy;
     int32_t S;        // total sections
     int32_t fir_mode; // FirMode of the merged FIR
+    int32_t cmp;      // tfx_compute of the FIR contraction (Toeplitz path)
     StageList sos;    // SOS stages in order (device pointers)
     StageList firs;   // FIR stages in order (merged when more than one)
     const float *state_in;
@@ -76,7 +79,7 @@ struct ChainPlan {
 
 // Workspace layout of a chain/SOS/FIR call.
 struct WsLayout {
-    size_t hdr, tab, recs, taps, merge, twid, hspec, tw64, total;
+    size_t hdr, tab, recs, taps, merge, twid, hspec, tw64, ttab, total;
     int64_t ntiles, cpad;
 };
 WsLayout ws_layout(int64_t C, int64_t N, int32_t S, int32_t M_merged, int32_t n_fir, int32_t fir_mode);
@@ -85,5 +88,46 @@ WsLayout ws_layout(int64_t C, int64_t N, int32_t S, int32_t M_merged, int32_t n_
 hipError_t launch_prepare(const ChainPlan &p);
 // The filtering itself; may be repeated on a prepared workspace.
 hipError_t launch_run(const ChainPlan &p);
+
+// Merged tap count of the FIR stages (each extra stage adds len - 1).
+int32_t merged_taps(const StageList &f);
+// The kernels of the prepare step into the workspace described by lay.
+hipError_t launch_tables(const ChainPlan &p, const WsLayout &lay, const float *h, int32_t M);
+// FIR part of a prepared chain alone over (in -> out): convolution with the
+// merged taps, or correlation with them (the FIR adjoint) when correlate.
+hipError_t launch_fir_pass(const ChainPlan &p, const WsLayout &lay, const float *in, int64_t ldin, float *out,
+                           int64_t ldout, bool correlate);
+
+// ---- matrix-core block-Toeplitz FIR (tfx_toeplitz.hip) --------------------------
+int32_t toeplitz_lags(int32_t M);
+size_t toeplitz_table_bytes(int32_t M, int32_t cmp);
+hipError_t launch_toeplitz_prepare(const float *h, int32_t M, int32_t cmp, void *tab, hipStream_t st);
+hipError_t launch_toeplitz(const float *x, float *y, int64_t C, int64_t N, int64_t ldx, int64_t ldy, int32_t M,
+                           int32_t cmp, const void *tab, hipStream_t st);
+
+// ---- adjoint -------------------------------------------------------------------
+struct GradList {
+    float *ptr[MAX_STAGES];
+    int32_t len[MAX_STAGES];
+    int32_t n;
+};
+
+struct BwdPlan {
+    ChainPlan fwd;      // stages, x (ldx), C, N, ckpt, ws, stream of the forward
+    const float *gy;    // gradient of the chain output
+    float *gx;          // gradient of the chain input
+    int64_t ldg, ldgx;
+    GradList gsos;      // per SOS stage (ptr may be null), in stage order
+    GradList gfir;      // per FIR stage (ptr may be null), in stage order
+};
+
+// Backward workspace: the forward layout, then the adjoint's buffers.
+struct BwdLayout {
+    WsLayout fwd;
+    size_t part_sos, fbuf, gfbuf, part_gh, gH, obuf, twid, tw64, total;
+    int64_t tpb, ntg, nlag;
+};
+BwdLayout bwd_layout(int64_t C, int64_t N, int32_t S, int32_t M_merged, int32_t n_fir, int32_t fir_mode);
+hipError_t launch_backward(const BwdPlan &p);
 
 }  // namespace tfx

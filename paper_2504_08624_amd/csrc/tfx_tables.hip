@@ -136,14 +136,19 @@ __global__ void fft_twiddle_kernel(float2 *twid, double2 *tw64) {
     tw64[k] = make_double2(c, s);
 }
 
-// hspec[k] = (sum_j h[j] e^{-2 pi i j k / 4096}) / 4096, the direct DFT of the
-// zero-padded taps in FP64 (exact twiddle indices j k mod 4096).  One block
-// of 256 lanes per 16 bins: lane (kk, jj) sums taps j = jj (mod 16) of bin
-// 16 blk + kk, then the 16 partial sums are added in a fixed order.
-__global__ void fft_spectrum_kernel(const float *h, int32_t M, const double2 *tw64, float2 *hspec) {
+// hspec[p][k] = (sum_j h[1025 p + j] e^{-2 pi i j k / 4096}) / 4096, the
+// direct DFT of tap partition p (j < 1025, zero-padded) in FP64 (exact
+// twiddle indices j k mod 4096).  Block (blk, p) of 256 lanes covers 16 bins:
+// lane (kk, jj) sums taps j = jj (mod 16) of bin 16 blk + kk, then the 16
+// partial sums are added in a fixed order.
+__global__ void fft_spectrum_kernel(const float *h_all, int32_t M_all, const double2 *tw64, float2 *hspec_all) {
     __shared__ double pr[16][17], pi[16][17];
     const int kk = threadIdx.x >> 4, jj = threadIdx.x & 15;
     const int k = blockIdx.x * 16 + kk;
+    const float *h = h_all + (int64_t)blockIdx.y * FFT_PART;
+    const int rest = M_all - (int)blockIdx.y * FFT_PART;
+    const int M = rest < FFT_PART ? rest : FFT_PART;
+    float2 *hspec = hspec_all + (int64_t)blockIdx.y * NFFT;
     double hr = 0.0, hi = 0.0;
     for (int j = jj; j < M; j += 16) {
         const double2 w = tw64[(j * k) & (NFFT - 1)];
@@ -185,7 +190,7 @@ hipError_t launch_tables(const ChainPlan &p, const WsLayout &lay, const float *h
         hipLaunchKernelGGL(fft_twiddle_kernel, dim3(NFFT / 256), dim3(256), 0, p.stream,
                            reinterpret_cast<float2 *>(ws + lay.twid), tw64);
         if ((e = hipGetLastError()) != hipSuccess) return e;
-        hipLaunchKernelGGL(fft_spectrum_kernel, dim3(NFFT / 16), dim3(256), 0, p.stream, h, M, tw64,
+        hipLaunchKernelGGL(fft_spectrum_kernel, dim3(NFFT / 16, fft_parts(M)), dim3(256), 0, p.stream, h, M, tw64,
                            reinterpret_cast<float2 *>(ws + lay.hspec));
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
@@ -207,7 +212,13 @@ hipError_t launch_tables(const ChainPlan &p, const WsLayout &lay, const float *h
     return hipSuccess;
 }
 
+hipError_t launch_twiddles(float2 *twid, double2 *tw64, hipStream_t st) {
+    hipLaunchKernelGGL(fft_twiddle_kernel, dim3(NFFT / 256), dim3(256), 0, st, twid, tw64);
+    return hipGetLastError();
+}
+
 hipError_t launch_state_passthrough(const float *in, float *out, int64_t n, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(state_passthrough_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, in, out, n);
     return hipGetLastError();
 }

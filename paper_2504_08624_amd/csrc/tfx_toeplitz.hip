@@ -1,0 +1,240 @@
+// tfx_toeplitz.hip -- FIR convolution as a block-Toeplitz matrix product on
+// the gfx950 matrix cores (bf16 or fp16 operands, fp32 accumulation, and a
+// split-bf16 mode with three products for close-to-fp32 accuracy).
+//
+// The signal of a channel is cut into frames of P = 32 samples, Y[b][i] =
+// y[32 b + i].  With q the frame lag and m the sample within a frame,
+//     y[32 b + i] = sum_{q, m} x[32 (b - q) + m] h[32 q + i - m]
+// (h = 0 outside [0, M)); for each i the pairs (q, m), q < Q = ceil((M-1)/32)
+// + 1, m < 32, meet every tap exactly once.  So Y = A B with
+//     A[b][(q, m)] = x[32 (b - q) + m]     (Toeplitz in frames: depends on b - q)
+//     B[(q, m)][i] = h[32 q + i - m]       (Toeplitz taps, the same for every channel)
+// a (frames x 32Q) by (32Q x 32) product: 2 M flops per output sample plus
+// under 1 % for the triangle of zero taps.  One v_mfma_f32_32x32x16 step
+// covers 32 frames x 32 outputs x 16 values of (q, m): a fixed q and
+// m in [16 hh, 16 hh + 16).
+//
+// Operand flow.  B is the same for every tile: the prepare step writes it
+// once, already in the matrix core's per-lane operand layout (16 bytes per
+// lane per step), and every wave streams it from L2.  A is a sliding window
+// over frames: a workgroup stages the frames it needs, converted to the
+// operand precision, into LDS once per block of lags, and each wave reads
+// its fragments from there.  A wave holds FB = 4 accumulator tiles (32 frames
+// each) and reuses each B fragment for all four.
+#include <hip/hip_runtime.h>
+
+#include "tfx_internal.h"
+
+namespace tfx {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+constexpr int TP = 32;                      // frame length = output columns
+constexpr int TFB = 4;                      // accumulator tiles per wave
+constexpr int TWAVES = 4;                   // waves per workgroup
+constexpr int TFRAMES = TFB * 32 * TWAVES;  // frames per workgroup tile (512)
+constexpr int TQC = 192;                    // lags per LDS stage
+constexpr int TROW = TP + 8;                // LDS row: 32 operands + 8 of padding (2-byte units)
+constexpr int TROWS = TFRAMES + TQC;        // staged frames per stage
+
+// Compute modes handled here (tfx_compute values).
+enum { TZ_BF16 = 1, TZ_F16 = 2, TZ_BF16X3 = 3 };
+
+template <int MODE> struct Op;
+template <> struct Op<TZ_BF16> {
+    typedef __bf16 T;
+    typedef bf16x8 V;
+    static __device__ __forceinline__ f32x16 mma(V a, V b, f32x16 c) {
+        return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+    }
+};
+template <> struct Op<TZ_F16> {
+    typedef _Float16 T;
+    typedef f16x8 V;
+    static __device__ __forceinline__ f32x16 mma(V a, V b, f32x16 c) {
+        return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
+    }
+};
+template <> struct Op<TZ_BF16X3> : Op<TZ_BF16> {};
+
+// B operand table: step s = 2 q + hh, lane l, element v holds
+// h[32 q + (l % 32) - 16 hh - 8 (l / 32) - v]  (0 outside [0, M)),
+// as hi (and, split mode, lo = h - hi) parts.  Layout [nsteps][64][8].
+template <int MODE>
+__global__ void toeplitz_btab_kernel(const float *h, int32_t M, int32_t nsteps, typename Op<MODE>::T *hi,
+                                     typename Op<MODE>::T *lo) {
+    typedef typename Op<MODE>::T T;
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (int64_t)nsteps * 64 * 8) return;
+    const int v = (int)(e & 7), l = (int)((e >> 3) & 63);
+    const int s = (int)(e >> 9);
+    const int q = s >> 1, hh = s & 1;
+    const int k = 32 * q + (l & 31) - 16 * hh - 8 * (l >> 5) - v;
+    const float t = (k >= 0 && k < M) ? h[k] : 0.f;
+    const T th = (T)t;
+    hi[e] = th;
+    if (MODE == TZ_BF16X3) lo[e] = (T)(t - (float)th);
+}
+
+struct TzArgs {
+    const float *x;
+    float *y;
+    int64_t C, N, ldx, ldy;
+    int32_t Q;            // frame lags
+    int64_t nft;          // frame tiles per channel
+    const void *bhi, *blo;
+    int32_t vec;          // x rows 16-byte aligned
+};
+
+// One workgroup: 512 consecutive frames (16384 outputs) of one channel.
+template <int MODE>
+__global__ __launch_bounds__(64 * TWAVES) void toeplitz_kernel(TzArgs a) {
+    typedef Op<MODE> O;
+    typedef typename O::T T;
+    typedef typename O::V V;
+    typedef T T4 __attribute__((ext_vector_type(4)));
+    constexpr int NA = MODE == TZ_BF16X3 ? 2 : 1;  // staged A parts (hi, lo)
+    __shared__ __align__(16) T lds[NA][TROWS * TROW];
+
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int64_t ch = blockIdx.x / a.nft;
+    const int64_t b0 = (blockIdx.x % a.nft) * TFRAMES;  // first frame of the tile
+    const float *xc = a.x + ch * a.ldx;
+    const V *bhi = static_cast<const V *>(a.bhi);
+    const V *blo = static_cast<const V *>(a.blo);
+
+    f32x16 acc[TFB];
+#pragma unroll
+    for (int j = 0; j < TFB; ++j)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[j][r] = 0.f;
+
+    const int r32 = lane & 31, kh = lane >> 5;
+    for (int q0 = 0; q0 < a.Q; q0 += TQC) {
+        const int q1 = min(a.Q, q0 + TQC);
+        // stage frames fbase .. fbase + TFRAMES + (q1 - q0) - 2
+        const int64_t fbase = b0 - (q1 - 1);
+        const int nrows = TFRAMES + (q1 - q0) - 1;
+        __syncthreads();
+        for (int e = tid; e < nrows * (TP / 4); e += 64 * TWAVES) {
+            const int row = e / (TP / 4), c4 = e % (TP / 4);
+            const int64_t n = (fbase + row) * TP + 4 * c4;
+            float v4[4];
+            if (a.vec && n >= 0 && n + 3 < a.N) {
+                const float4 t = *reinterpret_cast<const float4 *>(xc + n);
+                v4[0] = t.x;
+                v4[1] = t.y;
+                v4[2] = t.z;
+                v4[3] = t.w;
+            } else {
+#pragma unroll
+                for (int u = 0; u < 4; ++u) v4[u] = (n + u >= 0 && n + u < a.N) ? xc[n + u] : 0.f;
+            }
+            T4 hi4, lo4;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                hi4[u] = (T)v4[u];
+                lo4[u] = (T)(v4[u] - (float)hi4[u]);
+            }
+            *reinterpret_cast<T4 *>(&lds[0][row * TROW + 4 * c4]) = hi4;
+            if (MODE == TZ_BF16X3) *reinterpret_cast<T4 *>(&lds[NA - 1][row * TROW + 4 * c4]) = lo4;
+        }
+        __syncthreads();
+        for (int q = q0; q < q1; ++q) {
+#pragma unroll
+            for (int hh = 0; hh < 2; ++hh) {
+                const int64_t s = 2 * (int64_t)q + hh;
+                const V bh = bhi[s * 64 + lane];
+                V bl;
+                if (MODE == TZ_BF16X3) bl = blo[s * 64 + lane];
+#pragma unroll
+                for (int j = 0; j < TFB; ++j) {
+                    // frame b = b0 + 32 (w * TFB + j) + r32; staged row b - q - fbase
+                    const int row = 32 * (w * TFB + j) + r32 + (q1 - 1 - q);
+                    const int off = row * TROW + 16 * hh + 8 * kh;
+                    const V ah = *reinterpret_cast<const V *>(&lds[0][off]);
+                    acc[j] = O::mma(ah, bh, acc[j]);
+                    if (MODE == TZ_BF16X3) {
+                        const V al = *reinterpret_cast<const V *>(&lds[NA - 1][off]);
+                        acc[j] = O::mma(ah, bl, acc[j]);
+                        acc[j] = O::mma(al, bh, acc[j]);
+                    }
+                }
+            }
+        }
+    }
+    // accumulator (row i, column c): lane c + 32 (i / 4 % 2), register
+    // 4 (i / 8) + i % 4; output sample 32 (frame) + column
+    float *yc = a.y + ch * a.ldy;
+#pragma unroll
+    for (int j = 0; j < TFB; ++j) {
+        const int64_t fb = b0 + 32 * (w * TFB + j);
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int i = 8 * (r >> 2) + 4 * kh + (r & 3);
+            const int64_t n = (fb + i) * TP + r32;
+            if (n < a.N) yc[n] = acc[j][r];
+        }
+    }
+}
+
+// ------------------------------------------------------------------- host
+
+int32_t toeplitz_lags(int32_t M) { return (M - 1 + TP - 1) / TP + 1; }
+
+size_t toeplitz_table_bytes(int32_t M, int32_t cmp) {
+    const size_t steps = 2 * (size_t)toeplitz_lags(M);
+    return steps * 64 * 8 * 2 * (cmp == TZ_BF16X3 ? 2 : 1);
+}
+
+hipError_t launch_toeplitz_prepare(const float *h, int32_t M, int32_t cmp, void *tab, hipStream_t st) {
+    const int32_t nsteps = 2 * toeplitz_lags(M);
+    const int64_t n = (int64_t)nsteps * 64 * 8;
+    const dim3 grid((unsigned)((n + 255) / 256)), block(256);
+    char *t = static_cast<char *>(tab);
+    switch (cmp) {
+        case TZ_BF16:
+            hipLaunchKernelGGL(toeplitz_btab_kernel<TZ_BF16>, grid, block, 0, st, h, M, nsteps,
+                               reinterpret_cast<__bf16 *>(t), nullptr);
+            break;
+        case TZ_F16:
+            hipLaunchKernelGGL(toeplitz_btab_kernel<TZ_F16>, grid, block, 0, st, h, M, nsteps,
+                               reinterpret_cast<_Float16 *>(t), nullptr);
+            break;
+        default:
+            hipLaunchKernelGGL(toeplitz_btab_kernel<TZ_BF16X3>, grid, block, 0, st, h, M, nsteps,
+                               reinterpret_cast<__bf16 *>(t), reinterpret_cast<__bf16 *>(t + n * 2));
+            break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_toeplitz(const float *x, float *y, int64_t C, int64_t N, int64_t ldx, int64_t ldy, int32_t M,
+                           int32_t cmp, const void *tab, hipStream_t st) {
+    if (N == 0) return hipSuccess;
+    TzArgs a{};
+    a.x = x;
+    a.y = y;
+    a.C = C;
+    a.N = N;
+    a.ldx = ldx;
+    a.ldy = ldy;
+    a.Q = toeplitz_lags(M);
+    const int64_t frames = (N + TP - 1) / TP;
+    a.nft = (frames + TFRAMES - 1) / TFRAMES;
+    const int64_t n = 2 * (int64_t)a.Q * 64 * 8;
+    a.bhi = tab;
+    a.blo = static_cast<const char *>(tab) + n * 2;
+    a.vec = (reinterpret_cast<uintptr_t>(x) % 16 == 0 && ldx % 4 == 0) ? 1 : 0;
+    const dim3 grid((unsigned)(C * a.nft)), block(64 * TWAVES);
+    switch (cmp) {
+        case TZ_BF16: hipLaunchKernelGGL(toeplitz_kernel<TZ_BF16>, grid, block, 0, st, a); break;
+        case TZ_F16: hipLaunchKernelGGL(toeplitz_kernel<TZ_F16>, grid, block, 0, st, a); break;
+        default: hipLaunchKernelGGL(toeplitz_kernel<TZ_BF16X3>, grid, block, 0, st, a); break;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace tfx

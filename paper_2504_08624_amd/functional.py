@@ -1,8 +1,13 @@
-"""Torch-facing entry points: fir, sos, chain.
+"""Torch-facing entry points: fir, sos, chain and their adjoints.
 
 PyTorch supplies device memory (``torch.empty``) and the current HIP stream;
 the filtering runs in libtfx.so through the C ABI (``lib.py``).  Inputs must
 be float32 HIP tensors shaped [N] or [C, N]; there is no CPU path.
+
+When autograd is recording and the signal or a coefficient tensor requires a
+gradient, the calls go through ``torch.autograd.Function`` wrappers whose
+backward runs the library's adjoint kernels (the forward keeps only the
+tile-boundary checkpoints of the IIR states, not per-sample signals).
 """
 from __future__ import annotations
 
@@ -57,8 +62,7 @@ def tile_length() -> int:
     return int(lib.load().tfx_sos_tile_length())
 
 
-def fir(x: torch.Tensor, h, compute: str = "f32", algo: str = "auto") -> torch.Tensor:
-    """y[c, n] = sum_k h[k] x[c, n-k] (causal, zero history, same length)."""
+def _fir_raw(x: torch.Tensor, h, compute: str = "f32", algo: str = "auto") -> torch.Tensor:
     x2, squeeze, ld = _signal(x)
     C, N = x2.shape
     h = _coef(h, x.device).reshape(-1)
@@ -71,13 +75,8 @@ def fir(x: torch.Tensor, h, compute: str = "f32", algo: str = "auto") -> torch.T
     return y[0] if squeeze else y
 
 
-def sos(x: torch.Tensor, sections, state_in=None, return_state: bool = False,
-        return_ckpt: bool = False):
-    """Cascade of second-order sections, rows [b0 b1 b2 a1 a2] (a0 == 1).
-
-    state_in: optional [C, S, 2] TDF-II registers.  Returns y, plus the final
-    state [C, S, 2] if ``return_state`` and the tile checkpoints
-    [C, ceil(N/T), S, 2] if ``return_ckpt``."""
+def _sos_raw(x: torch.Tensor, sections, state_in=None, return_state: bool = False,
+             return_ckpt: bool = False):
     x2, squeeze, ld = _signal(x)
     C, N = x2.shape
     co = _coef(sections, x.device).reshape(-1, 5)
@@ -120,10 +119,7 @@ def _stages(stages, device):
     return kept, desc
 
 
-def chain(x: torch.Tensor, stages, compute: str = "f32", return_ckpt: bool = False):
-    """Apply ("fir", taps) / ("sos", sections) stages left to right in one
-    fused launch (all FIR stages merged and applied first, all sections
-    concatenated behind them)."""
+def _chain_raw(x: torch.Tensor, stages, compute: str = "f32", return_ckpt: bool = False):
     x2, squeeze, ld = _signal(x)
     C, N = x2.shape
     kept, desc = _stages(stages, x.device)
@@ -142,3 +138,157 @@ def chain(x: torch.Tensor, stages, compute: str = "f32", return_ckpt: bool = Fal
     del kept
     y = y[0] if squeeze else y
     return (y, ck) if return_ckpt else y
+
+
+# ------------------------------------------------------------------ adjoint
+
+def fir_backward(x: torch.Tensor, gy: torch.Tensor, h, compute: str = "f32", algo: str = "auto",
+                 need_taps: bool = True):
+    """(dL/dx, dL/dh) of y = fir(x, h) given gy = dL/dy."""
+    x2, squeeze, ld = _signal(x)
+    g2, _, ldg = _signal(gy)
+    C, N = x2.shape
+    if tuple(g2.shape) != (C, N):
+        raise ValueError("gy must have the shape of x")
+    h = _coef(h, x.device).reshape(-1)
+    gx = torch.empty((C, N), dtype=torch.float32, device=x.device)
+    gh = torch.empty_like(h) if need_taps else None
+    nb = lib.size_out()
+    lib.call("tfx_fir_backward_workspace_size", C, N, h.numel(), lib.COMPUTE[compute], lib.FIR_ALGO[algo], nb)
+    ws, wsb = _workspace(nb.value, x.device)
+    lib.call("tfx_fir_backward", _ptr(x2), _ptr(g2), _ptr(gx), C, N, ld, ldg, max(N, 1), _ptr(h), h.numel(),
+             _ptr(gh), lib.COMPUTE[compute], lib.FIR_ALGO[algo], _ptr(ws), wsb, _stream(x.device))
+    return (gx[0] if squeeze else gx), gh
+
+
+def sos_backward(x: torch.Tensor, gy: torch.Tensor, sections, ckpt: torch.Tensor, need_coef: bool = True):
+    """(dL/dx, dL/dsections) of y = sos(x, sections, state_in) given gy and
+    the forward's checkpoints (``sos(..., return_ckpt=True)``)."""
+    x2, squeeze, ld = _signal(x)
+    g2, _, ldg = _signal(gy)
+    C, N = x2.shape
+    if tuple(g2.shape) != (C, N):
+        raise ValueError("gy must have the shape of x")
+    co = _coef(sections, x.device).reshape(-1, 5)
+    S = co.shape[0]
+    gx = torch.empty((C, N), dtype=torch.float32, device=x.device)
+    gs = torch.empty_like(co) if need_coef else None
+    ck = ckpt.contiguous() if ckpt is not None else None
+    nb = lib.size_out()
+    lib.call("tfx_sos_backward_workspace_size", C, N, S, nb)
+    ws, wsb = _workspace(nb.value, x.device)
+    lib.call("tfx_sos_backward", _ptr(x2), _ptr(g2), _ptr(gx), C, N, ld, ldg, max(N, 1), _ptr(co), S, _ptr(ck),
+             _ptr(gs), _ptr(ws), wsb, _stream(x.device))
+    return (gx[0] if squeeze else gx), gs
+
+
+def chain_backward(x: torch.Tensor, gy: torch.Tensor, stages, ckpt, compute: str = "f32",
+                   need_coef: bool = True):
+    """(dL/dx, [dL/dcoef of every stage]) of y = chain(x, stages) given gy
+    and the forward's checkpoints (``chain(..., return_ckpt=True)``; None when
+    the chain has no SOS stage)."""
+    x2, squeeze, ld = _signal(x)
+    g2, _, ldg = _signal(gy)
+    C, N = x2.shape
+    if tuple(g2.shape) != (C, N):
+        raise ValueError("gy must have the shape of x")
+    kept, desc = _stages(stages, x.device)
+    arr = lib.stage_array(desc)
+    gx = torch.empty((C, N), dtype=torch.float32, device=x.device)
+    grads = [torch.empty_like(t) for t in kept] if need_coef else [None] * len(kept)
+    parr = lib.pointer_array([_ptr(g) for g in grads])
+    ck = ckpt.contiguous() if ckpt is not None else None
+    nb = lib.size_out()
+    lib.call("tfx_chain_backward_workspace_size", C, N, arr, len(desc), lib.COMPUTE[compute], nb)
+    ws, wsb = _workspace(nb.value, x.device)
+    lib.call("tfx_chain_backward", _ptr(x2), _ptr(g2), _ptr(gx), C, N, ld, ldg, max(N, 1), arr, len(desc),
+             lib.COMPUTE[compute], _ptr(ck), parr, _ptr(ws), wsb, _stream(x.device))
+    del kept
+    return (gx[0] if squeeze else gx), grads
+
+
+class _ChainFn(torch.autograd.Function):
+    """y = chain(x, stages) with the library's adjoint as backward."""
+
+    @staticmethod
+    def forward(ctx, kinds, compute, x, *coefs):
+        stages = list(zip(kinds, coefs))
+        has_sos = any(k == "sos" for k in kinds)
+        if has_sos:
+            y, ck = _chain_raw(x, stages, compute, return_ckpt=True)
+        else:
+            y, ck = _chain_raw(x, stages, compute), None
+        ctx.kinds, ctx.compute = kinds, compute
+        ctx.save_for_backward(x, ck if ck is not None else torch.empty(0, device=x.device), *coefs)
+        ctx.has_ck = ck is not None
+        return y
+
+    @staticmethod
+    def backward(ctx, gy):
+        x, ck, *coefs = ctx.saved_tensors
+        need_coef = any(ctx.needs_input_grad[3:])
+        gx, grads = chain_backward(x, gy.contiguous(), list(zip(ctx.kinds, coefs)), ck if ctx.has_ck else None,
+                                   ctx.compute, need_coef)
+        out = [None, None, gx if ctx.needs_input_grad[2] else None]
+        for c, g, need in zip(coefs, grads, ctx.needs_input_grad[3:]):
+            out.append(g.reshape(c.shape) if (need and g is not None) else None)
+        return tuple(out)
+
+
+def _wants_grad(x, coefs):
+    if not torch.is_grad_enabled():
+        return False
+    return bool(getattr(x, "requires_grad", False)) or any(
+        isinstance(c, torch.Tensor) and c.requires_grad for c in coefs)
+
+
+def _as_param(c, device, shape_fn):
+    if isinstance(c, torch.Tensor) and c.requires_grad:
+        if c.dtype != torch.float32 or c.device != device:
+            raise TypeError("trainable coefficients must be float32 tensors on the signal's device")
+        return c
+    return shape_fn(_coef(c, device))
+
+
+def chain(x: torch.Tensor, stages, compute: str = "f32", return_ckpt: bool = False):
+    """Apply ("fir", taps) / ("sos", sections) stages left to right in one
+    fused launch (all FIR stages merged and applied first, all sections
+    concatenated behind them).  Differentiable in x and every coefficient
+    tensor when autograd records (``return_ckpt`` is then not available)."""
+    coefs = [c for _, c in stages]
+    if _wants_grad(x, coefs):
+        if return_ckpt:
+            raise ValueError("return_ckpt is for explicit adjoint calls, not autograd")
+        kinds = tuple(k for k, _ in stages)
+        for k in kinds:
+            if k not in ("fir", "sos"):
+                raise ValueError("unknown stage kind %r" % (k,))
+        ts = [_as_param(c, x.device, (lambda t: t.reshape(-1)) if k == "fir" else (lambda t: t.reshape(-1, 5)))
+              for k, c in stages]
+        return _ChainFn.apply(kinds, compute, x, *ts)
+    return _chain_raw(x, stages, compute, return_ckpt)
+
+
+def fir(x: torch.Tensor, h, compute: str = "f32", algo: str = "auto") -> torch.Tensor:
+    """y[c, n] = sum_k h[k] x[c, n-k] (causal, zero history, same length).
+    Differentiable in x and h when autograd records."""
+    if _wants_grad(x, [h]):
+        if algo not in ("auto",):
+            raise ValueError("the differentiable FIR uses the automatic algorithm choice")
+        return chain(x, [("fir", h)], compute)
+    return _fir_raw(x, h, compute, algo)
+
+
+def sos(x: torch.Tensor, sections, state_in=None, return_state: bool = False,
+        return_ckpt: bool = False):
+    """Cascade of second-order sections, rows [b0 b1 b2 a1 a2] (a0 == 1).
+
+    state_in: optional [C, S, 2] TDF-II registers.  Returns y, plus the final
+    state [C, S, 2] if ``return_state`` and the tile checkpoints
+    [C, ceil(N/T), S, 2] if ``return_ckpt``.  Differentiable in x and the
+    sections (zero initial state) when autograd records."""
+    if _wants_grad(x, [sections]):
+        if state_in is not None or return_state or return_ckpt:
+            raise ValueError("the differentiable SOS takes no state and returns only y")
+        return chain(x, [("sos", sections)])
+    return _sos_raw(x, sections, state_in, return_state, return_ckpt)

@@ -50,6 +50,16 @@ _SIGS = {
     "tfx_chain_prepare": (_i32, [_i64, _i64, ctypes.POINTER(Stage), _i32, _i32, _vp, _sz, _vp]),
     "tfx_chain_run": (_i32, [_vp, _vp, _i64, _i64, _i64, _i64, ctypes.POINTER(Stage), _i32, _i32, _vp, _vp,
                              _sz, _vp]),
+    "tfx_chain_backward_workspace_size": (_i32, [_i64, _i64, ctypes.POINTER(Stage), _i32, _i32,
+                                                 ctypes.POINTER(_sz)]),
+    "tfx_chain_backward": (_i32, [_vp, _vp, _vp, _i64, _i64, _i64, _i64, _i64, ctypes.POINTER(Stage), _i32,
+                                  _i32, _vp, ctypes.POINTER(_vp), _vp, _sz, _vp]),
+    "tfx_fir_backward_workspace_size": (_i32, [_i64, _i64, _i32, _i32, _i32, ctypes.POINTER(_sz)]),
+    "tfx_fir_backward": (_i32, [_vp, _vp, _vp, _i64, _i64, _i64, _i64, _i64, _vp, _i32, _vp, _i32, _i32, _vp,
+                                _sz, _vp]),
+    "tfx_sos_backward_workspace_size": (_i32, [_i64, _i64, _i32, ctypes.POINTER(_sz)]),
+    "tfx_sos_backward": (_i32, [_vp, _vp, _vp, _i64, _i64, _i64, _i64, _i64, _vp, _i32, _vp, _vp, _vp, _sz,
+                                _vp]),
 }
 
 _lock = threading.Lock()
@@ -102,4 +112,12 @@ def stage_array(stages):
         arr[i].kind = kind
         arr[i].len = n
         arr[i].coef = ptr
+    return arr
+
+
+def pointer_array(ptrs):
+    """list of device pointers (or None) -> ctypes void* array."""
+    arr = (ctypes.c_void_p * max(1, len(ptrs)))()
+    for i, p in enumerate(ptrs):
+        arr[i] = p
     return arr

@@ -85,3 +85,39 @@ def test_missing_library_fails_loudly(monkeypatch, tmp_path):
     monkeypatch.setattr(lib, "LIB_PATH", str(tmp_path / "nope.so"))
     with pytest.raises(RuntimeError, match="not built"):
         lib.load()
+
+
+def test_backward_argument_validation():
+    # x, gy, gx at disjoint fake addresses; nothing is launched
+    X, G, GX = FAKE, FAKE + (1 << 30), FAKE + (2 << 30)
+    many = lib.stage_array([(lib.STAGE_SOS, 17, FAKE)])
+    assert _st("tfx_chain_backward", X, G, GX, 1, 10, 10, 10, 10, many, 1, 0, FAKE, None, None, 0, None) \
+        == "TFX_E_UNSUPPORTED"                                   # more than 16 sections
+    assert b"16" in lib.load().tfx_last_error()
+    one = lib.stage_array([(lib.STAGE_SOS, 2, FAKE)])
+    assert _st("tfx_chain_backward", X, G, GX, 1, 10, 10, 10, 10, one, 1, 0, None, None, None, 0, None) \
+        == "TFX_E_INVALID_ARG"                                   # no checkpoints
+    assert _st("tfx_chain_backward", X, G, G + 8, 1, 10, 10, 10, 10, one, 1, 0, FAKE, None, None, 0, None) \
+        == "TFX_E_ALIAS"                                         # gx overlaps gy
+    assert _st("tfx_chain_backward", X, G, GX, 1, 10, 10, 5, 10, one, 1, 0, FAKE, None, None, 0, None) \
+        == "TFX_E_INVALID_ARG"                                   # ldg < N
+    assert _st("tfx_chain_backward", X, G, GX, 1, 10, 10, 10, 10, one, 1, 0, FAKE, None, None, 0, None) \
+        == "TFX_E_WORKSPACE"
+    assert _st("tfx_sos_backward", X, G, GX, 1, 10, 10, 10, 10, FAKE, 2, None, None, None, 0, None) \
+        == "TFX_E_INVALID_ARG"                                   # no checkpoints
+    assert _st("tfx_fir_backward", X, G, GX, 1, 10, 10, 10, 10, None, 5, None, 0, 0, None, 0, None) \
+        == "TFX_E_INVALID_ARG"                                   # taps NULL
+    assert _st("tfx_fir_backward", X, G, GX, 1, 10, 10, 10, 10, FAKE, 2000, None, 0, 2, None, 0, None) \
+        == "TFX_E_UNSUPPORTED"                                   # Toeplitz with fp32 compute
+
+
+def test_backward_workspace_sizes():
+    n = ctypes.c_size_t(0)
+    st = lib.stage_array([(lib.STAGE_FIR, 1023, FAKE), (lib.STAGE_SOS, 6, FAKE)])
+    assert _st("tfx_chain_backward_workspace_size", 8, 5_760_000, st, 2, 0, ctypes.byref(n)) == "TFX_OK"
+    fwd = ctypes.c_size_t(0)
+    assert _st("tfx_chain_workspace_size", 8, 5_760_000, st, 2, 0, ctypes.byref(fwd)) == "TFX_OK"
+    # the adjoint keeps the FIR output and its gradient: two signal copies
+    assert n.value >= fwd.value + 2 * 8 * 5_760_000 * 4 and n.value % 256 == 0
+    assert _st("tfx_sos_backward_workspace_size", 2, 1000, 3, ctypes.byref(n)) == "TFX_OK" and n.value > 0
+    assert _st("tfx_fir_backward_workspace_size", 2, 1000, 64, 0, 0, ctypes.byref(n)) == "TFX_OK" and n.value > 0

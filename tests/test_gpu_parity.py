@@ -174,10 +174,21 @@ def test_fir_fft_lowpass_designed_taps():
     assert_close(y, O.fir(w.x, h), TOL_FIR_F32, "fft band-pass 1023")
 
 
-def test_fir_fft_rejects_long_filters():
-    x = _gpu(_x(1, 100, (132,)))
-    with pytest.raises(lib.TfxError, match="UNSUPPORTED"):
-        tfx.fir(x, np.ones(1026, np.float32), algo="fft")
+@pytest.mark.parametrize("M", [1026, 2050, 2051, 3000, 8191])
+@pytest.mark.parametrize("C,N", [(1, 500), (2, 3 * T + 5), (3, 9000)])
+def test_fir_fft_partitioned_parity(M, C, N):
+    # taps beyond 1025: partitions of 1025 taps summed in the frequency domain
+    x = _x(C, N, (132, M, C, N))
+    h = (np.random.default_rng(M + 11).standard_normal(M) / np.sqrt(M)).astype(np.float32)
+    y = _cpu(tfx.fir(_gpu(x), _gpu(h), algo="fft"))
+    assert_close(y, O.fir(x, h), TOL_FIR_F32, "partitioned fft fir M=%d C=%d N=%d" % (M, C, N))
+
+
+def test_fir_long_lowpass_reduced():
+    # the 8191-tap low-pass of the long-filter workload on 2 x 40,000 samples
+    w = workloads.fir_long(C=2, N=40_000)
+    y = _cpu(tfx.fir(_gpu(w.x), _gpu(w.stages[0][1])))
+    assert_close(y, O.fir(w.x, w.stages[0][1]), TOL_FIR_F32, "fir_long 8191 taps")
 
 
 def test_fir_longer_than_one_lds_pass():
