@@ -167,6 +167,54 @@ tfx_status tfx_chain_run(const float *x, float *y, int64_t C, int64_t N, int64_t
                          const tfx_stage *stages, int32_t nstages, tfx_compute cmp, float *ckpt,
                          void *ws, size_t ws_bytes, void *stream);
 
+/* ------------------------------------------------------- batched clips */
+
+/* One clip of a ragged batch: its own channel count C, length N, strides and
+ * SOS cascade sos[S][5] (device pointers, as for tfx_sos; zero initial
+ * state).  x and y of one clip must not overlap; different clips must not
+ * write overlapping outputs. */
+typedef struct tfx_clip {
+    const float *x;
+    float *y;
+    int64_t C, N, ldx, ldy;
+    const float *sos;
+    int32_t S;
+    int32_t reserved; /* 0 */
+} tfx_clip;
+
+/* Launch shape of the batched kernel.
+ *   chunk : samples per lane chunk, 16, 24 or 32 (tile = 128 chunk samples
+ *           of one channel); 0 = 24
+ *   order : 0 = clips in the given order, 1 = longest clip first */
+typedef struct tfx_batch_config {
+    int32_t chunk;
+    int32_t order;
+} tfx_batch_config;
+
+/* Workspace for any configuration of this batch (host clips array). */
+tfx_status tfx_sos_batched_workspace_size(const tfx_clip *clips, int32_t nclips, size_t *bytes);
+/* Writes the clip descriptor table and every clip's section tables into ws
+ * and initialises it (a few small kernels on `stream`).  Coefficients must
+ * stay fixed until the next prepare.  cfg may be NULL (defaults). */
+tfx_status tfx_sos_batched_prepare(const tfx_clip *clips, int32_t nclips, const tfx_batch_config *cfg,
+                                   void *ws, size_t ws_bytes, void *stream);
+/* Filters every clip of a prepared batch: ONE kernel launch over all clips
+ * (plus a one-thread kernel that re-arms ws), no memset, so it may be
+ * captured in a hipGraph and replayed.  clips, nclips and cfg must equal the
+ * prepare call's. */
+tfx_status tfx_sos_batched_run(const tfx_clip *clips, int32_t nclips, const tfx_batch_config *cfg,
+                               void *ws, size_t ws_bytes, void *stream);
+/* prepare + run. */
+tfx_status tfx_sos_batched(const tfx_clip *clips, int32_t nclips, const tfx_batch_config *cfg, void *ws,
+                           size_t ws_bytes, void *stream);
+/* Autotuner: times every configuration (chunk 16/24/32 x both orders) on
+ * this batch with HIP events, `reps` timed runs each after one warm-up, and
+ * returns the fastest in *best (its mean time in *best_ms if not NULL).
+ * Synchronises `stream`; overwrites the clips' outputs; leaves ws prepared
+ * for *best. */
+tfx_status tfx_sos_batched_tune(const tfx_clip *clips, int32_t nclips, int32_t reps, void *ws,
+                                size_t ws_bytes, void *stream, tfx_batch_config *best, float *best_ms);
+
 /* --------------------------------------------------------------- adjoint */
 
 /* Gradients of a scalar loss L through the forward calls above, given

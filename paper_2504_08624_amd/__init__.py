@@ -5,7 +5,8 @@ libtfx.so (include/tfx.h); this package is its Python binding.  Importing it
 loads nothing: the library is loaded on the first call and every call raises
 if it is not built (there is no CPU fallback).
 """
-from .functional import (chain, chain_backward, fir, fir_backward, sos, sos_backward,  # noqa: F401
-                         tile_length)
+from .functional import (SosBatch, chain, chain_backward, fir, fir_backward, sos, sos_backward,  # noqa: F401
+                         sos_batched, tile_length)
 
-__all__ = ["fir", "sos", "chain", "fir_backward", "sos_backward", "chain_backward", "tile_length"]
+__all__ = ["fir", "sos", "chain", "fir_backward", "sos_backward", "chain_backward", "sos_batched", "SosBatch",
+           "tile_length"]

@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <vector>
 
 #include "tfx.h"
 #include "tfx_internal.h"
@@ -194,6 +195,68 @@ tfx_status bwd_plan(const float *x, const float *gy, float *gx, int64_t C, int64
     bp.ldg = ldg;
     bp.ldgx = ldgx;
     return TFX_OK;
+}
+
+// ---- batched clips
+
+tfx_status batch_clips(const tfx_clip *clips, int32_t n, tfx::ClipIn *out) {
+    if (n < 0 || n > 65536) return fail(TFX_E_INVALID_ARG, "nclips must be in [0, 65536]");
+    if (n > 0 && !clips) return fail(TFX_E_INVALID_ARG, "clips is NULL");
+    for (int i = 0; i < n; ++i) {
+        const tfx_clip &c = clips[i];
+        tfx_status s = check_signal(c.x, c.y, c.C, c.N, c.ldx, c.ldy);
+        if (s) return fail(s, "clip %d: %s", i, g_last_error.c_str());
+        if (c.S < 0 || c.S > tfx::MAX_SECTIONS) return fail(TFX_E_INVALID_ARG, "clip %d: S must be in [0, %d]", i, tfx::MAX_SECTIONS);
+        if (c.S > 0 && !c.sos) return fail(TFX_E_INVALID_ARG, "clip %d: sos is NULL", i);
+        if (c.reserved != 0) return fail(TFX_E_INVALID_ARG, "clip %d: reserved must be 0", i);
+        // 16-sample chunks give the most tiles
+        if (c.C * ((c.N + 2047) / 2048) >= (int64_t(1) << 31)) return fail(TFX_E_UNSUPPORTED, "clip %d too large", i);
+        out[i] = tfx::ClipIn{c.x, c.y, c.C, c.N, c.ldx, c.ldy, c.sos, c.S};
+    }
+    return TFX_OK;
+}
+
+tfx_status batch_config(const tfx_batch_config *cfg, int *lc, int *order) {
+    *lc = 24;
+    *order = 0;
+    if (!cfg) return TFX_OK;
+    if (cfg->chunk != 0 && cfg->chunk != 16 && cfg->chunk != 24 && cfg->chunk != 32)
+        return fail(TFX_E_INVALID_ARG, "chunk must be 0, 16, 24 or 32 (got %d)", cfg->chunk);
+    if (cfg->order != 0 && cfg->order != 1) return fail(TFX_E_INVALID_ARG, "order must be 0 or 1");
+    if (cfg->chunk) *lc = cfg->chunk;
+    *order = cfg->order;
+    return TFX_OK;
+}
+
+size_t batch_ws_max(const tfx::ClipIn *c, int32_t n) {
+    size_t m = 0;
+    for (int lc : tfx::BATCH_CHUNKS) {
+        const size_t t = tfx::batch_plan(c, n, lc, 0, nullptr).total;
+        m = t > m ? t : m;
+    }
+    return m;
+}
+
+// Validates, and prepares (prep) and/or runs (run) one configuration.
+tfx_status batch_do(const tfx_clip *clips, int32_t n, const tfx_batch_config *cfg, void *ws, size_t ws_bytes,
+                    void *stream, bool prep, bool run) {
+    std::vector<tfx::ClipIn> in(n > 0 ? n : 1);
+    tfx_status s = batch_clips(clips, n, in.data());
+    if (s) return s;
+    int lc, order;
+    if ((s = batch_config(cfg, &lc, &order))) return s;
+    std::vector<tfx::ClipDesc> desc(n > 0 ? n : 1);
+    const tfx::BatchLayout lay = tfx::batch_plan(in.data(), n, lc, order, desc.data());
+    if ((s = check_ws(ws, ws_bytes, lay.total))) return s;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    hipError_t e = hipSuccess;
+    if (prep && n > 0) {
+        if ((e = tfx::upload_descriptors(desc.data(), n, lay, ws, st)) != hipSuccess) return hip_fail(e, "descriptor upload");
+        if ((e = tfx::launch_batch_prepare(lay, lc, n, ws, st)) != hipSuccess) return hip_fail(e, "batch prepare");
+    }
+    if (run && n > 0 && (e = tfx::launch_batch_run(lay, lc, n, ws, st)) != hipSuccess)
+        return hip_fail(e, "batch kernel launch");
+    return ok();
 }
 
 tfx_status backward(const tfx::BwdPlan &bp) {
@@ -470,6 +533,74 @@ tfx_status tfx_sos_backward(const float *x, const float *gy, float *gx, int64_t 
         return ok();
     }
     return backward(bp);
+}
+
+tfx_status tfx_sos_batched_workspace_size(const tfx_clip *clips, int32_t nclips, size_t *bytes) {
+    if (!bytes) return fail(TFX_E_INVALID_ARG, "bytes is NULL");
+    std::vector<tfx::ClipIn> in(nclips > 0 ? nclips : 1);
+    tfx_status s = batch_clips(clips, nclips, in.data());
+    if (s) return s;
+    *bytes = batch_ws_max(in.data(), nclips);
+    return ok();
+}
+
+tfx_status tfx_sos_batched_prepare(const tfx_clip *clips, int32_t nclips, const tfx_batch_config *cfg, void *ws,
+                                   size_t ws_bytes, void *stream) {
+    return batch_do(clips, nclips, cfg, ws, ws_bytes, stream, true, false);
+}
+
+tfx_status tfx_sos_batched_run(const tfx_clip *clips, int32_t nclips, const tfx_batch_config *cfg, void *ws,
+                               size_t ws_bytes, void *stream) {
+    return batch_do(clips, nclips, cfg, ws, ws_bytes, stream, false, true);
+}
+
+tfx_status tfx_sos_batched(const tfx_clip *clips, int32_t nclips, const tfx_batch_config *cfg, void *ws,
+                           size_t ws_bytes, void *stream) {
+    return batch_do(clips, nclips, cfg, ws, ws_bytes, stream, true, true);
+}
+
+tfx_status tfx_sos_batched_tune(const tfx_clip *clips, int32_t nclips, int32_t reps, void *ws, size_t ws_bytes,
+                                void *stream, tfx_batch_config *best, float *best_ms) {
+    if (!best) return fail(TFX_E_INVALID_ARG, "best is NULL");
+    if (reps < 1 || reps > 1000) return fail(TFX_E_INVALID_ARG, "reps must be in [1, 1000]");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    hipEvent_t e0, e1;
+    hipError_t he;
+    if ((he = hipEventCreate(&e0)) != hipSuccess) return hip_fail(he, "hipEventCreate");
+    if ((he = hipEventCreate(&e1)) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return hip_fail(he, "hipEventCreate");
+    }
+    tfx_status s = TFX_OK;
+    float bms = -1.f;
+    tfx_batch_config bc{24, 0};
+    for (int lc : tfx::BATCH_CHUNKS) {
+        for (int order = 0; order < 2 && !s; ++order) {
+            const tfx_batch_config c{lc, order};
+            if ((s = batch_do(clips, nclips, &c, ws, ws_bytes, stream, true, true))) break;  // prepare + warm-up
+            if ((he = hipEventRecord(e0, st)) != hipSuccess) { s = hip_fail(he, "hipEventRecord"); break; }
+            for (int r = 0; r < reps && !s; ++r) s = batch_do(clips, nclips, &c, ws, ws_bytes, stream, false, true);
+            if (s) break;
+            if ((he = hipEventRecord(e1, st)) != hipSuccess || (he = hipEventSynchronize(e1)) != hipSuccess) {
+                s = hip_fail(he, "timing");
+                break;
+            }
+            float ms = 0.f;
+            if ((he = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) { s = hip_fail(he, "hipEventElapsedTime"); break; }
+            ms /= reps;
+            if (bms < 0.f || ms < bms) {
+                bms = ms;
+                bc = c;
+            }
+        }
+        if (s) break;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (s) return s;
+    *best = bc;
+    if (best_ms) *best_ms = bms;
+    return batch_do(clips, nclips, &bc, ws, ws_bytes, stream, true, false);
 }
 
 }  // extern "C"

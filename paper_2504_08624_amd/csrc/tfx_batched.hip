@@ -1,0 +1,228 @@
+// tfx_batched.hip -- a ragged batch of clips (each with its own channel
+// count, length and SOS cascade) filtered by one kernel launch.
+//
+// The launch covers every (clip, tile, channel pair) of the batch: blocks are
+// numbered clip by clip in a chosen clip order, tile-major within a clip, so a
+// tile's predecessors in time always have lower block ids and the decoupled
+// look-back of the chain kernel carries over unchanged.  A block finds its
+// clip by a binary search over the clips' first block ids in the descriptor
+// table the prepare step leaves in the workspace; every clip has its own
+// section tables and look-back records.  The chunk length LC (and with it
+// the tile length 128 LC) is a template parameter, chosen per batch by the
+// autotuner among 16, 24 and 32.
+#include <hip/hip_runtime.h>
+
+#include "tfx_device.h"
+
+namespace tfx {
+
+template <int LC, typename CT>
+__device__ void batch_section(const SecTab &tb, float (&v)[LC], const CarryCtx &cc, double (*s_agg)[GWAVES][2],
+                              double (*s_pre)[2], int buf) {
+    const float b0 = tb.coef[0], b1 = tb.coef[1], b2 = tb.coef[2];
+    const float a1 = tb.coef[3], a2 = tb.coef[4];
+    float s1 = 0.f, s2 = 0.f;
+#pragma unroll
+    for (int r = 0; r < LC; ++r) {
+        const float xv = v[r];
+        const float yv = fmaf(b0, xv, s1);
+        s1 = fmaf(b1, xv, fmaf(-a1, yv, s2));
+        s2 = fmaf(b2, xv, -a2 * yv);
+        v[r] = yv;
+    }
+    float z1, z2;
+    carry<CT, false>(tb, cc, s1, s2, z1, z2, s_agg, s_pre, buf);
+#pragma unroll
+    for (int r = 0; r < LC; ++r) {
+        v[r] += z1;
+        const float n1 = fmaf(-a1, z1, z2);
+        z2 = -a2 * z1;
+        z1 = n1;
+    }
+}
+
+struct BatchArgs {
+    const ClipDesc *desc;
+    int32_t nclips;
+    const SecTab *tab;
+    uint64_t *recs;
+    uint32_t *hdr;
+};
+
+template <int LC>
+__global__ __launch_bounds__(WG) void batch_kernel(BatchArgs a) {
+    typedef Chunk<LC> K;
+    __shared__ __align__(16) float lds[GROUPS * K::STG];
+    __shared__ double s_agg[2 * GROUPS][GWAVES][2];
+    __shared__ double s_pre[2 * GROUPS][2];
+    __shared__ uint32_t s_epoch;
+    __shared__ int s_clip;
+
+    const int tid = threadIdx.x, lane = tid & 63, grp = tid / GL, gl = tid % GL, gw = gl >> 6;
+    const int64_t id = blockIdx.x;
+    if (tid == 0) {
+        s_epoch = load_epoch(a.hdr, HDR_EPOCH);
+        int lo = 0, hi = a.nclips - 1;  // the last clip whose first block is <= id
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) / 2;
+            if (a.desc[mid].blk0 <= id) lo = mid;
+            else hi = mid - 1;
+        }
+        s_clip = lo;
+    }
+    __syncthreads();
+    const ClipDesc &d = a.desc[s_clip];
+    const uint32_t epoch = s_epoch;
+    const int64_t npairs = d.cpad / 2, local = id - d.blk0;
+    const int64_t tile = local / npairs, pair = local % npairs;
+    const int64_t ch = 2 * pair + grp;
+    const bool valid = ch < d.C;
+    const int64_t n0 = tile * K::T;
+    float *stg = lds + grp * K::STG;
+    float v[LC];
+    stage_tile<LC>(stg, d.x + ch * d.ldx + n0, d.N - n0, valid, d.vec != 0, gl);
+    __syncthreads();
+    load_chunk<LC>(stg, gl, v);
+    for (int s = 0; s < d.S; ++s) {
+        const SecTab &tb = a.tab[d.tab0 + s];
+        CarryCtx cc;
+        cc.lane = lane;
+        cc.gw = gw;
+        cc.grp = grp;
+        cc.lookback = true;
+        cc.pos = tile;
+        cc.recs = a.recs;
+        cc.rec0 = d.rec0 + ch * d.ntiles * d.S + s;
+        cc.rstride = d.S;
+        cc.epoch = epoch;
+        cc.hdr = a.hdr;
+        cc.known0 = cc.known1 = 0.0;
+        cc.prefix_out = nullptr;
+        const int buf = (s & 1) * GROUPS + grp;
+        if (tb.hiq)
+            batch_section<LC, double>(tb, v, cc, s_agg, s_pre, buf);
+        else
+            batch_section<LC, float>(tb, v, cc, s_agg, s_pre, buf);
+    }
+    __syncthreads();
+    store_chunk<LC>(stg, gl, v);
+    __syncthreads();
+    if (valid) store_tile<LC>(d.y + ch * d.ldy + n0, stg, d.N - n0, d.vec != 0, gl);
+}
+
+// The descriptor table reaches the device through kernel arguments, 32
+// clips per launch: no host buffer has to outlive the call.
+constexpr int DESC_CHUNK = 32;
+struct DescChunk {
+    ClipDesc d[DESC_CHUNK];
+    int32_t first, n;
+};
+__global__ void desc_write_kernel(ClipDesc *dst, DescChunk c) {
+    const int i = threadIdx.x;
+    if (i < c.n) dst[c.first + i] = c.d[i];
+}
+
+hipError_t upload_descriptors(const ClipDesc *desc, int32_t n, const BatchLayout &lay, void *ws, hipStream_t st) {
+    ClipDesc *dst = reinterpret_cast<ClipDesc *>(static_cast<char *>(ws) + lay.desc);
+    for (int32_t f = 0; f < n; f += DESC_CHUNK) {
+        DescChunk c{};
+        c.first = f;
+        c.n = n - f < DESC_CHUNK ? n - f : DESC_CHUNK;
+        for (int i = 0; i < c.n; ++i) c.d[i] = desc[f + i];
+        hipLaunchKernelGGL(desc_write_kernel, dim3(1), dim3(DESC_CHUNK), 0, st, dst, c);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+__global__ void batch_bump_epoch_kernel(uint32_t *hdr) {
+    const uint32_t ne = (hdr[HDR_EPOCH] + 1u) & EPOCH_MASK;
+    hdr[HDR_EPOCH] = ne == 0u ? 1u : ne;
+}
+
+// ------------------------------------------------------------------- host
+
+static size_t al256b(size_t b) { return (b + 255) & ~size_t(255); }
+
+BatchLayout batch_plan(const ClipIn *clips, int32_t n, int lc, int order, ClipDesc *desc) {
+    BatchLayout lay{};
+    const int64_t T_ = (int64_t)GL * lc;
+    // processing order: as given, or by tile count, longest first (stable)
+    int32_t *ord = new int32_t[n > 0 ? n : 1];
+    for (int i = 0; i < n; ++i) ord[i] = i;
+    if (order == 1) {
+        for (int i = 1; i < n; ++i) {  // insertion sort, stable
+            const int32_t k = ord[i];
+            const int64_t tk = (clips[k].N + T_ - 1) / T_;
+            int j = i - 1;
+            while (j >= 0 && (clips[ord[j]].N + T_ - 1) / T_ < tk) {
+                ord[j + 1] = ord[j];
+                --j;
+            }
+            ord[j + 1] = k;
+        }
+    }
+    int64_t blk = 0, tab = 0, rec = 0;
+    for (int j = 0; j < n; ++j) {
+        const ClipIn &c = clips[ord[j]];
+        ClipDesc d{};
+        d.x = c.x;
+        d.y = c.y;
+        d.sos = c.sos;
+        d.C = c.C;
+        d.N = c.N;
+        d.ldx = c.ldx;
+        d.ldy = c.ldy;
+        d.S = c.S;
+        d.ntiles = (c.N + T_ - 1) / T_;
+        d.cpad = c.C + (c.C & 1);
+        d.blk0 = blk;
+        d.tab0 = tab;
+        d.rec0 = rec;
+        d.vec = ((reinterpret_cast<uintptr_t>(c.x) | reinterpret_cast<uintptr_t>(c.y)) % 16 == 0 && c.ldx % 4 == 0 &&
+                 c.ldy % 4 == 0) ? 1 : 0;
+        blk += d.cpad / 2 * d.ntiles;
+        tab += c.S;
+        rec += d.cpad * d.ntiles * c.S;
+        if (desc) desc[j] = d;
+    }
+    delete[] ord;
+    lay.nblocks = blk;
+    lay.nsec = tab;
+    lay.nrec = rec;
+    size_t off = 0;
+    lay.hdr = off;
+    off += 256;
+    lay.desc = off;
+    off += al256b(sizeof(ClipDesc) * (size_t)(n > 0 ? n : 1));
+    lay.tab = off;
+    off += al256b(sizeof(SecTab) * (size_t)tab);
+    lay.recs = off;
+    off += al256b((size_t)rec * REC_WORDS * sizeof(uint64_t));
+    lay.total = off;
+    return lay;
+}
+
+hipError_t launch_batch_run(const BatchLayout &lay, int lc, int32_t nclips, void *ws, hipStream_t st) {
+    if (lay.nblocks == 0) return hipSuccess;
+    char *w = static_cast<char *>(ws);
+    BatchArgs a;
+    a.desc = reinterpret_cast<const ClipDesc *>(w + lay.desc);
+    a.nclips = nclips;
+    a.tab = reinterpret_cast<const SecTab *>(w + lay.tab);
+    a.recs = reinterpret_cast<uint64_t *>(w + lay.recs);
+    a.hdr = reinterpret_cast<uint32_t *>(w + lay.hdr);
+    const dim3 grid((unsigned)lay.nblocks), block(WG);
+    switch (lc) {
+        case 16: hipLaunchKernelGGL(batch_kernel<16>, grid, block, 0, st, a); break;
+        case 32: hipLaunchKernelGGL(batch_kernel<32>, grid, block, 0, st, a); break;
+        default: hipLaunchKernelGGL(batch_kernel<24>, grid, block, 0, st, a); break;
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(batch_bump_epoch_kernel, dim3(1), dim3(1), 0, st, a.hdr);
+    return hipGetLastError();
+}
+
+}  // namespace tfx

@@ -103,62 +103,76 @@ template <> struct Tab<double> {
 };
 
 // ------------------------------------------------------------------ staging
-// LDS layout of lane chunks: 24 samples then 4 floats of padding, so a lane's
-// chunk starts 112 bytes after its neighbour's and 16-byte reads of 16 lanes
-// hit distinct banks.
-constexpr int CSTRIDE = L + 4;
-constexpr int STG_FLOATS = GL * CSTRIDE;
-__device__ __forceinline__ int cphys(int i) { return (i / L) * CSTRIDE + (i % L); }
+// LDS layout of lane chunks of LC samples: LC samples then 4 floats of
+// padding, so a lane's chunk starts 16 LC + 16 bytes after its neighbour's
+// and 16-byte reads of 16 lanes hit distinct banks (LC = 16, 24, 32).  The
+// defaults are the chain kernel's chunk length L.
+template <int LC = L> struct Chunk {
+    static constexpr int T = GL * LC;       // samples per group tile
+    static constexpr int STRIDE = LC + 4;   // floats per staged chunk
+    static constexpr int STG = GL * STRIDE;  // floats per staged tile
+    static __device__ __forceinline__ int phys(int i) { return (i / LC) * STRIDE + (i % LC); }
+};
+constexpr int CSTRIDE = Chunk<>::STRIDE;
+constexpr int STG_FLOATS = Chunk<>::STG;
+__device__ __forceinline__ int cphys(int i) { return Chunk<>::phys(i); }
 
-__device__ __forceinline__ void load_chunk(const float *stg, int gl, float (&v)[L]) {
+template <int LC = L>
+__device__ __forceinline__ void load_chunk(const float *stg, int gl, float (&v)[LC]) {
 #pragma unroll
-    for (int q = 0; q < L / 4; ++q) {
-        const float4 t4 = *reinterpret_cast<const float4 *>(&stg[gl * CSTRIDE + 4 * q]);
+    for (int q = 0; q < LC / 4; ++q) {
+        const float4 t4 = *reinterpret_cast<const float4 *>(&stg[gl * Chunk<LC>::STRIDE + 4 * q]);
         v[4 * q + 0] = t4.x;
         v[4 * q + 1] = t4.y;
         v[4 * q + 2] = t4.z;
         v[4 * q + 3] = t4.w;
     }
 }
-__device__ __forceinline__ void store_chunk(float *stg, int gl, const float (&v)[L]) {
+template <int LC = L>
+__device__ __forceinline__ void store_chunk(float *stg, int gl, const float (&v)[LC]) {
 #pragma unroll
-    for (int q = 0; q < L / 4; ++q)
-        *reinterpret_cast<float4 *>(&stg[gl * CSTRIDE + 4 * q]) =
+    for (int q = 0; q < LC / 4; ++q)
+        *reinterpret_cast<float4 *>(&stg[gl * Chunk<LC>::STRIDE + 4 * q]) =
             make_float4(v[4 * q + 0], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]);
 }
 
-// One group (GL lanes) stages T samples src[0..rem) (zeros past rem) into stg
-// in the chunk layout.  vec: src is 16-byte aligned.
+// One group (GL lanes) stages the tile's samples src[0..rem) (zeros past rem)
+// into stg in the chunk layout.  vec: src is 16-byte aligned.
+template <int LC = L>
 __device__ __forceinline__ void stage_tile(float *stg, const float *src, int64_t rem, bool valid, bool vec, int gl) {
-    if (vec && rem >= T) {
-        float4 t4[T / (4 * GL)];
+    typedef Chunk<LC> K;
+    if (vec && rem >= K::T) {
+        float4 t4[K::T / (4 * GL)];
 #pragma unroll
-        for (int k = 0; k < T / (4 * GL); ++k)
+        for (int k = 0; k < K::T / (4 * GL); ++k)
             t4[k] = valid ? reinterpret_cast<const float4 *>(src)[gl + GL * k] : make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
-        for (int k = 0; k < T / (4 * GL); ++k) *reinterpret_cast<float4 *>(&stg[cphys(4 * (gl + GL * k))]) = t4[k];
+        for (int k = 0; k < K::T / (4 * GL); ++k)
+            *reinterpret_cast<float4 *>(&stg[K::phys(4 * (gl + GL * k))]) = t4[k];
     } else {  // ragged last tile or unaligned rows
 #pragma unroll 4
-        for (int k = 0; k < T / GL; ++k) {
+        for (int k = 0; k < K::T / GL; ++k) {
             const int i = gl + GL * k;
-            stg[cphys(i)] = (valid && i < rem) ? src[i] : 0.f;
+            stg[K::phys(i)] = (valid && i < rem) ? src[i] : 0.f;
         }
     }
 }
 
 // One group writes its staged tile (chunk layout) to dst[0..rem).
+template <int LC = L>
 __device__ __forceinline__ void store_tile(float *dst, const float *stg, int64_t rem, bool vec, int gl) {
-    if (vec && rem >= T) {
+    typedef Chunk<LC> K;
+    if (vec && rem >= K::T) {
 #pragma unroll
-        for (int k = 0; k < T / (4 * GL); ++k) {
+        for (int k = 0; k < K::T / (4 * GL); ++k) {
             const int f = gl + GL * k;
-            reinterpret_cast<float4 *>(dst)[f] = *reinterpret_cast<const float4 *>(&stg[cphys(4 * f)]);
+            reinterpret_cast<float4 *>(dst)[f] = *reinterpret_cast<const float4 *>(&stg[K::phys(4 * f)]);
         }
     } else {
 #pragma unroll 4
-        for (int k = 0; k < T / GL; ++k) {
+        for (int k = 0; k < K::T / GL; ++k) {
             const int i = gl + GL * k;
-            if (i < rem) dst[i] = stg[cphys(i)];
+            if (i < rem) dst[i] = stg[K::phys(i)];
         }
     }
 }

@@ -105,6 +105,44 @@ hipError_t launch_toeplitz_prepare(const float *h, int32_t M, int32_t cmp, void 
 hipError_t launch_toeplitz(const float *x, float *y, int64_t C, int64_t N, int64_t ldx, int64_t ldy, int32_t M,
                            int32_t cmp, const void *tab, hipStream_t st);
 
+// ---- batched ragged clips (tfx_batched.hip) -------------------------------------
+// Device descriptor of one clip, in processing order.  Blocks of the single
+// launch are numbered clip by clip (blk0 = the clip's first block); within a
+// clip they are tile-major over channel pairs, as in the chain kernel.
+struct alignas(16) ClipDesc {
+    const float *x;
+    float *y;
+    const float *sos;
+    int64_t C, N, ldx, ldy;
+    int64_t blk0, tab0, rec0;
+    int64_t ntiles, cpad;
+    int32_t S, vec;
+};
+
+struct BatchLayout {
+    size_t hdr, desc, tab, recs, total;
+    int64_t nblocks, nsec, nrec;
+};
+
+// host-side clip record (mirrors the public tfx_clip)
+struct ClipIn {
+    const float *x;
+    float *y;
+    int64_t C, N, ldx, ldy;
+    const float *sos;
+    int32_t S;
+};
+
+// chunk lengths of the batched kernel
+constexpr int BATCH_CHUNKS[3] = {16, 24, 32};
+
+// Fills desc (processing order) and returns the layout for chunk length lc
+// and clip order (0: as given, 1: longest first).
+BatchLayout batch_plan(const ClipIn *clips, int32_t n, int lc, int order, ClipDesc *desc);
+hipError_t upload_descriptors(const ClipDesc *desc, int32_t n, const BatchLayout &lay, void *ws, hipStream_t st);
+hipError_t launch_batch_prepare(const BatchLayout &lay, int lc, int32_t nclips, void *ws, hipStream_t st);
+hipError_t launch_batch_run(const BatchLayout &lay, int lc, int32_t nclips, void *ws, hipStream_t st);
+
 // ---- adjoint -------------------------------------------------------------------
 struct GradList {
     float *ptr[MAX_STAGES];

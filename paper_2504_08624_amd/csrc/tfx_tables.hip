@@ -29,14 +29,14 @@ __device__ void put4(float *f, double *d, const double *m) {
 
 // Transition powers of one TDF-II section.  With state s = (s1, s2) the
 // section is s' = A s + B x, y = s1 + b0 x, A = [[-a1, 1], [-a2, 0]], so a
-// state s entering a chunk becomes A^L s after L samples.
-__device__ void build_section(SecTab *tb, const float *co) {
+// state s entering a chunk becomes A^Lc s after Lc samples.
+__device__ void build_section(SecTab *tb, const float *co, int Lc) {
     const double a1 = co[3], a2 = co[4];
     for (int i = 0; i < 5; ++i) tb->coef[i] = co[i];
     tb->pad[0] = tb->pad[1] = 0;
     const double A[4] = {-a1, 1.0, -a2, 0.0};
     double P[4] = {A[0], A[1], A[2], A[3]};
-    for (int t = 1; t < L; ++t) mat2_mul(P, A, P);
+    for (int t = 1; t < Lc; ++t) mat2_mul(P, A, P);
     const double Phi[4] = {P[0], P[1], P[2], P[3]};
     double F[4] = {1.0, 0.0, 0.0, 1.0};
     for (int k = 0; k < 64; ++k) {
@@ -90,7 +90,7 @@ __global__ void prep_kernel(PrepArgs a) {
             s -= a.sos.len[st];
             ++st;
         }
-        build_section(&a.tab[gid], a.sos.ptr[st] + 5 * s);
+        build_section(&a.tab[gid], a.sos.ptr[st] + 5 * s, L);
     }
 }
 
@@ -171,6 +171,60 @@ __global__ void fft_spectrum_kernel(const float *h_all, int32_t M_all, const dou
 __global__ void state_passthrough_kernel(const float *in, float *out, int64_t n) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) out[i] = in ? in[i] : 0.f;
+}
+
+// Batched clips: section tables of every clip (chunk length lc), cleared
+// look-back records, epoch 1.  Thread g < nsec builds section g, found by a
+// binary search over the clips' first table index.
+struct BatchPrepArgs {
+    const ClipDesc *desc;
+    int32_t nclips;
+    SecTab *tab;
+    int64_t nsec;
+    uint64_t *recs;
+    int64_t nwords;
+    uint32_t *hdr;
+    int32_t lc;
+};
+
+__global__ void batch_prep_kernel(BatchPrepArgs a) {
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = gid; i < a.nwords; i += stride) a.recs[i] = 0ull;
+    if (gid == 0) {
+        a.hdr[1] = 0u;
+        a.hdr[2] = 1u;
+    }
+    for (int64_t g = gid; g < a.nsec; g += stride) {
+        // the last clip with tab0 <= g: tab0 grows with the clip index by S,
+        // so that clip has S > 0 and holds section g
+        int lo = 0, hi = a.nclips - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) / 2;
+            if (a.desc[mid].tab0 <= g) lo = mid;
+            else hi = mid - 1;
+        }
+        build_section(&a.tab[g], a.desc[lo].sos + 5 * (g - a.desc[lo].tab0), a.lc);
+    }
+}
+
+hipError_t launch_batch_prepare(const BatchLayout &lay, int lc, int32_t nclips, void *ws, hipStream_t st) {
+    char *w = static_cast<char *>(ws);
+    BatchPrepArgs a;
+    a.desc = reinterpret_cast<const ClipDesc *>(w + lay.desc);
+    a.nclips = nclips;
+    a.tab = reinterpret_cast<SecTab *>(w + lay.tab);
+    a.nsec = lay.nsec;
+    a.recs = reinterpret_cast<uint64_t *>(w + lay.recs);
+    a.nwords = lay.nrec * 4;
+    a.hdr = reinterpret_cast<uint32_t *>(w + lay.hdr);
+    a.lc = lc;
+    const int64_t work = a.nwords > a.nsec ? a.nwords : a.nsec;
+    int64_t nb = (work + 255) / 256;
+    if (nb > 2048) nb = 2048;
+    if (nb < 1) nb = 1;
+    hipLaunchKernelGGL(batch_prep_kernel, dim3((unsigned)nb), dim3(256), 0, st, a);
+    return hipGetLastError();
 }
 
 hipError_t launch_tables(const ChainPlan &p, const WsLayout &lay, const float *h, int32_t M) {

@@ -11,6 +11,8 @@ tile-boundary checkpoints of the IIR states, not per-sample signals).
 """
 from __future__ import annotations
 
+import ctypes
+
 import torch
 
 from . import lib
@@ -292,3 +294,68 @@ def sos(x: torch.Tensor, sections, state_in=None, return_state: bool = False,
             raise ValueError("the differentiable SOS takes no state and returns only y")
         return chain(x, [("sos", sections)])
     return _sos_raw(x, sections, state_in, return_state, return_ckpt)
+
+
+# ------------------------------------------------------------------ batched
+
+class SosBatch:
+    """A ragged batch of clips, each [C_i, N_i] with its own cascade [S_i, 5],
+    filtered by one kernel launch.
+
+    ``SosBatch(xs, sections)`` allocates the outputs and the workspace and
+    prepares the batch (descriptor table and section tables on the device);
+    ``run()`` then filters every clip with one launch on the current stream
+    and may be captured in a CUDA/HIP graph; ``tune()`` times every launch
+    configuration on this batch and keeps the fastest.  The inputs, the
+    coefficient tensors and the outputs stay owned by this object."""
+
+    def __init__(self, xs, sections, config=None):
+        if len(xs) != len(sections):
+            raise ValueError("one cascade per clip")
+        self.device = xs[0].device if xs else torch.device("cuda", torch.cuda.current_device())
+        self.xs, self.lds, self.secs, self.ys = [], [], [], []
+        for x, sec in zip(xs, sections):
+            x2, _, ld = _signal(x)
+            self.xs.append(x2)
+            self.lds.append(ld)
+            self.secs.append(_coef(sec, self.device).reshape(-1, 5))
+            self.ys.append(torch.empty(x2.shape, dtype=torch.float32, device=self.device))
+        n = len(self.xs)
+        self.clips = (lib.Clip * max(1, n))()
+        for i, (x2, ld, sec, y) in enumerate(zip(self.xs, self.lds, self.secs, self.ys)):
+            c = self.clips[i]
+            c.x, c.y = _ptr(x2), _ptr(y)
+            c.C, c.N = x2.shape
+            c.ldx, c.ldy = ld, max(x2.shape[1], 1)
+            c.sos, c.S, c.reserved = _ptr(sec), sec.shape[0], 0
+        self.n = n
+        nb = lib.size_out()
+        lib.call("tfx_sos_batched_workspace_size", self.clips, n, nb)
+        self.ws, self.wsb = _workspace(nb.value, self.device)
+        self.config = lib.BatchConfig(0, 0)
+        if config:
+            self.config.chunk, self.config.order = int(config.get("chunk", 0)), int(config.get("order", 0))
+        self.prepare()
+
+    def prepare(self):
+        lib.call("tfx_sos_batched_prepare", self.clips, self.n, self.config, _ptr(self.ws), self.wsb,
+                 _stream(self.device))
+
+    def run(self):
+        lib.call("tfx_sos_batched_run", self.clips, self.n, self.config, _ptr(self.ws), self.wsb,
+                 _stream(self.device))
+        return self.ys
+
+    def tune(self, reps: int = 3):
+        best, ms = lib.BatchConfig(0, 0), ctypes.c_float(0.0)
+        lib.call("tfx_sos_batched_tune", self.clips, self.n, reps, _ptr(self.ws), self.wsb, _stream(self.device),
+                 best, ms)
+        self.config = best
+        return {"chunk": best.chunk, "order": best.order}, float(ms.value)
+
+
+def sos_batched(xs, sections, config=None):
+    """Filter clip i ([C_i, N_i]) by its own cascade sections[i] ([S_i, 5]),
+    all clips in one launch; returns the list of outputs."""
+    b = SosBatch(xs, sections, config)
+    return b.run()

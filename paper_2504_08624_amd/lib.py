@@ -29,6 +29,16 @@ class TfxError(RuntimeError):
         super().__init__("%s failed: %s: %s" % (func, STATUS_NAMES.get(status, status), message))
 
 
+class Clip(ctypes.Structure):
+    _fields_ = [("x", ctypes.c_void_p), ("y", ctypes.c_void_p), ("C", ctypes.c_int64), ("N", ctypes.c_int64),
+                ("ldx", ctypes.c_int64), ("ldy", ctypes.c_int64), ("sos", ctypes.c_void_p), ("S", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+class BatchConfig(ctypes.Structure):
+    _fields_ = [("chunk", ctypes.c_int32), ("order", ctypes.c_int32)]
+
+
 class Stage(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("len", ctypes.c_int32), ("coef", ctypes.c_void_p)]
 
@@ -57,6 +67,12 @@ _SIGS = {
     "tfx_fir_backward_workspace_size": (_i32, [_i64, _i64, _i32, _i32, _i32, ctypes.POINTER(_sz)]),
     "tfx_fir_backward": (_i32, [_vp, _vp, _vp, _i64, _i64, _i64, _i64, _i64, _vp, _i32, _vp, _i32, _i32, _vp,
                                 _sz, _vp]),
+    "tfx_sos_batched_workspace_size": (_i32, [ctypes.POINTER(Clip), _i32, ctypes.POINTER(_sz)]),
+    "tfx_sos_batched_prepare": (_i32, [ctypes.POINTER(Clip), _i32, ctypes.POINTER(BatchConfig), _vp, _sz, _vp]),
+    "tfx_sos_batched_run": (_i32, [ctypes.POINTER(Clip), _i32, ctypes.POINTER(BatchConfig), _vp, _sz, _vp]),
+    "tfx_sos_batched": (_i32, [ctypes.POINTER(Clip), _i32, ctypes.POINTER(BatchConfig), _vp, _sz, _vp]),
+    "tfx_sos_batched_tune": (_i32, [ctypes.POINTER(Clip), _i32, _i32, _vp, _sz, _vp, ctypes.POINTER(BatchConfig),
+                                    ctypes.POINTER(ctypes.c_float)]),
     "tfx_sos_backward_workspace_size": (_i32, [_i64, _i64, _i32, ctypes.POINTER(_sz)]),
     "tfx_sos_backward": (_i32, [_vp, _vp, _vp, _i64, _i64, _i64, _i64, _i64, _vp, _i32, _vp, _vp, _vp, _sz,
                                 _vp]),

@@ -121,3 +121,21 @@ def test_backward_workspace_sizes():
     assert n.value >= fwd.value + 2 * 8 * 5_760_000 * 4 and n.value % 256 == 0
     assert _st("tfx_sos_backward_workspace_size", 2, 1000, 3, ctypes.byref(n)) == "TFX_OK" and n.value > 0
     assert _st("tfx_fir_backward_workspace_size", 2, 1000, 64, 0, 0, ctypes.byref(n)) == "TFX_OK" and n.value > 0
+
+
+def test_batched_validation_and_sizes():
+    L = lib.load()
+    clips = (lib.Clip * 2)()
+    for i in range(2):
+        clips[i].x, clips[i].y = FAKE + (i << 32), FAKE + (i << 32) + (1 << 30)
+        clips[i].C, clips[i].N, clips[i].ldx, clips[i].ldy = 3, 10000, 10000, 10000
+        clips[i].sos, clips[i].S = FAKE, 2 + i
+    n = ctypes.c_size_t(0)
+    assert _st("tfx_sos_batched_workspace_size", clips, 2, ctypes.byref(n)) == "TFX_OK" and n.value > 0
+    cfg = lib.BatchConfig(20, 0)
+    assert _st("tfx_sos_batched_prepare", clips, 2, ctypes.byref(cfg), None, 0, None) == "TFX_E_INVALID_ARG"
+    cfg = lib.BatchConfig(16, 0)
+    assert _st("tfx_sos_batched_prepare", clips, 2, ctypes.byref(cfg), None, 0, None) == "TFX_E_WORKSPACE"
+    clips[1].y = clips[1].x + 8                                    # output overlaps the input
+    assert _st("tfx_sos_batched_workspace_size", clips, 2, ctypes.byref(n)) == "TFX_E_ALIAS"
+    assert b"clip 1" in L.tfx_last_error()
