@@ -51,11 +51,18 @@
 namespace tfx {
 
 constexpr int DIRECT_GROUP_FLOATS = ((T + KBLK_MAX + L - 1) / L + 1) * CSTRIDE;
+// kernel variant of FIR_FFT for filters of more than one tap partition
+constexpr int FIR_FFT_PARTS = 4;
+
+template <int FIRM>
+constexpr bool is_fft() { return FIRM == FIR_FFT || FIRM == FIR_FFT_PARTS; }
 
 template <int FIRM>
 constexpr int lds_floats() {
+    // the partitioned FFT keeps its spectrum accumulator in LDS after the
+    // FFT buffers
     return FIRM == FIR_DIRECT ? GROUPS * DIRECT_GROUP_FLOATS
-                              : (FIRM == FIR_FFT ? 2 * NFFT : GROUPS * STG_FLOATS);
+                              : (FIRM == FIR_FFT_PARTS ? 4 * NFFT : (FIRM == FIR_FFT ? 2 * NFFT : GROUPS * STG_FLOATS));
 }
 static_assert(GROUPS * STG_FLOATS <= 2 * NFFT, "staging must fit in the FFT buffers");
 
@@ -80,43 +87,59 @@ struct KArgs {
     int32_t nparts;
 };
 
-// Overlap-save block of the pair, uniformly partitioned: the taps are cut
-// into partitions of 1025 (partition p = taps [1025 p, 1025 p + 1025)), each
-// filtering its own 4096-sample input block; the products with the partition
-// spectra are summed in the frequency domain and inverted once.
-// Convolution: block p starts 1024 + 1025 p samples before the tile and
-// outputs c[256 a + t], a = 4..15, are the tile.  Correlation (the FIR
-// adjoint, spectra conjugated): block p starts 1025 p samples after the tile
-// start and outputs a = 0..11 are the tile.
+// Overlap-save block of the pair.  Convolution: the block starts 1024 samples
+// before the tile and outputs c[256 a + t], a = 4..15, are the tile.
+// Correlation (the FIR adjoint, spectrum conjugated): the block starts at the
+// tile and outputs a = 0..11 are the tile.  Filters longer than 1025 taps
+// (PARTS) are uniformly partitioned: partition p = taps [1025 p, 1025 p +
+// 1025) filters its own input block, shifted by 1025 p samples (earlier for
+// the convolution, later for the correlation); the products with the
+// partition spectra are summed in the frequency domain and inverted once.
+template <bool PARTS>
 __device__ void fft_block(const KArgs &a, float *lds, int64_t pair, int64_t n0, int tid, float (&zr)[16],
                           float (&zi)[16]) {
     const int64_t chA = 2 * pair, chB = 2 * pair + 1;
     const float *xA = a.x + chA * a.ldx;
     const float *xB = chB < a.C ? a.x + chB * a.ldx : nullptr;
-    float ar[16], ai[16];
-    for (int p = 0; p < a.nparts; ++p) {
-        const int64_t shift = (int64_t)FFT_PART * p;
-        if (p > 0) __syncthreads();  // the previous partition's last LDS reads
-        load_pair_block(zr, zi, xA, xB, a.correlate ? n0 + shift : n0 - FFT_DISCARD - shift, a.N, a.N, tid);
+    const int64_t base = a.correlate ? n0 : n0 - FFT_DISCARD;
+    if (!PARTS) {
+        load_pair_block(zr, zi, xA, xB, base, a.N, a.N, tid);
         fft4096_forward(zr, zi, lds, a.twid, tid);
-        const float2 *hs = a.hspec + (int64_t)p * NFFT;
         if (a.correlate) {
 #pragma unroll
-            for (int k3 = 0; k3 < 16; ++k3) cmul_tw<true>(zr[k3], zi[k3], hs[tid + 256 * k3]);
+            for (int k3 = 0; k3 < 16; ++k3) cmul_tw<true>(zr[k3], zi[k3], a.hspec[tid + 256 * k3]);
         } else {
 #pragma unroll
-            for (int k3 = 0; k3 < 16; ++k3) cmul_tw<false>(zr[k3], zi[k3], hs[tid + 256 * k3]);
+            for (int k3 = 0; k3 < 16; ++k3) cmul_tw<false>(zr[k3], zi[k3], a.hspec[tid + 256 * k3]);
+        }
+    } else {
+        // spectrum accumulator: lane t owns bins t + 256 k3 (no sharing, no
+        // barrier), after the two FFT buffers
+        float2 *acc = reinterpret_cast<float2 *>(lds + 2 * NFFT);
+#pragma unroll 1
+        for (int p = 0; p < a.nparts; ++p) {
+            const int64_t shift = (int64_t)FFT_PART * p;
+            __syncthreads();  // the previous pass's last LDS reads
+            load_pair_block(zr, zi, xA, xB, a.correlate ? base + shift : base - shift, a.N, a.N, tid);
+            fft4096_forward(zr, zi, lds, a.twid, tid);
+            const float2 *hs = a.hspec + (int64_t)p * NFFT;
+            const float sg = a.correlate ? -1.f : 1.f;
+#pragma unroll 4
+            for (int k3 = 0; k3 < 16; ++k3) {
+                const float2 w = hs[tid + 256 * k3];
+                const float wi = sg * w.y;
+                float2 s = p ? acc[tid + 256 * k3] : make_float2(0.f, 0.f);
+                s.x = fmaf(zr[k3], w.x, fmaf(-zi[k3], wi, s.x));
+                s.y = fmaf(zr[k3], wi, fmaf(zi[k3], w.x, s.y));
+                acc[tid + 256 * k3] = s;
+            }
         }
 #pragma unroll
         for (int k3 = 0; k3 < 16; ++k3) {
-            ar[k3] = p ? ar[k3] + zr[k3] : zr[k3];
-            ai[k3] = p ? ai[k3] + zi[k3] : zi[k3];
+            const float2 s = acc[tid + 256 * k3];
+            zr[k3] = s.x;
+            zi[k3] = s.y;
         }
-    }
-#pragma unroll
-    for (int k3 = 0; k3 < 16; ++k3) {
-        zr[k3] = ar[k3];
-        zi[k3] = ai[k3];
     }
     fft4096_inverse(zr, zi, lds, a.twid, tid);
     if (a.correlate) {  // move the tile to a = 4..15 like the convolution case
@@ -139,8 +162,8 @@ struct TileCtx {
 // One section over the group's tile: zero-state response, carry, then the
 // zero-input response of each chunk-entering state added in place.  s_agg /
 // s_pre are double-buffered by section parity (no barrier needed at the end).
-template <typename CT>
-__device__ void run_section(const KArgs &a, const SecTab &tb, int s, float (&v)[L], const TileCtx &c,
+template <typename CT, class TB>
+__device__ void run_section(const KArgs &a, const TB &tb, int s, float (&v)[L], const TileCtx &c,
                             double (*s_agg)[GWAVES][2], double (*s_pre)[2]) {
     const float b0 = tb.coef[0], b1 = tb.coef[1], b2 = tb.coef[2];
     const float a1 = tb.coef[3], a2 = tb.coef[4];
@@ -186,7 +209,7 @@ __device__ void run_section(const KArgs &a, const SecTab &tb, int s, float (&v)[
     }
     cc.prefix_out = (a.ckpt && c.valid) ? a.ckpt + ((c.ch * a.ntiles + c.tile) * a.S + s) * 2 : nullptr;
     float z1, z2;
-    carry<CT, false>(tb, cc, s1, s2, z1, z2, s_agg, s_pre, (s & 1) * GROUPS + c.grp);
+    carry<CT, false, TB>(tb, cc, s1, s2, z1, z2, s_agg, s_pre, (s & 1) * GROUPS + c.grp);
     if (c.is_last) {
 #pragma unroll
         for (int r = 0; r < L; ++r) {
@@ -220,6 +243,7 @@ __global__ __launch_bounds__(WG) void chain_kernel(KArgs a) {
     __shared__ double s_agg[2 * GROUPS][GWAVES][2];
     __shared__ double s_pre[2 * GROUPS][2];
     __shared__ uint32_t s_epoch;
+    extern __shared__ __align__(16) SecLds s_tab[];  // fp32 tables of up to LDS_SECTIONS sections
 
     TileCtx c;
     c.tid = threadIdx.x;
@@ -231,6 +255,8 @@ __global__ __launch_bounds__(WG) void chain_kernel(KArgs a) {
     c.epoch = 0;
     if (HAS_SOS) {
         if (c.tid == 0) s_epoch = load_epoch(a.hdr, HDR_EPOCH);
+        // the tables' loads overlap the FIR part of the tile
+        stage_tables(s_tab, a.tab, 0, min(a.S, LDS_SECTIONS), c.tid, WG);
         __syncthreads();
         c.epoch = s_epoch;
     }
@@ -309,7 +335,7 @@ __global__ __launch_bounds__(WG) void chain_kernel(KArgs a) {
         for (int r = 0; r < L; ++r) v[r] = acc[r];
     } else {  // FIR_FFT
         float zr[16], zi[16];
-        fft_block(a, lds, pair, n0, c.tid, zr, zi);
+        fft_block<FIRM == FIR_FFT_PARTS>(a, lds, pair, n0, c.tid, zr, zi);
         if (!HAS_SOS) {
             const int64_t chA = 2 * pair, chB = chA + 1;
             float *yA = a.y + chA * a.ldy;
@@ -342,11 +368,16 @@ __global__ __launch_bounds__(WG) void chain_kernel(KArgs a) {
         c.r_last = c.is_last ? (int)(plast % L) : 0;
         c.owner = c.is_last ? (int)(plast / L) : -1;
         for (int s = 0; s < a.S; ++s) {
-            const SecTab &tb = a.tab[s];
-            if (tb.hiq)
-                run_section<double>(a, tb, s, v, c, s_agg, s_pre);
+            if (s > 0 && s % LDS_SECTIONS == 0) {  // next block of tables
+                __syncthreads();
+                stage_tables(s_tab, a.tab, s, min(a.S - s, LDS_SECTIONS), c.tid, WG);
+                __syncthreads();
+            }
+            const SecLds &tl = s_tab[s % LDS_SECTIONS];
+            if (tl.hiq)
+                run_section<double>(a, a.tab[s], s, v, c, s_agg, s_pre);
             else
-                run_section<float>(a, tb, s, v, c, s_agg, s_pre);
+                run_section<float>(a, tl, s, v, c, s_agg, s_pre);
         }
     }
 
@@ -403,7 +434,8 @@ hipError_t launch_state_passthrough(const float *in, float *out, int64_t n, hipS
 
 template <int F, bool S>
 static hipError_t launch_main(const KArgs &k, int64_t nblocks, hipStream_t st) {
-    hipLaunchKernelGGL((chain_kernel<F, S>), dim3((unsigned)nblocks), dim3(WG), 0, st, k);
+    const size_t dyn = S ? sizeof(SecLds) * (size_t)(k.S < LDS_SECTIONS ? k.S : LDS_SECTIONS) : 0;
+    hipLaunchKernelGGL((chain_kernel<F, S>), dim3((unsigned)nblocks), dim3(WG), dyn, st, k);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !S) return e;
     hipLaunchKernelGGL(bump_epoch_kernel, dim3(1), dim3(1), 0, st, k.hdr, (int)HDR_EPOCH);
@@ -480,8 +512,12 @@ hipError_t launch_run(const ChainPlan &p) {
     switch (Mtot > 0 ? p.fir_mode : FIR_NONE) {
         case FIR_DIRECT: return s ? launch_main<FIR_DIRECT, true>(k, nblocks, p.stream)
                                   : launch_main<FIR_DIRECT, false>(k, nblocks, p.stream);
-        case FIR_FFT: return s ? launch_main<FIR_FFT, true>(k, nblocks, p.stream)
-                               : launch_main<FIR_FFT, false>(k, nblocks, p.stream);
+        case FIR_FFT:
+            if (k.nparts > 1)
+                return s ? launch_main<FIR_FFT_PARTS, true>(k, nblocks, p.stream)
+                         : launch_main<FIR_FFT_PARTS, false>(k, nblocks, p.stream);
+            return s ? launch_main<FIR_FFT, true>(k, nblocks, p.stream)
+                     : launch_main<FIR_FFT, false>(k, nblocks, p.stream);
         default: return s ? launch_main<FIR_NONE, true>(k, nblocks, p.stream)
                           : launch_main<FIR_NONE, false>(k, nblocks, p.stream);
     }
@@ -513,6 +549,7 @@ hipError_t launch_fir_pass(const ChainPlan &p, const WsLayout &lay, const float 
     k.hspec = reinterpret_cast<const float2 *>(ws + lay.hspec);
     k.nparts = fft_parts(Mtot);
     const int64_t nblocks = (lay.cpad / 2) * lay.ntiles;
+    if (p.fir_mode == FIR_FFT && k.nparts > 1) return launch_main<FIR_FFT_PARTS, false>(k, nblocks, p.stream);
     return p.fir_mode == FIR_FFT ? launch_main<FIR_FFT, false>(k, nblocks, p.stream)
                                  : launch_main<FIR_DIRECT, false>(k, nblocks, p.stream);
 }

@@ -90,17 +90,29 @@ __device__ __forceinline__ void madd2(CT &w0, CT &w1, const CT *P, CT t0, CT t1)
     w1 = n1;
 }
 
+// Table access by carry precision; the fp32 tables may sit in a SecTab
+// (global memory) or in its LDS copy (SecLds).
 template <typename CT> struct Tab;
 template <> struct Tab<float> {
-    static __device__ __forceinline__ const float *fold(const SecTab &t, int k) { return t.fold[k]; }
-    static __device__ __forceinline__ const float *psi(const SecTab &t, int w) { return t.psi[w]; }
-    static __device__ __forceinline__ const float *lb(const SecTab &t, int j) { return t.lb[j]; }
+    template <class TB> static __device__ __forceinline__ const float *fold(const TB &t, int k) { return t.fold[k]; }
+    template <class TB> static __device__ __forceinline__ const float *psi(const TB &t, int w) { return t.psi[w]; }
+    template <class TB> static __device__ __forceinline__ const float *lb(const TB &t, int j) { return t.lb[j]; }
 };
 template <> struct Tab<double> {
     static __device__ __forceinline__ const double *fold(const SecTab &t, int k) { return t.fold_d[k]; }
     static __device__ __forceinline__ const double *psi(const SecTab &t, int w) { return t.psi_d[w]; }
     static __device__ __forceinline__ const double *lb(const SecTab &t, int j) { return t.lb_d[j]; }
 };
+
+// Copies the fp32 tables of sections [s0, s0 + n) into LDS (whole
+// workgroup; the caller synchronises before and after).
+__device__ __forceinline__ void stage_tables(SecLds *dst, const SecTab *src, int s0, int n, int tid, int nthreads) {
+    constexpr int V = sizeof(SecLds) / 16;
+    for (int e = tid; e < n * V; e += nthreads) {
+        const int s = e / V, i = e % V;
+        reinterpret_cast<float4 *>(&dst[s])[i] = reinterpret_cast<const float4 *>(&src[s0 + s])[i];
+    }
+}
 
 // ------------------------------------------------------------------ staging
 // LDS layout of lane chunks of LC samples: LC samples then 4 floats of
@@ -388,8 +400,8 @@ struct CarryCtx {
 // predecessor pos-1-l (a window of 64 tiles per step); a lane stops
 // re-reading its record once the aggregate or the prefix is out, so the spin
 // costs one 32-byte read per still-missing predecessor.
-template <typename CT, bool TR>
-__device__ void lookback(const SecTab &tb, const CarryCtx &cc, CT agg0, CT agg1, CT &P0, CT &P1) {
+template <typename CT, bool TR, class TB>
+__device__ void lookback(const TB &tb, const CarryCtx &cc, CT agg0, CT agg1, CT &P0, CT &P1) {
     const int lane = cc.lane;
     publish(cc.recs, cc.rec0 + cc.pos * cc.rstride, 0, cc.epoch, (float)agg0, (float)agg1, lane);
     CT acc0 = 0, acc1 = 0;
@@ -466,8 +478,8 @@ __device__ void lookback(const SecTab &tb, const CarryCtx &cc, CT agg0, CT agg1,
 // into every chunk with the table of Phi^k.  Contains two workgroup
 // barriers; s_agg / s_pre slot `buf` must not be in use by a neighbouring
 // call (callers alternate two slots).
-template <typename CT, bool TR>
-__device__ void carry(const SecTab &tb, const CarryCtx &cc, float z0, float z1, float &e0, float &e1,
+template <typename CT, bool TR, class TB>
+__device__ void carry(const TB &tb, const CarryCtx &cc, float z0, float z1, float &e0, float &e1,
                       double (*s_agg)[GWAVES][2], double (*s_pre)[2], int buf) {
     const int lane = cc.lane;
     CT w0 = (CT)z0, w1 = (CT)z1;
@@ -513,7 +525,7 @@ __device__ void carry(const SecTab &tb, const CarryCtx &cc, float z0, float z1, 
     if (cc.gw == 0) {
         CT P0 = (CT)cc.known0, P1 = (CT)cc.known1;
         if (cc.lookback) {
-            if (cc.pos > 0) lookback<CT, TR>(tb, cc, E0, E1, P0, P1);
+            if (cc.pos > 0) lookback<CT, TR, TB>(tb, cc, E0, E1, P0, P1);
             CT i0 = E0, i1 = E1;
             madd2<TR>(i0, i1, Tab<CT>::lb(tb, 0), P0, P1);  // PhiT P + E
             publish(cc.recs, cc.rec0 + cc.pos * cc.rstride, 1, cc.epoch, (float)i0, (float)i1, lane);

@@ -54,6 +54,20 @@ struct alignas(16) SecTab {
     double lb_d[9][4];
 };
 
+// The fp32 part of a SecTab (its leading members, same layout): what a
+// workgroup copies into LDS for the sections it carries in fp32.
+struct alignas(16) SecLds {
+    float coef[5];
+    int32_t hiq;
+    int32_t pad[2];
+    float fold[64][4];
+    float psi[GWAVES][4];
+    float lb[9][4];
+};
+static_assert(offsetof(SecTab, lb) == offsetof(SecLds, lb), "SecLds must be the leading part of SecTab");
+static_assert(sizeof(SecLds) <= offsetof(SecTab, fold_d), "SecLds must be the leading part of SecTab");
+constexpr int LDS_SECTIONS = 32;  // sections staged in LDS at a time
+
 struct StageList {
     const float *ptr[MAX_STAGES];
     int32_t len[MAX_STAGES];
