@@ -1,22 +1,33 @@
-"""Throughput of the fused FIR -> IIR-SOS chain on one MI355X.
+"""Throughput of the multichannel FIR -> IIR-SOS chain on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--quick] [--no-cpu-baseline]
 
-Workload (the mid-size chain): 8 channels x 5,760,000 samples (120 s at
-48 kHz), fp32, per-channel seeded 1/f noise plus a 20 Hz-20 kHz log sweep;
-chain = 1023-tap Hamming band-pass FIR | 8th-order Chebyshev-I low-pass
-(4 sections) | 2 peaking EQs, i.e. one FIR plus a 6-section cascade.
+Headline workload (the mid-size chain): 8 channels x 5,760,000 samples
+(120 s at 48 kHz), fp32, per-channel seeded 1/f noise plus a 20 Hz-20 kHz log
+sweep; chain = 1023-tap Hamming band-pass FIR | 8th-order Chebyshev-I
+low-pass (4 sections) | 2 peaking EQs: one FIR plus a 6-section cascade.
 
 A step is one full tfx_chain call on the resident input: the device table
 build (tfx_chain_prepare) followed by the fused filter kernel
 (tfx_chain_run).  W untimed steps, then K timed steps between two device
-synchronisations.  HIP events recorded on the launch stream around every
-tfx_chain_run give the dominant kernel's average duration for the roofline
-(algorithmic bytes = 8 B per channel-sample: read x once, write y once).
+synchronisations; `value` is channel-samples per second of the whole step.
+HIP events recorded on the launch stream around every tfx_chain_run give the
+fused kernel's average duration for the roofline (algorithmic bytes = 8 B
+per channel-sample: read x once, write y once).  The same loop is then timed
+for forward + backward (forward with tile checkpoints, then the adjoint of
+the chain for a fixed upstream gradient: gradients of input, taps and
+sections).
 
-The CPU baseline runs the FP64 oracle (test infrastructure, plain C with one
-OpenMP thread per channel) on the same input and reports its throughput and
-the GPU result's error against it.  Prints one JSON line.
+Unless --quick, the other workloads are measured once each (context, in
+"secondary"): the short chain, the 8191-tap FIR by FFT (fp32) and by the
+matrix-core Toeplitz product (bf16, fp16, split bf16), the ragged batch of
+256 clips (autotuned single launch, against one tfx_sos call per clip), and
+the differentiable workload's forward + backward.  Low-precision errors are
+measured against the oracle on sampled outputs.
+
+The CPU baseline runs the FP64 oracle (test infrastructure: plain C, one
+OpenMP thread per channel) on a bounded sample of the headline input and
+reports its throughput.  Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -31,7 +42,23 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-HBM_PEAK_GBS = 8000.0  # MI355X published HBM3E bandwidth
+HBM_PEAK_GBS = 8000.0        # MI355X published HBM3E bandwidth
+MFMA_BF16_PEAK_TFS = 2500.0  # dense bf16 / fp16 matrix peak
+# fp32 vector peak without packed-FP32 instructions (disabled at build time):
+# 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz
+VALU_F32_PEAK_TFS = 78.6
+
+
+def chain_flops_per_sample(M, S):
+    """Algorithmic flops per channel-sample of the fused FFT-FIR + SOS kernel:
+    per 6144 channel-samples (one channel pair, one 3072-sample tile) one
+    4096-point complex FFT per tap partition of 1025 plus one inverse
+    (5 N log2 N each) and the spectrum products (6 flops per bin and
+    partition); per section 9 (TDF-II) + 4 (zero-input correction) + 2 (scan
+    and fold)."""
+    parts = (M + 1024) // 1025
+    fft = (parts + 1) * 5 * 4096 * 12 + parts * 6 * 4096
+    return fft / 6144.0 + 15.0 * S
 
 
 def parse():
@@ -39,10 +66,109 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--quick", action="store_true", help="headline workload only")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
-                    help="also time a plain device copy of the same size (bandwidth reference)")
+                    help="also time a plain device copy of the headline input (counter calibration)")
     return ap.parse_args()
+
+
+def log(msg):
+    print("bench: " + msg, file=sys.stderr, flush=True)
+
+
+def rel_err(y, ref):
+    num = np.linalg.norm(np.asarray(y, np.float64) - ref, axis=-1)
+    den = np.linalg.norm(ref, axis=-1)
+    return float((num / np.where(den > 0, den, 1.0)).max())
+
+
+def timed(torch, fn, reps, stream):
+    for _ in range(2):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / reps
+
+
+def secondary(torch, dev, stream):
+    import paper_2504_08624_amd as tfx
+    from oracle import oracle as O
+    from paper_2504_08624_amd import workloads
+    out = {}
+
+    log("chain_short")
+    w = workloads.chain_short()
+    x = torch.from_numpy(w.x).to(dev)
+    st = [(k, torch.from_numpy(c).to(dev)) for k, c in w.stages]
+    s = timed(torch, lambda: tfx.chain(x, st), 20, stream)
+    y = tfx.chain(x, st).cpu().numpy()
+    out["chain_short"] = {"workload": "2 x 480,000, 101-tap FIR | Butterworth HP (2 SOS)",
+                          "Msamples_per_s": round(x.numel() / s / 1e6, 1), "ms": round(s * 1e3, 4),
+                          "rel_err": rel_err(y, O.chain(w.x, w.stages)), "tolerance": 1e-4}
+    del x, st
+
+    log("fir_long")
+    w = workloads.fir_long()
+    x = torch.from_numpy(w.x).to(dev)
+    h = torch.from_numpy(w.stages[0][1]).to(dev)
+    n = x.numel()
+    M = h.numel()
+    pos = np.linspace(0, w.x.shape[1] - 1, 257).astype(np.int64)
+    chans = [0, 21, 63]
+    ref = O.fir_at(w.x[chans], w.stages[0][1], pos)
+    res = {"workload": "64 x 5,760,000, 8191-tap low-pass", "error": "rel RMS on 3 ch x 257 sampled outputs"}
+    for name, kw, tol in [("fft_f32", {}, 1e-5), ("toeplitz_bf16", {"compute": "bf16"}, 1e-2),
+                          ("toeplitz_f16", {"compute": "f16"}, 1e-2), ("toeplitz_bf16x3", {"compute": "bf16x3"}, None)]:
+        s = timed(torch, lambda: tfx.fir(x, h, **kw), 3, stream)
+        yy = tfx.fir(x, h, **kw)[chans][:, pos].cpu().numpy()
+        e = {"Msamples_per_s": round(n / s / 1e6, 1), "ms": round(s * 1e3, 3), "rel_err": rel_err(yy, ref)}
+        if tol:
+            e["tolerance"] = tol
+        if name.startswith("toeplitz"):
+            flops = 2.0 * n * M * (3 if name.endswith("x3") else 1)
+            e["mfma_TFLOP_per_s"] = round(flops / s / 1e12, 1)
+            e["mfma_frac"] = round(flops / s / 1e12 / MFMA_BF16_PEAK_TFS, 4)
+        res[name] = e
+    out["fir_long"] = res
+    del x, h
+
+    log("ragged batch")
+    clips = workloads.ragged()
+    xs = [torch.from_numpy(c[0]).to(dev) for c in clips]
+    ss = [torch.from_numpy(c[1]).to(dev) for c in clips]
+    n = sum(t.numel() for t in xs)
+    b = tfx.SosBatch(xs, ss)
+    cfg, _ = b.tune(reps=2)
+    s_b = timed(torch, b.run, 5, stream)
+    s_l = timed(torch, lambda: [tfx.sos(a, c) for a, c in zip(xs, ss)], 3, stream)
+    ys = b.run()
+    errs = [rel_err(ys[i].cpu().numpy(), O.sos(clips[i][0], clips[i][1])) for i in (0, 97, 201)]
+    out["ragged_batch"] = {"workload": "256 clips @44.1 kHz, 1-30 s, 1-16 ch, 1-6 SOS each",
+                           "samples": n, "tuned": cfg, "Msamples_per_s": round(n / s_b / 1e6, 1),
+                           "ms": round(s_b * 1e3, 3), "per_clip_calls_ms": round(s_l * 1e3, 3),
+                           "speedup_vs_per_clip": round(s_l / s_b, 2), "rel_err_3_clips": max(errs),
+                           "tolerance": 1e-4}
+    del xs, ss, b, ys
+
+    log("learnable fwd+bwd")
+    x_np, params, target = workloads.learnable()
+    x = torch.from_numpy(x_np).to(dev)
+    hh = torch.from_numpy(params["h"]).to(dev).requires_grad_(True)
+    sec = torch.from_numpy(target[1][1]).to(dev).requires_grad_(True)
+    tgt = torch.from_numpy(O.chain(x_np, target).astype(np.float32)).to(dev)
+
+    def step():
+        yv = tfx.chain(x, [("fir", hh), ("sos", sec)])
+        loss = torch.mean((yv - tgt) ** 2)
+        loss.backward()
+    s = timed(torch, step, 10, stream)
+    out["learnable"] = {"workload": "64 x 192,000, 255-tap FIR + 8 SOS, MSE loss, grads of taps and sections",
+                        "fwd_bwd_ms": round(s * 1e3, 3), "Msamples_per_s": round(x.numel() / s / 1e6, 1)}
+    return out
 
 
 def main():
@@ -55,12 +181,13 @@ def main():
 
     import torch
 
+    import paper_2504_08624_amd as tfx
     from paper_2504_08624_amd import lib, workloads
     from paper_2504_08624_amd.functional import _stages
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    print("bench: generating chain_mid inputs (8 x 5,760,000)", file=sys.stderr, flush=True)
+    log("generating chain_mid inputs (8 x 5,760,000)")
     w = workloads.chain_mid()
     C, N = w.x.shape
     x = torch.from_numpy(w.x).to(dev)
@@ -82,7 +209,7 @@ def main():
         lib.check(L.tfx_chain_run(x.data_ptr(), y.data_ptr(), C, N, N, N, arr, nst, 0, None,
                                   ws.data_ptr(), ws.numel(), sp), "tfx_chain_run")
 
-    print("bench: warmup %d" % args.warmup, file=sys.stderr, flush=True)
+    log("warmup %d" % args.warmup)
     for _ in range(args.warmup):
         prepare()
         run()
@@ -101,14 +228,19 @@ def main():
     t1 = time.perf_counter()
     wall = t1 - t0
     kern_ms = np.array([a.elapsed_time(b) for a, b in ev])
-    print("bench: timed %d steps in %.3f s" % (K, wall), file=sys.stderr, flush=True)
+    log("timed %d forward steps in %.3f s" % (K, wall))
 
     samples = C * N
     ms_step = wall / K * 1e3
     value = samples / (wall / K) / 1e6
     alg_bytes = 8.0 * samples
+    S_tot = int(sum(s[1].shape[0] for s in w.stages if s[0] == "sos"))
+    fps = chain_flops_per_sample(int(w.stages[0][1].size), S_tot)
+    alg_flops = fps * samples
     kern_s = float(kern_ms.mean()) / 1e3
-    achieved = alg_bytes / kern_s / 1e9
+    achieved_gbs = alg_bytes / kern_s / 1e9
+    achieved_tfs = alg_flops / kern_s / 1e12
+    out = y.cpu().numpy()
 
     copy = None
     if args.copy_probe:
@@ -122,10 +254,34 @@ def main():
         b.record(stream)
         torch.cuda.synchronize()
         cs = a.elapsed_time(b) / 10 / 1e3
-        copy = {"bytes": 2 * 4 * samples, "us": cs * 1e6, "GB/s": 2 * 4 * samples / cs / 1e9}
+        copy = {"bytes": 2 * 4 * samples, "us": round(cs * 1e6, 2), "GB/s": round(2 * 4 * samples / cs / 1e9, 1)}
         del z
 
-    out = y.cpu().numpy()
+    # forward + backward on the same workload
+    st = [(k, t) for (k, _), t in zip(w.stages, kept)]
+    g = torch.from_numpy(np.random.default_rng(11).standard_normal((C, N)).astype(np.float32)).to(dev)
+
+    def fwd_bwd():
+        yv, ck = tfx.chain(x, st, return_ckpt=True)
+        return tfx.chain_backward(x, g, st, ck)
+    for _ in range(args.warmup):
+        fwd_bwd()
+    torch.cuda.synchronize()
+    kb = max(5, K // 5)
+    t0 = time.perf_counter()
+    for _ in range(kb):
+        fwd_bwd()
+    torch.cuda.synchronize()
+    fb = (time.perf_counter() - t0) / kb
+    log("timed %d forward+backward steps" % kb)
+    fwd_bwd_rec = {"Msamples_per_s": round(samples / fb / 1e6, 3), "ms_per_step": round(fb * 1e3, 4),
+                   "ratio_to_fwd": round((samples / fb / 1e6) / value, 4),
+                   "step": "tfx_chain with checkpoints + tfx_chain_backward (input, taps, sections)"}
+    del g
+
+    sec = None
+    if not args.quick:
+        sec = secondary(torch, dev, stream)
 
     cpu = None
     err = None
@@ -133,19 +289,19 @@ def main():
         from oracle import oracle as O
         O.build()
         threads = min(C, len(os.sched_getaffinity(0)), int(os.environ.get("OMP_NUM_THREADS", "1024")))
-        print("bench: oracle on the full input (%d threads)" % threads, file=sys.stderr, flush=True)
+        Ns = 1_440_000  # the first 30 s of every channel
+        log("oracle on 8 x %d samples (%d threads)" % (Ns, threads))
         c0 = time.perf_counter()
-        ref = O.chain(w.x, w.stages)
+        ref = O.chain(w.x[:, :Ns], w.stages)
         c1 = time.perf_counter()
-        cpu = {"value": samples / (c1 - c0) / 1e6, "unit": "Msamples/s", "cores": threads,
+        cpu = {"value": round(C * Ns / (c1 - c0) / 1e6, 3), "unit": "Msamples/s", "cores": threads,
                "kind": "oracle",
-               "sample": "the full chain_mid input (8 x 5,760,000, all stages), FP64, %.1f s" % (c1 - c0)}
-        num = np.linalg.norm(out.astype(np.float64) - ref, axis=1)
-        den = np.linalg.norm(ref, axis=1)
-        err = float((num / den).max())
+               "sample": "the first 1,440,000 samples (30 s) of all 8 channels, whole chain, FP64, %.1f s"
+                         % (c1 - c0)}
+        err = rel_err(out[:, :Ns], ref)
 
     rec = {
-        "metric": "Msamples/s (ch x samples) fwd, % HBM roofline, at stated error",
+        "metric": "Msamples/s (ch x samples) fwd and fwd+bwd, % HBM roofline, at stated error",
         "value": round(value, 3),
         "unit": "Msamples/s",
         "n_gpus": 1,
@@ -161,15 +317,20 @@ def main():
                                "FIR 1023-tap band-pass | Chebyshev-I 8th order (4 SOS) | 2 peaking EQ",
                    "channels": C, "samples": N, "fir_taps": int(w.stages[0][1].size),
                    "sections": int(sum(s[1].shape[0] for s in w.stages if s[0] == "sos")),
-                   "fir_algo": "fft" if 48 < w.stages[0][1].size <= 1025 else "direct", "step": "tfx_chain_prepare + tfx_chain_run"},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                   "fir_algo": "fft", "step": "tfx_chain_prepare + tfx_chain_run"},
+        "roofline": {"bound": "alu", "achieved": round(achieved_tfs, 3), "peak": VALU_F32_PEAK_TFS,
+                     "unit": "TFLOP/s", "frac": round(achieved_tfs / VALU_F32_PEAK_TFS, 4), "traffic": None,
                      "kernel": "chain_kernel<FIR_FFT, true>", "kernel_us": round(kern_s * 1e6, 2),
-                     "alg_bytes_per_launch": alg_bytes},
+                     "alg_flops_per_launch": alg_flops, "alg_flops_per_sample": round(fps, 2),
+                     "alg_bytes_per_launch": alg_bytes, "hbm_achieved_GBps": round(achieved_gbs, 2),
+                     "hbm_peak_GBps": HBM_PEAK_GBS, "hbm_frac": round(achieved_gbs / HBM_PEAK_GBS, 4)},
+        "fwd_bwd": fwd_bwd_rec,
         "cpu_baseline": cpu,
         "max_rel_err_vs_oracle": err,
         "tolerance": 1e-4,
     }
+    if sec is not None:
+        rec["secondary"] = sec
     if copy is not None:
         rec["copy_probe"] = copy
     print(json.dumps(rec), flush=True)
