@@ -35,6 +35,9 @@ namespace tfx {
 
 struct BArgs {
     const float *f;   // cascade input (the chain input, or its FIR output)
+    const float *x;   // FFT_FIR: the chain input; the FIR output is recomputed per tile
+    int64_t ldx;
+    const float2 *twid, *hspec;
     const float *g;   // gradient of the cascade output
     float *gf;        // gradient of the cascade input
     int64_t C, N, ldf, ldg, ldo;
@@ -61,14 +64,23 @@ __device__ __forceinline__ void tdf2_chunk(float (&v)[L], const float *co, float
     }
 }
 
-__global__ __launch_bounds__(WG) void sos_bwd_kernel(BArgs a) {
-    __shared__ __align__(16) float stg_all[GROUPS * STG_FLOATS];
-    __shared__ float2 sig[GROUPS][BWD_MAX_SECTIONS][GL];  // chunk-entering forward states
+// HIQ: the variant with the FP64 carry; both are launched and the one that
+// does not match the workspace's high-Q word exits at once.  FFT_FIR: the
+// cascade input is the overlap-save FFT FIR output of the chain input,
+// recomputed for the tile here instead of read from memory.
+template <bool HIQ, bool FFT_FIR>
+__global__ __launch_bounds__(WG, 3) void sos_bwd_kernel(BArgs a) {
+    // staging of both groups' tiles, or the FFT buffers
+    __shared__ __align__(16) float stg_all[FFT_FIR ? 2 * NFFT : GROUPS * STG_FLOATS];
+    // dynamic: fp32 tables of the S sections, then the chunk-entering forward
+    // states sig[grp][s][chunk]
+    extern __shared__ __align__(16) SecLds s_tab[];
     __shared__ double s_agg[2 * GROUPS][GWAVES][2];
     __shared__ double s_pre[2 * GROUPS][2];
     __shared__ double s_red[2][GROUPS][GWAVES][5];
     __shared__ uint32_t s_epoch;
 
+    if ((a.hdr[HDR_HIQ] != 0u) != HIQ) return;
     const int tid = threadIdx.x, lane = tid & 63, grp = tid / GL, gl = tid % GL, gw = gl >> 6;
     if (tid == 0) s_epoch = load_epoch(a.hdr, HDR_EPOCH);
     const uint64_t npairs = (uint64_t)(a.cpad / 2);
@@ -81,10 +93,30 @@ __global__ __launch_bounds__(WG) void sos_bwd_kernel(BArgs a) {
     const int S = a.S;
     float *stg = stg_all + grp * STG_FLOATS;
     const int mc = GL - 1 - gl;  // the chunk this lane owns in reverse time
+    float2 *sig = reinterpret_cast<float2 *>(s_tab + S) + grp * S * GL;
+    stage_tables(s_tab, a.tab, 0, S, tid, WG);
 
     // 1. stage f; lanes take their forward chunk (gl) and their reverse-time
     //    chunk (mc)
-    stage_tile(stg, a.f + ch * a.ldf + n0, a.N - n0, valid, a.vecf != 0, gl);
+    if (FFT_FIR) {
+        float zr[16], zi[16];
+        const float *xA = a.x + 2 * pair * a.ldx;
+        const float *xB = 2 * pair + 1 < a.C ? xA + a.ldx : nullptr;
+        load_pair_block(zr, zi, xA, xB, n0 - FFT_DISCARD, a.N, a.N, tid);
+        fft4096_forward(zr, zi, stg_all, a.twid, tid);
+        spectrum_product(zr, zi, a.hspec, tid, false);
+        fft4096_inverse(zr, zi, stg_all, a.twid, tid);
+        __syncthreads();  // the FFT buffers become the two staging areas
+#pragma unroll
+        for (int q = 4; q < 16; ++q) {
+            const int j = 256 * (q - 4) + tid;
+            const bool in = n0 + j < a.N;  // zero past the signal, as staged input is
+            stg_all[cphys(j)] = in ? zr[q] : 0.f;
+            stg_all[STG_FLOATS + cphys(j)] = in ? zi[q] : 0.f;
+        }
+    } else {
+        stage_tile(stg, a.f + ch * a.ldf + n0, a.N - n0, valid, a.vecf != 0, gl);
+    }
     __syncthreads();
     const uint32_t epoch = s_epoch;
     float v[L], fr[L];
@@ -94,7 +126,7 @@ __global__ __launch_bounds__(WG) void sos_bwd_kernel(BArgs a) {
     // 2. forward recompute from the checkpointed tile-entering states,
     //    recording every section's chunk-entering state
     for (int s = 0; s < S; ++s) {
-        const SecTab &tb = a.tab[s];
+        const SecLds &tb = s_tab[s];
         const float b0 = tb.coef[0], b1 = tb.coef[1], b2 = tb.coef[2], a1 = tb.coef[3], a2 = tb.coef[4];
         float s1 = 0.f, s2 = 0.f;
 #pragma unroll
@@ -120,11 +152,11 @@ __global__ __launch_bounds__(WG) void sos_bwd_kernel(BArgs a) {
         cc.known1 = valid ? a.ckpt[((ch * a.ntiles + tile) * S + s) * 2 + 1] : 0.0;
         cc.prefix_out = nullptr;
         float z1, z2;
-        if (tb.hiq)
-            carry<double, false>(tb, cc, s1, s2, z1, z2, s_agg, s_pre, (s & 1) * GROUPS + grp);
+        if (HIQ && tb.hiq)
+            carry<double, false>(a.tab[s], cc, s1, s2, z1, z2, s_agg, s_pre, (s & 1) * GROUPS + grp);
         else
             carry<float, false>(tb, cc, s1, s2, z1, z2, s_agg, s_pre, (s & 1) * GROUPS + grp);
-        sig[grp][s][gl] = make_float2(z1, z2);
+        sig[s * GL + gl] = make_float2(z1, z2);
         if (s + 1 < S) {
 #pragma unroll
             for (int r = 0; r < L; ++r) {
@@ -144,7 +176,7 @@ __global__ __launch_bounds__(WG) void sos_bwd_kernel(BArgs a) {
 
     // 4. sections in reverse order
     for (int s = S - 1; s >= 0; --s) {
-        const SecTab &tb = a.tab[s];
+        const SecLds &tb = s_tab[s];
         const float b0 = tb.coef[0], b1 = tb.coef[1], b2 = tb.coef[2], a1 = tb.coef[3], a2 = tb.coef[4];
         const float B0 = fmaf(-a1, b0, b1), B1 = fmaf(-a2, b0, b2);
         // (a) input of section s over chunk mc, and s1 before every sample
@@ -152,11 +184,11 @@ __global__ __launch_bounds__(WG) void sos_bwd_kernel(BArgs a) {
 #pragma unroll
         for (int r = 0; r < L; ++r) xs[r] = fr[r];
         for (int j = 0; j < s; ++j) {
-            const float2 st = sig[grp][j][mc];
-            tdf2_chunk(xs, a.tab[j].coef, st.x, st.y);
+            const float2 st = sig[j * GL + mc];
+            tdf2_chunk(xs, s_tab[j].coef, st.x, st.y);
         }
         {
-            const float2 st = sig[grp][s][mc];
+            const float2 st = sig[s * GL + mc];
             float s1 = st.x, s2 = st.y;
 #pragma unroll
             for (int r = 0; r < L; ++r) {
@@ -192,8 +224,8 @@ __global__ __launch_bounds__(WG) void sos_bwd_kernel(BArgs a) {
         cc.prefix_out = nullptr;
         float e0, e1;
         const int buf = ((S - 1 - s) & 1) * GROUPS + grp;
-        if (tb.hiq)
-            carry<double, true>(tb, cc, m0, m1, e0, e1, s_agg, s_pre, buf);
+        if (HIQ && tb.hiq)
+            carry<double, true>(a.tab[s], cc, m0, m1, e0, e1, s_agg, s_pre, buf);
         else
             carry<float, true>(tb, cc, m0, m1, e0, e1, s_agg, s_pre, buf);
         // (d) the adjoint recursion from the true state: input gradient and
@@ -246,18 +278,35 @@ __global__ __launch_bounds__(WG) void sos_bwd_kernel(BArgs a) {
 }
 
 // Section-coefficient gradients from the per-tile partial sums.  One block
-// per section: each of the five sums is reduced in FP64 in a fixed order
-// (lane-strided partial sums, then a fixed tree), then mapped to the
-// gradients [b0 b1 b2 a1 a2] of the section's stage row.
+// per (section, sum): lane-strided FP64 partial sums in a fixed order, then
+// a fixed tree; a second kernel maps each section's five sums to the
+// gradients [b0 b1 b2 a1 a2] of its stage row.
 struct SosGradArgs {
     const double *part;
     const SecTab *tab;
     int32_t S;
     int64_t C, ntiles, cpad;
+    double *sums;  // [S][5]
     GradList out;
 };
 
 constexpr int RED_THREADS = 256;
+
+// sum_{j >= 0, t + j s < n} p[t + j s] in index order, eight loads in flight.
+template <typename T>
+__device__ __forceinline__ double strided_sum(const T *p, int64_t n, int64_t t, int64_t s) {
+    double acc = 0.0;
+    int64_t i = t;
+    for (; i + 7 * s < n; i += 8 * s) {
+        T v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = p[i + u * s];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc += (double)v[u];
+    }
+    for (; i < n; i += s) acc += (double)p[i];
+    return acc;
+}
 
 __device__ double block_sum_fixed(double v, double *sh) {
     const int t = threadIdx.x;
@@ -274,17 +323,18 @@ __device__ double block_sum_fixed(double v, double *sh) {
 
 __global__ __launch_bounds__(RED_THREADS) void sos_grad_reduce_kernel(SosGradArgs a) {
     __shared__ double sh[RED_THREADS];
-    const int s = blockIdx.x;
     const int64_t stride = a.cpad * a.ntiles;
     const int64_t n = a.C * a.ntiles;  // entries ch * ntiles + tile, ch < C
+    const double *p = a.part + (int64_t)blockIdx.x * stride;  // block = 5 s + k
+    const double t = block_sum_fixed(strided_sum(p, n, threadIdx.x, RED_THREADS), sh);
+    if (threadIdx.x == 0) a.sums[blockIdx.x] = t;
+}
+
+__global__ void sos_grad_map_kernel(SosGradArgs a) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= a.S) return;
     double d[5];
-    for (int k = 0; k < 5; ++k) {
-        const double *p = a.part + ((int64_t)s * 5 + k) * stride;
-        double t = 0.0;
-        for (int64_t i = threadIdx.x; i < n; i += RED_THREADS) t += p[i];
-        d[k] = block_sum_fixed(t, sh);
-    }
-    if (threadIdx.x != 0) return;
+    for (int k = 0; k < 5; ++k) d[k] = a.sums[5 * s + k];
     const double b0 = a.tab[s].coef[0], a1 = a.tab[s].coef[3], a2 = a.tab[s].coef[4];
     const double dA00 = d[0], dA10 = d[1], dB0 = d[2], dB1 = d[3], dD = d[4];
     int st = 0, j = s;
@@ -301,73 +351,81 @@ __global__ __launch_bounds__(RED_THREADS) void sos_grad_reduce_kernel(SosGradArg
     o[5 * j + 4] = (float)(-dA10 - b0 * dB1);  // a2 enters A[1][0] and B[1]
 }
 
-// Tap-gradient partials.  Block (pair, tile group, lag block kb): for the
-// lags k in [1025 kb, 1025 kb + 1025) and the tiles of the group,
-//   part[blk][k] = sum over the pair's two channels, the tiles' samples n of
-//                  g[n] x[n - k],
-// one 4096-point circular cross-correlation per tile: with z the x block
-// starting 1024 + 1025 kb samples before the tile and w the tile's g (zero
-// past it), Re IFFT(conj(W) Z)[d] at d = 1024 - (k - 1025 kb) is that sum
-// (no wrap-around, as d + 3071 < 4096), both channels at once.
+// Tap-gradient partials.  Block (pair-tile, lag block kb): for the lags k in
+// [1025 kb, 1025 kb + 1025),
+//   part[kb][blk][k - 1025 kb] = sum over the pair's two channels and the
+//                                tile's samples n of g[n] x[n - k],
+// one 4096-point circular cross-correlation: with z the x block starting
+// 1024 + 1025 kb samples before the tile and w the tile's g (zero past it),
+// Re IFFT(conj(W) Z)[d] at d = 1024 - (k - 1025 kb) is that sum (no
+// wrap-around, as d + 3071 < 4096), both channels at once.
 struct GhArgs {
     const float *x, *g;
     int64_t C, N, ldx, ldg;
     int32_t M;
-    int64_t ntiles, cpad, tpb;
+    int64_t cpad;
     const float2 *twid;
-    float *part;  // [npairs * ntg][M]
+    float *part;  // [lag block][pair-tile block][1025]
 };
 
 __global__ __launch_bounds__(WG) void fir_gh_part_kernel(GhArgs a) {
+    // FFT buffers, then the g block's spectrum (lane t keeps bins t + 256 k)
     __shared__ __align__(16) float lds[2 * NFFT];
+    __shared__ __align__(16) float2 wspec[NFFT];
     const int tid = threadIdx.x;
     const int64_t npairs = a.cpad / 2;
-    const int64_t tg = blockIdx.x / npairs, pair = blockIdx.x % npairs;
+    const int64_t tile = blockIdx.x / npairs, pair = blockIdx.x % npairs;
     const int64_t k0 = (int64_t)blockIdx.y * FFT_PART;
     const int64_t chA = 2 * pair, chB = chA + 1;
-    const float *xA = a.x + chA * a.ldx, *xB = chB < a.C ? a.x + chB * a.ldx : nullptr;
-    const float *gA = a.g + chA * a.ldg, *gB = chB < a.C ? a.g + chB * a.ldg : nullptr;
-    float acc[16];
+    const int64_t n0 = tile * T;
+    float zr[16], zi[16];
+    // g tile [n0, n0 + 3072), zero past it
+    load_pair_block(zr, zi, a.g + chA * a.ldg, chB < a.C ? a.g + chB * a.ldg : nullptr, n0, a.N, n0 + T, tid);
+    fft4096_forward(zr, zi, lds, a.twid, tid);
 #pragma unroll
-    for (int q = 0; q < 16; ++q) acc[q] = 0.f;
-    const int64_t t1 = min(a.ntiles, (tg + 1) * a.tpb);
-    for (int64_t tile = tg * a.tpb; tile < t1; ++tile) {
-        const int64_t n0 = tile * T;
-        float zr[16], zi[16], wr[16], wi[16];
-        load_pair_block(zr, zi, xA, xB, n0 - FFT_DISCARD - k0, a.N, a.N, tid);
-        __syncthreads();  // previous tile's last LDS reads
-        fft4096_forward(zr, zi, lds, a.twid, tid);
-        load_pair_block(wr, wi, gA, gB, n0, a.N, n0 + T, tid);
-        __syncthreads();
-        fft4096_forward(wr, wi, lds, a.twid, tid);
+    for (int k = 0; k < 16; ++k) wspec[tid + 256 * k] = make_float2(zr[k], zi[k]);
+    // x block [n0 - 1024 - k0, n0 + 3072 - k0)
+    load_pair_block(zr, zi, a.x + chA * a.ldx, chB < a.C ? a.x + chB * a.ldx : nullptr, n0 - FFT_DISCARD - k0,
+                    a.N, a.N, tid);
+    __syncthreads();  // the first FFT's last LDS reads
+    fft4096_forward(zr, zi, lds, a.twid, tid);
 #pragma unroll
-        for (int k = 0; k < 16; ++k) {  // conj(W) Z
-            const float r = wr[k] * zr[k] + wi[k] * zi[k];
-            const float i = wr[k] * zi[k] - wi[k] * zr[k];
-            zr[k] = r;
-            zi[k] = i;
-        }
-        fft4096_inverse(zr, zi, lds, a.twid, tid);
-#pragma unroll
-        for (int q = 0; q < 16; ++q) acc[q] += zr[q];
+    for (int k = 0; k < 16; ++k) {  // conj(W) Z
+        const float2 w = wspec[tid + 256 * k];
+        const float r = w.x * zr[k] + w.y * zi[k];
+        const float i = w.x * zi[k] - w.y * zr[k];
+        zr[k] = r;
+        zi[k] = i;
     }
-    // lane tid holds d = 256 q + tid
-    float *out = a.part + (int64_t)blockIdx.x * a.M;
+    fft4096_inverse(zr, zi, lds, a.twid, tid);
+    // lane tid holds d = 256 q + tid; lag k = k0 + 1024 - d
+    float *out = a.part + ((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * FFT_PART;
 #pragma unroll
     for (int q = 0; q < 5; ++q) {
         const int d = 256 * q + tid;
-        const int64_t k = k0 + FFT_DISCARD - d;
-        if (d <= FFT_DISCARD && k < a.M) out[k] = acc[q] * (1.0f / NFFT);
+        if (d <= FFT_DISCARD) out[FFT_DISCARD - d] = zr[q] * (1.0f / NFFT);
     }
 }
 
-// dst[k] = sum of the partials in block order, FP64.
-__global__ void fir_gh_reduce_kernel(const float *part, int32_t M, int64_t nparts, float *dst) {
+// Two-level FP64 reduction of the tap-gradient partials, in a fixed order:
+// level 1 sums the partials of 128 consecutive blocks per lag
+// (sum1[split][k]), level 2 the splits in order.
+constexpr int GH_SPLIT = 128;
+
+__global__ void fir_gh_reduce1_kernel(const float *part, int32_t M, int64_t nparts, double *sum1) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= M) return;
-    double t = 0.0;
-    for (int64_t p = 0; p < nparts; ++p) t += (double)part[p * M + k];
-    dst[k] = (float)t;
+    const int64_t i0 = (int64_t)blockIdx.y * GH_SPLIT;
+    const int64_t i1 = min(nparts, i0 + GH_SPLIT);
+    const int kb = k / FFT_PART, kk = k % FFT_PART;
+    const float *p = part + ((int64_t)kb * nparts + i0) * FFT_PART + kk;
+    sum1[(int64_t)blockIdx.y * M + k] = strided_sum(p, (i1 - i0) * FFT_PART, 0, FFT_PART);
+}
+
+__global__ void fir_gh_reduce2_kernel(const double *sum1, int32_t M, int32_t nsplit, float *dst) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= M) return;
+    dst[k] = (float)strided_sum(sum1 + k, (int64_t)nsplit * M, 0, M);
 }
 
 // out = a (*) b, FP64 (a == null stands for the unit impulse).
@@ -412,20 +470,21 @@ BwdLayout bwd_layout(int64_t C, int64_t N, int32_t S, int32_t M_merged, int32_t 
     if (b.fwd.total == 0) b.fwd.hdr = 0;
     b.part_sos = off;
     off += al256((size_t)S * 5 * cpad * ntiles * sizeof(double));
+    b.sos_sum = off;
+    off += al256((size_t)S * 5 * sizeof(double));
     const bool both = n_fir > 0 && S > 0;
+    const bool fused = both && fir_mode == FIR_FFT && fft_parts(M_merged) == 1;  // FIR recomputed in the adjoint
     b.fbuf = off;
-    if (both) off += al256((size_t)C * N * sizeof(float));
+    if (both && !fused) off += al256((size_t)C * N * sizeof(float));
     b.gfbuf = off;
     if (both) off += al256((size_t)C * N * sizeof(float));
-    b.tpb = b.ntg = b.nlag = 0;
-    b.part_gh = b.gH = b.obuf = b.twid = b.tw64 = off;
+    b.nlag = 0;
+    b.part_gh = b.gh1 = b.gH = b.obuf = b.twid = b.tw64 = off;
     if (n_fir > 0 && ntiles > 0) {
         b.nlag = (M_merged + FFT_PART - 1) / FFT_PART;
-        const int64_t want = 2048;  // blocks to fill the chip
-        b.tpb = (npairs * ntiles * b.nlag + want - 1) / want;
-        if (b.tpb < 1) b.tpb = 1;
-        b.ntg = (ntiles + b.tpb - 1) / b.tpb;
-        off += al256((size_t)npairs * b.ntg * M_merged * sizeof(float));
+        off += al256((size_t)b.nlag * npairs * ntiles * FFT_PART * sizeof(float));
+        b.gh1 = off;
+        off += al256((size_t)((npairs * ntiles + GH_SPLIT - 1) / GH_SPLIT) * M_merged * sizeof(double));
         b.gH = off;
         off += al256((size_t)M_merged * sizeof(float));
         b.obuf = off;
@@ -467,11 +526,16 @@ hipError_t launch_backward(const BwdPlan &bp) {
     int64_t ldf = p.ldx;
     float *gf = bp.gx;
     int64_t ldgf = bp.ldgx;
+    // a single-partition FFT FIR is recomputed inside the adjoint kernel;
+    // other FIR forms are run into a buffer first
+    const bool fuse = has_fir && has_sos && p.fir_mode == FIR_FFT && fft_parts(M) == 1;
     if (has_fir && has_sos) {
-        float *fb = reinterpret_cast<float *>(ws + lay.fbuf);
-        if ((e = launch_fir_pass(p, lay.fwd, p.x, p.ldx, fb, p.N, false)) != hipSuccess) return e;
-        f = fb;
-        ldf = p.N;
+        if (!fuse) {
+            float *fb = reinterpret_cast<float *>(ws + lay.fbuf);
+            if ((e = launch_fir_pass(p, lay.fwd, p.x, p.ldx, fb, p.N, false)) != hipSuccess) return e;
+            f = fb;
+            ldf = p.N;
+        }
         gf = reinterpret_cast<float *>(ws + lay.gfbuf);
         ldgf = p.N;
     }
@@ -497,7 +561,21 @@ hipError_t launch_backward(const BwdPlan &bp) {
         b.vecf = (reinterpret_cast<uintptr_t>(b.f) % 16 == 0 && b.ldf % 4 == 0) ? 1 : 0;
         b.vecg = (reinterpret_cast<uintptr_t>(b.g) % 16 == 0 && b.ldg % 4 == 0) ? 1 : 0;
         b.veco = (reinterpret_cast<uintptr_t>(b.gf) % 16 == 0 && b.ldo % 4 == 0) ? 1 : 0;
-        hipLaunchKernelGGL(sos_bwd_kernel, dim3((unsigned)(npairs * ntiles)), dim3(WG), 0, st, b);
+        const size_t dyn = (size_t)p.S * (sizeof(SecLds) + GROUPS * GL * sizeof(float2));
+        const dim3 grid((unsigned)(npairs * ntiles)), block(WG);
+        if (fuse) {
+            b.x = p.x;
+            b.ldx = p.ldx;
+            b.twid = reinterpret_cast<const float2 *>(ws + lay.fwd.twid);
+            b.hspec = reinterpret_cast<const float2 *>(ws + lay.fwd.hspec);
+            hipLaunchKernelGGL((sos_bwd_kernel<false, true>), grid, block, dyn, st, b);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+            hipLaunchKernelGGL((sos_bwd_kernel<true, true>), grid, block, dyn, st, b);
+        } else {
+            hipLaunchKernelGGL((sos_bwd_kernel<false, false>), grid, block, dyn, st, b);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+            hipLaunchKernelGGL((sos_bwd_kernel<true, false>), grid, block, dyn, st, b);
+        }
         if ((e = hipGetLastError()) != hipSuccess) return e;
         SosGradArgs r{};
         r.part = b.part;
@@ -507,7 +585,10 @@ hipError_t launch_backward(const BwdPlan &bp) {
         r.ntiles = ntiles;
         r.cpad = cpad;
         r.out = bp.gsos;
-        hipLaunchKernelGGL(sos_grad_reduce_kernel, dim3((unsigned)p.S), dim3(RED_THREADS), 0, st, r);
+        r.sums = reinterpret_cast<double *>(ws + lay.sos_sum);
+        hipLaunchKernelGGL(sos_grad_reduce_kernel, dim3((unsigned)(5 * p.S)), dim3(RED_THREADS), 0, st, r);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        hipLaunchKernelGGL(sos_grad_map_kernel, dim3((unsigned)((p.S + 63) / 64)), dim3(64), 0, st, r);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     if (!has_fir) return hipSuccess;
@@ -527,9 +608,7 @@ hipError_t launch_backward(const BwdPlan &bp) {
     g.ldx = p.ldx;
     g.ldg = ldgfc;
     g.M = M;
-    g.ntiles = ntiles;
     g.cpad = cpad;
-    g.tpb = lay.tpb;
     g.twid = reinterpret_cast<const float2 *>(ws + lay.fwd.twid);
     g.part = reinterpret_cast<float *>(ws + lay.part_gh);
     if (p.fir_mode != FIR_FFT) {  // the direct path's prepare leaves no twiddles
@@ -538,12 +617,18 @@ hipError_t launch_backward(const BwdPlan &bp) {
                                  st)) != hipSuccess)
             return e;
     }
-    hipLaunchKernelGGL(fir_gh_part_kernel, dim3((unsigned)(npairs * lay.ntg), (unsigned)lay.nlag), dim3(WG), 0, st,
+    hipLaunchKernelGGL(fir_gh_part_kernel, dim3((unsigned)(npairs * ntiles), (unsigned)lay.nlag), dim3(WG), 0, st,
                        g);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     float *gH = p.firs.n == 1 ? bp.gfir.ptr[0] : reinterpret_cast<float *>(ws + lay.gH);
-    hipLaunchKernelGGL(fir_gh_reduce_kernel, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, st,
-                       static_cast<const float *>(g.part), M, npairs * lay.ntg, gH);
+    const int64_t nbx = npairs * ntiles;
+    const int32_t nsplit = (int32_t)((nbx + GH_SPLIT - 1) / GH_SPLIT);
+    double *sum1 = reinterpret_cast<double *>(ws + lay.gh1);
+    hipLaunchKernelGGL(fir_gh_reduce1_kernel, dim3((unsigned)((M + 255) / 256), (unsigned)nsplit), dim3(256), 0, st,
+                       static_cast<const float *>(g.part), M, nbx, sum1);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(fir_gh_reduce2_kernel, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, st,
+                       static_cast<const double *>(sum1), M, nsplit, gH);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (p.firs.n == 1) return hipSuccess;
     // several FIR stages: chain rule through the tap convolution

@@ -16,8 +16,8 @@
 
 namespace tfx {
 
-template <int LC, typename CT>
-__device__ void batch_section(const SecTab &tb, float (&v)[LC], const CarryCtx &cc, double (*s_agg)[GWAVES][2],
+template <int LC, typename CT, class TB>
+__device__ void batch_section(const TB &tb, float (&v)[LC], const CarryCtx &cc, double (*s_agg)[GWAVES][2],
                               double (*s_pre)[2], int buf) {
     const float b0 = tb.coef[0], b1 = tb.coef[1], b2 = tb.coef[2];
     const float a1 = tb.coef[3], a2 = tb.coef[4];
@@ -31,7 +31,7 @@ __device__ void batch_section(const SecTab &tb, float (&v)[LC], const CarryCtx &
         v[r] = yv;
     }
     float z1, z2;
-    carry<CT, false>(tb, cc, s1, s2, z1, z2, s_agg, s_pre, buf);
+    carry<CT, false, TB>(tb, cc, s1, s2, z1, z2, s_agg, s_pre, buf);
 #pragma unroll
     for (int r = 0; r < LC; ++r) {
         v[r] += z1;
@@ -49,7 +49,9 @@ struct BatchArgs {
     uint32_t *hdr;
 };
 
-template <int LC>
+// HIQ: the variant with the FP64 carry; both run, the one that does not match
+// the batch's high-Q word exits at once.
+template <int LC, bool HIQ>
 __global__ __launch_bounds__(WG) void batch_kernel(BatchArgs a) {
     typedef Chunk<LC> K;
     __shared__ __align__(16) float lds[GROUPS * K::STG];
@@ -57,7 +59,9 @@ __global__ __launch_bounds__(WG) void batch_kernel(BatchArgs a) {
     __shared__ double s_pre[2 * GROUPS][2];
     __shared__ uint32_t s_epoch;
     __shared__ int s_clip;
+    extern __shared__ __align__(16) SecLds s_tab[];  // fp32 tables, LDS_SECTIONS at a time
 
+    if ((a.hdr[HDR_HIQ] != 0u) != HIQ) return;
     const int tid = threadIdx.x, lane = tid & 63, grp = tid / GL, gl = tid % GL, gw = gl >> 6;
     const int64_t id = blockIdx.x;
     if (tid == 0) {
@@ -80,11 +84,17 @@ __global__ __launch_bounds__(WG) void batch_kernel(BatchArgs a) {
     const int64_t n0 = tile * K::T;
     float *stg = lds + grp * K::STG;
     float v[LC];
+    stage_tables(s_tab, a.tab, (int)d.tab0, min(d.S, LDS_SECTIONS), tid, WG);
     stage_tile<LC>(stg, d.x + ch * d.ldx + n0, d.N - n0, valid, d.vec != 0, gl);
     __syncthreads();
     load_chunk<LC>(stg, gl, v);
     for (int s = 0; s < d.S; ++s) {
-        const SecTab &tb = a.tab[d.tab0 + s];
+        if (s > 0 && s % LDS_SECTIONS == 0) {  // next block of tables
+            __syncthreads();
+            stage_tables(s_tab, a.tab, (int)d.tab0 + s, min(d.S - s, LDS_SECTIONS), tid, WG);
+            __syncthreads();
+        }
+        const SecLds &tb = s_tab[s % LDS_SECTIONS];
         CarryCtx cc;
         cc.lane = lane;
         cc.gw = gw;
@@ -99,8 +109,8 @@ __global__ __launch_bounds__(WG) void batch_kernel(BatchArgs a) {
         cc.known0 = cc.known1 = 0.0;
         cc.prefix_out = nullptr;
         const int buf = (s & 1) * GROUPS + grp;
-        if (tb.hiq)
-            batch_section<LC, double>(tb, v, cc, s_agg, s_pre, buf);
+        if (HIQ && tb.hiq)
+            batch_section<LC, double>(a.tab[d.tab0 + s], v, cc, s_agg, s_pre, buf);
         else
             batch_section<LC, float>(tb, v, cc, s_agg, s_pre, buf);
     }
@@ -184,6 +194,7 @@ BatchLayout batch_plan(const ClipIn *clips, int32_t n, int lc, int order, ClipDe
                  c.ldy % 4 == 0) ? 1 : 0;
         blk += d.cpad / 2 * d.ntiles;
         tab += c.S;
+        if (c.S > lay.smax) lay.smax = c.S;
         rec += d.cpad * d.ntiles * c.S;
         if (desc) desc[j] = d;
     }
@@ -214,12 +225,19 @@ hipError_t launch_batch_run(const BatchLayout &lay, int lc, int32_t nclips, void
     a.recs = reinterpret_cast<uint64_t *>(w + lay.recs);
     a.hdr = reinterpret_cast<uint32_t *>(w + lay.hdr);
     const dim3 grid((unsigned)lay.nblocks), block(WG);
-    switch (lc) {
-        case 16: hipLaunchKernelGGL(batch_kernel<16>, grid, block, 0, st, a); break;
-        case 32: hipLaunchKernelGGL(batch_kernel<32>, grid, block, 0, st, a); break;
-        default: hipLaunchKernelGGL(batch_kernel<24>, grid, block, 0, st, a); break;
+    const size_t dyn = sizeof(SecLds) * (size_t)(lay.smax < LDS_SECTIONS ? lay.smax : LDS_SECTIONS);
+    hipError_t e = hipSuccess;
+    for (int hiq = 0; hiq < 2 && e == hipSuccess; ++hiq) {
+        switch (lc * 2 + hiq) {
+            case 32: hipLaunchKernelGGL((batch_kernel<16, false>), grid, block, dyn, st, a); break;
+            case 33: hipLaunchKernelGGL((batch_kernel<16, true>), grid, block, dyn, st, a); break;
+            case 64: hipLaunchKernelGGL((batch_kernel<32, false>), grid, block, dyn, st, a); break;
+            case 65: hipLaunchKernelGGL((batch_kernel<32, true>), grid, block, dyn, st, a); break;
+            case 49: hipLaunchKernelGGL((batch_kernel<24, true>), grid, block, dyn, st, a); break;
+            default: hipLaunchKernelGGL((batch_kernel<24, false>), grid, block, dyn, st, a); break;
+        }
+        e = hipGetLastError();
     }
-    hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(batch_bump_epoch_kernel, dim3(1), dim3(1), 0, st, a.hdr);
     return hipGetLastError();

@@ -105,13 +105,7 @@ __device__ void fft_block(const KArgs &a, float *lds, int64_t pair, int64_t n0, 
     if (!PARTS) {
         load_pair_block(zr, zi, xA, xB, base, a.N, a.N, tid);
         fft4096_forward(zr, zi, lds, a.twid, tid);
-        if (a.correlate) {
-#pragma unroll
-            for (int k3 = 0; k3 < 16; ++k3) cmul_tw<true>(zr[k3], zi[k3], a.hspec[tid + 256 * k3]);
-        } else {
-#pragma unroll
-            for (int k3 = 0; k3 < 16; ++k3) cmul_tw<false>(zr[k3], zi[k3], a.hspec[tid + 256 * k3]);
-        }
+        spectrum_product(zr, zi, a.hspec, tid, a.correlate != 0);
     } else {
         // spectrum accumulator: lane t owns bins t + 256 k3 (no sharing, no
         // barrier), after the two FFT buffers
@@ -237,7 +231,10 @@ __device__ void run_section(const KArgs &a, const TB &tb, int s, float (&v)[L], 
     }
 }
 
-template <int FIRM, bool HAS_SOS>
+// HIQ: the variant with the FP64 carry.  Both variants are launched; the one
+// that does not match the workspace's high-Q word exits at once, so the
+// common case is compiled without the FP64 path's registers.
+template <int FIRM, bool HAS_SOS, bool HIQ>
 __global__ __launch_bounds__(WG) void chain_kernel(KArgs a) {
     __shared__ __align__(16) float lds[lds_floats<FIRM>()];
     __shared__ double s_agg[2 * GROUPS][GWAVES][2];
@@ -245,6 +242,7 @@ __global__ __launch_bounds__(WG) void chain_kernel(KArgs a) {
     __shared__ uint32_t s_epoch;
     extern __shared__ __align__(16) SecLds s_tab[];  // fp32 tables of up to LDS_SECTIONS sections
 
+    if (HAS_SOS && (a.hdr[HDR_HIQ] != 0u) != HIQ) return;  // the other variant runs
     TileCtx c;
     c.tid = threadIdx.x;
     c.lane = c.tid & 63;
@@ -374,7 +372,7 @@ __global__ __launch_bounds__(WG) void chain_kernel(KArgs a) {
                 __syncthreads();
             }
             const SecLds &tl = s_tab[s % LDS_SECTIONS];
-            if (tl.hiq)
+            if (HIQ && tl.hiq)
                 run_section<double>(a, a.tab[s], s, v, c, s_agg, s_pre);
             else
                 run_section<float>(a, tl, s, v, c, s_agg, s_pre);
@@ -435,11 +433,16 @@ hipError_t launch_state_passthrough(const float *in, float *out, int64_t n, hipS
 template <int F, bool S>
 static hipError_t launch_main(const KArgs &k, int64_t nblocks, hipStream_t st) {
     const size_t dyn = S ? sizeof(SecLds) * (size_t)(k.S < LDS_SECTIONS ? k.S : LDS_SECTIONS) : 0;
-    hipLaunchKernelGGL((chain_kernel<F, S>), dim3((unsigned)nblocks), dim3(WG), dyn, st, k);
+    hipLaunchKernelGGL((chain_kernel<F, S, false>), dim3((unsigned)nblocks), dim3(WG), dyn, st, k);
     hipError_t e = hipGetLastError();
-    if (e != hipSuccess || !S) return e;
-    hipLaunchKernelGGL(bump_epoch_kernel, dim3(1), dim3(1), 0, st, k.hdr, (int)HDR_EPOCH);
-    return hipGetLastError();
+    if constexpr (S) {
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL((chain_kernel<F, S, true>), dim3((unsigned)nblocks), dim3(WG), dyn, st, k);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        hipLaunchKernelGGL(bump_epoch_kernel, dim3(1), dim3(1), 0, st, k.hdr, (int)HDR_EPOCH);
+        e = hipGetLastError();
+    }
+    return e;
 }
 
 int32_t merged_taps(const StageList &f) {

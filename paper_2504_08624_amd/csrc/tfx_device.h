@@ -23,8 +23,6 @@ namespace tfx {
 constexpr uint32_t EPOCH_MASK = 0x3FFFFFFFu;
 constexpr int64_t SPIN_MAX = int64_t(1) << 22;
 constexpr int REC_WORDS = 4;
-// header words of a workspace
-enum { HDR_ERROR = 1, HDR_EPOCH = 2 };
 
 __device__ __forceinline__ uint64_t ld_word(const uint64_t *p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -362,6 +360,28 @@ __device__ __forceinline__ void fft4096_inverse(float (&zr)[16], float (&zi)[16]
             zi[k1] = Li[ex1(k1, b, c)];
         }
         dft16<1>(zr, zi);
+    }
+}
+
+// Z *= H (or conj(H)) bin by bin, H = the tap spectrum in the forward FFT's
+// output layout.  The spectrum loads go in groups of four with a compiler
+// barrier between groups, so at most four bins' spectra sit in registers
+// beside the data (with all sixteen in flight the fused kernels needed about
+// 160 VGPRs instead of 128).
+__device__ __forceinline__ void spectrum_product(float (&zr)[16], float (&zi)[16], const float2 *hspec, int tid,
+                                                 bool conj) {
+    const float sg = conj ? -1.f : 1.f;
+#pragma unroll
+    for (int g4 = 0; g4 < 4; ++g4) {
+        float2 w[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) w[u] = hspec[tid + 256 * (4 * g4 + u)];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            w[u].y *= sg;
+            cmul_tw<false>(zr[4 * g4 + u], zi[4 * g4 + u], w[u]);
+        }
+        asm volatile("" ::: "memory");
     }
 }
 

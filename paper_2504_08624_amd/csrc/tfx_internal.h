@@ -3,6 +3,7 @@
 #include <hip/hip_runtime_api.h>
 #include <stddef.h>
 #include <stdint.h>
+#include <math.h>
 
 namespace tfx {
 
@@ -67,6 +68,26 @@ struct alignas(16) SecLds {
 static_assert(offsetof(SecTab, lb) == offsetof(SecLds, lb), "SecLds must be the leading part of SecTab");
 static_assert(sizeof(SecLds) <= offsetof(SecTab, fold_d), "SecLds must be the leading part of SecTab");
 constexpr int LDS_SECTIONS = 32;  // sections staged in LDS at a time
+
+// Header words of a workspace: look-back error bit, look-back epoch, and
+// whether any section needs the FP64 carry (the filter kernels come in two
+// variants; the one that does not match this word exits at once).
+enum { HDR_ERROR = 1, HDR_EPOCH = 2, HDR_HIQ = 3 };
+
+// Pole radius of 1 + a1 z^-1 + a2 z^-2 above 0.999: the section's carry
+// runs in FP64.
+__host__ __device__ inline bool section_hiq(double a1, double a2) {
+    const double disc = a1 * a1 - 4.0 * a2;
+    double r;
+    if (disc < 0.0) {
+        r = sqrt(a2);
+    } else {
+        const double sq = sqrt(disc);
+        const double r1 = fabs(0.5 * (-a1 + sq)), r2 = fabs(0.5 * (-a1 - sq));
+        r = r1 > r2 ? r1 : r2;
+    }
+    return r > 0.999;
+}
 
 struct StageList {
     const float *ptr[MAX_STAGES];
@@ -136,6 +157,7 @@ struct alignas(16) ClipDesc {
 struct BatchLayout {
     size_t hdr, desc, tab, recs, total;
     int64_t nblocks, nsec, nrec;
+    int32_t smax;  // longest cascade of the batch
 };
 
 // host-side clip record (mirrors the public tfx_clip)
@@ -176,8 +198,8 @@ struct BwdPlan {
 // Backward workspace: the forward layout, then the adjoint's buffers.
 struct BwdLayout {
     WsLayout fwd;
-    size_t part_sos, fbuf, gfbuf, part_gh, gH, obuf, twid, tw64, total;
-    int64_t tpb, ntg, nlag;
+    size_t part_sos, sos_sum, fbuf, gfbuf, part_gh, gh1, gH, obuf, twid, tw64, total;
+    int64_t nlag;
 };
 BwdLayout bwd_layout(int64_t C, int64_t N, int32_t S, int32_t M_merged, int32_t n_fir, int32_t fir_mode);
 hipError_t launch_backward(const BwdPlan &p);

@@ -54,15 +54,7 @@ __device__ void build_section(SecTab *tb, const float *co, int Lc) {
         put4(tb->lb[j], tb->lb_d[j], B);
         mat2_mul(B, B, B);
     }
-    const double disc = a1 * a1 - 4.0 * a2;
-    double r;
-    if (disc < 0.0) {
-        r = sqrt(a2);
-    } else {
-        const double sq = sqrt(disc);
-        r = fmax(fabs(0.5 * (-a1 + sq)), fabs(0.5 * (-a1 - sq)));
-    }
-    tb->hiq = r > 0.999 ? 1 : 0;
+    tb->hiq = section_hiq(a1, a2) ? 1 : 0;
 }
 
 struct PrepArgs {
@@ -81,8 +73,18 @@ __global__ void prep_kernel(PrepArgs a) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = gid; i < a.nwords; i += stride) a.recs[i] = 0ull;
     if (gid == 0) {
-        a.hdr[1] = 0u;  // error word
-        a.hdr[2] = 1u;  // epoch
+        a.hdr[HDR_ERROR] = 0u;
+        a.hdr[HDR_EPOCH] = 1u;
+        uint32_t any = 0u;
+        for (int s = 0, st = 0, j = 0; s < a.S; ++s, ++j) {
+            while (j >= a.sos.len[st]) {
+                j -= a.sos.len[st];
+                ++st;
+            }
+            const float *co = a.sos.ptr[st] + 5 * j;
+            any |= section_hiq(co[3], co[4]) ? 1u : 0u;
+        }
+        a.hdr[HDR_HIQ] = any;
     }
     if (gid < a.S) {
         int s = (int)gid, st = 0;
@@ -192,8 +194,13 @@ __global__ void batch_prep_kernel(BatchPrepArgs a) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = gid; i < a.nwords; i += stride) a.recs[i] = 0ull;
     if (gid == 0) {
-        a.hdr[1] = 0u;
-        a.hdr[2] = 1u;
+        a.hdr[HDR_ERROR] = 0u;
+        a.hdr[HDR_EPOCH] = 1u;
+        uint32_t any = 0u;
+        for (int c = 0; c < a.nclips; ++c)
+            for (int s = 0; s < a.desc[c].S; ++s)
+                any |= section_hiq(a.desc[c].sos[5 * s + 3], a.desc[c].sos[5 * s + 4]) ? 1u : 0u;
+        a.hdr[HDR_HIQ] = any;
     }
     for (int64_t g = gid; g < a.nsec; g += stride) {
         // the last clip with tab0 <= g: tab0 grows with the clip index by S,
