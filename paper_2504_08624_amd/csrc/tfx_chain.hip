@@ -57,6 +57,15 @@ constexpr int FIR_FFT_PARTS = 4;
 template <int FIRM>
 constexpr bool is_fft() { return FIRM == FIR_FFT || FIRM == FIR_FFT_PARTS; }
 
+// LDS of the cascade-level look-back (floats): Phi_T, Phi_T^2, Phi_T^4 and a
+// window weight per group (D x D each), tile aggregate and prefix per group.
+__host__ __device__ constexpr int casc_floats(int D) { return (3 + GROUPS) * D * D + 2 * GROUPS * 16; }
+// After the FFT the tail of its buffers beyond the two staging areas is free.
+constexpr int FFT_TAIL_FLOATS = 2 * NFFT - GROUPS * STG_FLOATS;
+__host__ __device__ constexpr bool casc_in_tail(int FIRM, int S) {
+    return (FIRM == FIR_FFT || FIRM == 4) && casc_floats(2 * S) <= FFT_TAIL_FLOATS;
+}
+
 template <int FIRM>
 constexpr int lds_floats() {
     // the partitioned FFT keeps its spectrum accumulator in LDS after the
@@ -85,6 +94,7 @@ struct KArgs {
     const float2 *twid;   // e^{-2 pi i j / 4096}
     const float2 *hspec;  // [nparts][4096] spectra of the tap partitions / 4096
     int32_t nparts;
+    const CascTab *casc;  // cascade tile-transition powers (cascade-level look-back)
 };
 
 // Overlap-save block of the pair.  Convolution: the block starts 1024 samples
@@ -156,9 +166,12 @@ struct TileCtx {
 // One section over the group's tile: zero-state response, carry, then the
 // zero-input response of each chunk-entering state added in place.  s_agg /
 // s_pre are double-buffered by section parity (no barrier needed at the end).
-template <typename CT, class TB>
+// KNOWN: the section's tile-entering state `known` has been produced by the
+// cascade-level look-back (no look-back here; the checkpoint is written by
+// the caller).
+template <typename CT, class TB, bool KNOWN = false>
 __device__ void run_section(const KArgs &a, const TB &tb, int s, float (&v)[L], const TileCtx &c,
-                            double (*s_agg)[GWAVES][2], double (*s_pre)[2]) {
+                            double (*s_agg)[GWAVES][2], double (*s_pre)[2], const float *known = nullptr) {
     const float b0 = tb.coef[0], b1 = tb.coef[1], b2 = tb.coef[2];
     const float a1 = tb.coef[3], a2 = tb.coef[4];
     float s1 = 0.f, s2 = 0.f, c1 = 0.f, c2 = 0.f;
@@ -203,7 +216,13 @@ __device__ void run_section(const KArgs &a, const TB &tb, int s, float (&v)[L], 
     }
     cc.prefix_out = (a.ckpt && c.valid) ? a.ckpt + ((c.ch * a.ntiles + c.tile) * a.S + s) * 2 : nullptr;
     float z1, z2;
-    carry<CT, false, TB>(tb, cc, s1, s2, z1, z2, s_agg, s_pre, (s & 1) * GROUPS + c.grp);
+    if constexpr (KNOWN) {
+        CT E0, E1;
+        carry_local<CT, TB>(tb, c.lane, c.gw, s1, s2, (CT)known[0], (CT)known[1], z1, z2, E0, E1, s_agg,
+                            (s & 1) * GROUPS + c.grp);
+    } else {
+        carry<CT, false, TB>(tb, cc, s1, s2, z1, z2, s_agg, s_pre, (s & 1) * GROUPS + c.grp);
+    }
     if (c.is_last) {
 #pragma unroll
         for (int r = 0; r < L; ++r) {
@@ -234,13 +253,25 @@ __device__ void run_section(const KArgs &a, const TB &tb, int s, float (&v)[L], 
 // HIQ: the variant with the FP64 carry.  Both variants are launched; the one
 // that does not match the workspace's high-Q word exits at once, so the
 // common case is compiled without the FP64 path's registers.
-template <int FIRM, bool HAS_SOS, bool HIQ>
+// CASC: the cascade (at most CASC_MAX sections, none needing FP64) is run in
+// three phases per tile: (A) every section over the tile from a zero
+// tile-entering state, giving the cascade's tile aggregate; (B) one
+// decoupled look-back of the whole 2S-component cascade state; (C) every
+// section again from its now known tile-entering state, with no look-back.
+// This trades a second in-tile pass for S - 1 fewer cross-tile round trips,
+// which dominate the per-section form.
+template <int FIRM, bool HAS_SOS, bool HIQ, bool CASC>
 __global__ __launch_bounds__(WG) void chain_kernel(KArgs a) {
     __shared__ __align__(16) float lds[lds_floats<FIRM>()];
     __shared__ double s_agg[2 * GROUPS][GWAVES][2];
     __shared__ double s_pre[2 * GROUPS][2];
     __shared__ uint32_t s_epoch;
-    extern __shared__ __align__(16) SecLds s_tab[];  // fp32 tables of up to LDS_SECTIONS sections
+    // dynamic: the fp32 tables (LDS_SECTIONS sections at a time, or all of a
+    // cascade-level cascade without their look-back powers), then the
+    // cascade look-back area unless it sits in the FFT buffers' tail
+    extern __shared__ __align__(16) unsigned char s_dyn[];
+    SecLds *s_tab = reinterpret_cast<SecLds *>(s_dyn);
+    SecLdsC *s_tabc = reinterpret_cast<SecLdsC *>(s_dyn);
 
     if (HAS_SOS && (a.hdr[HDR_HIQ] != 0u) != HIQ) return;  // the other variant runs
     TileCtx c;
@@ -254,7 +285,10 @@ __global__ __launch_bounds__(WG) void chain_kernel(KArgs a) {
     if (HAS_SOS) {
         if (c.tid == 0) s_epoch = load_epoch(a.hdr, HDR_EPOCH);
         // the tables' loads overlap the FIR part of the tile
-        stage_tables(s_tab, a.tab, 0, min(a.S, LDS_SECTIONS), c.tid, WG);
+        if (CASC)
+            stage_tables(s_tabc, a.tab, 0, a.S, c.tid, WG);
+        else
+            stage_tables(s_tab, a.tab, 0, min(a.S, LDS_SECTIONS), c.tid, WG);
         __syncthreads();
         c.epoch = s_epoch;
     }
@@ -360,7 +394,71 @@ __global__ __launch_bounds__(WG) void chain_kernel(KArgs a) {
         load_chunk(stg, c.gl, v);
     }
 
-    if (HAS_SOS) {
+    if (HAS_SOS && CASC) {
+        c.is_last = (c.tile == a.ntiles - 1);
+        const int64_t plast = a.N - 1 - n0;
+        c.r_last = c.is_last ? (int)(plast % L) : 0;
+        c.owner = c.is_last ? (int)(plast / L) : -1;
+        if (FIRM == FIR_DIRECT) store_chunk(stg, c.gl, v);  // keep the cascade input chunk
+        // cascade look-back area: T (3 D x D), window weights, E and P
+        const int D = 2 * a.S, DD = D * D;
+        float *cr = casc_in_tail(FIRM, a.S) ? lds + GROUPS * STG_FLOATS
+                                            : reinterpret_cast<float *>(s_dyn + a.S * sizeof(SecLdsC));
+        float *cT = cr, *cM = cr + 3 * DD + c.grp * DD, *cE = cr + (3 + GROUPS) * DD + 32 * c.grp, *cP = cE + 16;
+        for (int e = c.tid; e < 3 * DD; e += WG) {  // read in phase B, after phase A's barriers
+            const int k = e / DD, i = (e % DD) / D, j = e % D;
+            cT[e] = a.casc->T[k][i][j];
+        }
+        // (A) zero tile-entering state: the cascade's tile aggregate
+        for (int s = 0; s < a.S; ++s) {
+            const SecLdsC &tb = s_tabc[s];
+            const float b0 = tb.coef[0], b1 = tb.coef[1], b2 = tb.coef[2], a1 = tb.coef[3], a2 = tb.coef[4];
+            float s1 = 0.f, s2 = 0.f;
+#pragma unroll
+            for (int r = 0; r < L; ++r) {
+                const float xv = v[r];
+                const float yv = fmaf(b0, xv, s1);
+                s1 = fmaf(b1, xv, fmaf(-a1, yv, s2));
+                s2 = fmaf(b2, xv, -a2 * yv);
+                v[r] = yv;
+            }
+            float z1, z2, E0, E1;
+            carry_local<float, SecLdsC>(tb, c.lane, c.gw, s1, s2, 0.f, 0.f, z1, z2, E0, E1, s_agg,
+                                        (s & 1) * GROUPS + c.grp);
+            if (c.gl == 0) {
+                cE[2 * s] = E0;
+                cE[2 * s + 1] = E1;
+            }
+            if (s + 1 < a.S) {
+#pragma unroll
+                for (int r = 0; r < L; ++r) {
+                    v[r] += z1;
+                    const float n1 = fmaf(-a1, z1, z2);
+                    z2 = -a2 * z1;
+                    z1 = n1;
+                }
+            }
+        }
+        // (B) one look-back of the cascade state (first wave of each group)
+        if (c.gw == 0) {
+            CascCtx cc;
+            cc.lane = c.lane;
+            cc.D = 2 * a.S;
+            cc.depth = a.casc->depth;
+            cc.rec = a.recs + c.ch * a.ntiles * (int64_t)(4 * a.S);
+            cc.pos = c.tile;
+            cc.epoch = c.epoch;
+            cc.hdr = a.hdr;
+            cc.known = (a.state_in && c.valid) ? a.state_in + c.ch * a.S * 2 : nullptr;
+            casc_lookback(cc, cT, cE, cP, cM);
+            if (a.ckpt && c.valid && c.lane < D) a.ckpt[(c.ch * a.ntiles + c.tile) * a.S * 2 + c.lane] = cP[c.lane];
+        }
+        __syncthreads();
+        // (C) every section from its known tile-entering state
+        load_chunk(stg, c.gl, v);
+        for (int s = 0; s < a.S; ++s)
+            run_section<float, SecLdsC, true>(a, s_tabc[s], s, v, c, s_agg, s_pre, cP + 2 * s);
+    } else if (HAS_SOS) {
         c.is_last = (c.tile == a.ntiles - 1);
         const int64_t plast = a.N - 1 - n0;
         c.r_last = c.is_last ? (int)(plast % L) : 0;
@@ -407,6 +505,8 @@ WsLayout ws_layout(int64_t C, int64_t N, int32_t S, int32_t M_merged, int32_t n_
     const size_t nrec = (size_t)w.cpad * (size_t)w.ntiles * (size_t)S;
     w.recs = off;
     off += al256(nrec * REC_WORDS * sizeof(uint64_t));
+    w.casc = off;
+    if (S > 0 && S <= CASC_MAX) off += al256(sizeof(CascTab));
     w.taps = w.merge = off;
     if (n_fir > 1) {
         off += al256((size_t)M_merged * sizeof(float));
@@ -433,11 +533,20 @@ hipError_t launch_state_passthrough(const float *in, float *out, int64_t n, hipS
 template <int F, bool S>
 static hipError_t launch_main(const KArgs &k, int64_t nblocks, hipStream_t st) {
     const size_t dyn = S ? sizeof(SecLds) * (size_t)(k.S < LDS_SECTIONS ? k.S : LDS_SECTIONS) : 0;
-    hipLaunchKernelGGL((chain_kernel<F, S, false>), dim3((unsigned)nblocks), dim3(WG), dyn, st, k);
+    if constexpr (S) {
+        const size_t dync = sizeof(SecLdsC) * (size_t)k.S +
+                            (casc_in_tail(F, k.S) ? 0 : sizeof(float) * (size_t)casc_floats(2 * k.S));
+        if (k.S <= CASC_MAX)
+            hipLaunchKernelGGL((chain_kernel<F, S, false, true>), dim3((unsigned)nblocks), dim3(WG), dync, st, k);
+        else
+            hipLaunchKernelGGL((chain_kernel<F, S, false, false>), dim3((unsigned)nblocks), dim3(WG), dyn, st, k);
+    } else {
+        hipLaunchKernelGGL((chain_kernel<F, S, false, false>), dim3((unsigned)nblocks), dim3(WG), dyn, st, k);
+    }
     hipError_t e = hipGetLastError();
     if constexpr (S) {
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL((chain_kernel<F, S, true>), dim3((unsigned)nblocks), dim3(WG), dyn, st, k);
+        hipLaunchKernelGGL((chain_kernel<F, S, true, false>), dim3((unsigned)nblocks), dim3(WG), dyn, st, k);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         hipLaunchKernelGGL(bump_epoch_kernel, dim3(1), dim3(1), 0, st, k.hdr, (int)HDR_EPOCH);
         e = hipGetLastError();
@@ -510,6 +619,7 @@ hipError_t launch_run(const ChainPlan &p) {
     k.twid = reinterpret_cast<const float2 *>(ws + lay.twid);
     k.hspec = reinterpret_cast<const float2 *>(ws + lay.hspec);
     k.nparts = fft_parts(Mtot);
+    k.casc = reinterpret_cast<const CascTab *>(ws + lay.casc);
     const int64_t nblocks = (lay.cpad / 2) * lay.ntiles;
     const bool s = p.S > 0;
     switch (Mtot > 0 ? p.fir_mode : FIR_NONE) {

@@ -102,10 +102,12 @@ template <> struct Tab<double> {
     static __device__ __forceinline__ const double *lb(const SecTab &t, int j) { return t.lb_d[j]; }
 };
 
-// Copies the fp32 tables of sections [s0, s0 + n) into LDS (whole
-// workgroup; the caller synchronises before and after).
-__device__ __forceinline__ void stage_tables(SecLds *dst, const SecTab *src, int s0, int n, int tid, int nthreads) {
-    constexpr int V = sizeof(SecLds) / 16;
+// Copies the fp32 tables (the leading sizeof(SL) bytes of each SecTab) of
+// sections [s0, s0 + n) into LDS (whole workgroup; the caller synchronises
+// before and after).
+template <class SL>
+__device__ __forceinline__ void stage_tables(SL *dst, const SecTab *src, int s0, int n, int tid, int nthreads) {
+    constexpr int V = sizeof(SL) / 16;
     for (int e = tid; e < n * V; e += nthreads) {
         const int s = e / V, i = e % V;
         reinterpret_cast<float4 *>(&dst[s])[i] = reinterpret_cast<const float4 *>(&src[s0 + s])[i];
@@ -429,7 +431,9 @@ __device__ void lookback(const TB &tb, const CarryCtx &cc, CT agg0, CT agg1, CT 
     int64_t base = cc.pos - 1;
     while (true) {
         const int64_t q = base - lane;
-        int st = q < 0 ? 3 : 0;  // 0 missing, 1 aggregate, 2 prefix, 3 before the first tile
+        // 0 missing, 1 aggregate, 2 prefix, 3 before the first tile; a tile
+        // beyond the look-back depth counts as a prefix of zero
+        int st = q < 0 ? 3 : ((tb.depth > 0 && q < cc.pos - tb.depth) ? 2 : 0);
         float r0 = 0.f, r1 = 0.f;
         int64_t spins = 0;
         while (true) {
@@ -566,6 +570,199 @@ __device__ void carry(const TB &tb, const CarryCtx &cc, float z0, float z1, floa
     madd2<TR>(s0, s1, Tab<CT>::fold(tb, lane), x0, x1);
     e0 = (float)s0;
     e1 = (float)s1;
+}
+
+// ------------------------------------------------ cascade-level carry
+// The same chunk scan as `carry`, with the tile-entering state P known (no
+// look-back) and a single workgroup barrier.  Returns the chunk-entering
+// state e of the lane's chunk and the group's tile aggregate E (the state at
+// the tile's end from a zero tile-entering state).  s_agg slot `buf` must
+// not be in use by a neighbouring call (callers alternate two slots).
+template <typename CT, class TB>
+__device__ void carry_local(const TB &tb, int lane, int gw, float z0, float z1, CT P0, CT P1, float &e0, float &e1,
+                            CT &E0, CT &E1, double (*s_agg)[GWAVES][2], int buf) {
+    CT w0 = (CT)z0, w1 = (CT)z1;
+    {
+        CT t0 = dpp<DPP_ROW_SHR + 1>(w0), t1 = dpp<DPP_ROW_SHR + 1>(w1);
+        madd2<false>(w0, w1, Tab<CT>::fold(tb, 1), t0, t1);
+        t0 = dpp<DPP_ROW_SHR + 2>(w0);
+        t1 = dpp<DPP_ROW_SHR + 2>(w1);
+        madd2<false>(w0, w1, Tab<CT>::fold(tb, 2), t0, t1);
+        t0 = dpp<DPP_ROW_SHR + 4>(w0);
+        t1 = dpp<DPP_ROW_SHR + 4>(w1);
+        madd2<false>(w0, w1, Tab<CT>::fold(tb, 4), t0, t1);
+        t0 = dpp<DPP_ROW_SHR + 8>(w0);
+        t1 = dpp<DPP_ROW_SHR + 8>(w1);
+        madd2<false>(w0, w1, Tab<CT>::fold(tb, 8), t0, t1);
+        t0 = dpp<DPP_ROW_BCAST15, 0xA>(w0);
+        t1 = dpp<DPP_ROW_BCAST15, 0xA>(w1);
+        madd2<false>(w0, w1, Tab<CT>::fold(tb, (lane & 15) + 1), t0, t1);
+        t0 = dpp<DPP_ROW_BCAST31, 0xC>(w0);
+        t1 = dpp<DPP_ROW_BCAST31, 0xC>(w1);
+        madd2<false>(w0, w1, Tab<CT>::fold(tb, (lane & 31) + 1), t0, t1);
+    }
+    if (lane == 63) {
+        s_agg[buf][gw][0] = (double)w0;
+        s_agg[buf][gw][1] = (double)w1;
+    }
+    __syncthreads();
+    const CT *Psi = Tab<CT>::psi(tb, 1);
+    CT A0 = 0, A1 = 0, ew0 = 0, ew1 = 0;
+#pragma unroll
+    for (int w = 0; w < GWAVES; ++w) {
+        if (w == gw) {
+            ew0 = A0;
+            ew1 = A1;
+        }
+        CT g0 = (CT)s_agg[buf][w][0], g1 = (CT)s_agg[buf][w][1];
+        madd2<false>(g0, g1, Psi, A0, A1);
+        A0 = g0;
+        A1 = g1;
+    }
+    E0 = A0;
+    E1 = A1;
+    CT x0 = ew0, x1 = ew1;  // wave-entering state
+    madd2<false>(x0, x1, Tab<CT>::psi(tb, gw), P0, P1);
+    CT s0 = dpp<DPP_WAVE_SHR1>(w0), s1 = dpp<DPP_WAVE_SHR1>(w1);
+    madd2<false>(s0, s1, Tab<CT>::fold(tb, lane), x0, x1);
+    e0 = (float)s0;
+    e1 = (float)s1;
+}
+
+// Decoupled look-back over the whole cascade state (D = 2S <= 16 components,
+// section s at components 2s, 2s+1), by one wave.  Lanes form 4 rows of 16:
+// row r watches predecessor pos-1-r, lane c of a row component c.  Every
+// record holds the tile aggregate (D tagged words) then the inclusive prefix
+// (D words).  T (LDS) holds the cascade's tile transition Phi_T, its square
+// and its fourth power, D x D row-major each.  Publishes the aggregate E
+// (LDS, D floats), writes the tile-entering state to P (LDS) and publishes
+// the inclusive prefix Phi_T P + E.  `known`: the state entering tile 0
+// (null = zero).  Mw: a D x D LDS matrix of this wave (the pending window
+// weight).
+struct CascCtx {
+    int lane, D;
+    int depth;         // look-back depth (0 = unbounded)
+    uint64_t *rec;     // record of tile 0 of this channel; tile q at rec + q * 2D
+    int64_t pos;       // tile position
+    uint32_t epoch;
+    uint32_t *hdr;
+    const float *known;
+};
+
+// sum_d Tm[c][d] v(src_row, d) for lanes c < D of every row (0 elsewhere);
+// Tm is D x D row-major.
+__device__ __forceinline__ float row_matvec(const float *Tm, int D, int c, float v, int src_row) {
+    float acc = 0.f;
+    const float *tr = Tm + (c < D ? c : 0) * D;
+    for (int d = 0; d < D; ++d) acc = fmaf(tr[d], __shfl(v, src_row * 16 + d), acc);
+    return c < D ? acc : 0.f;
+}
+
+__device__ void casc_lookback(const CascCtx &cc, const float *T, const float *E, float *P, float *Mw) {
+    const int lane = cc.lane, row = lane >> 4, c = lane & 15, D = cc.D;
+    const bool active = c < D;
+    const int W = 2 * D;
+    const uint64_t tag = (uint64_t)cc.epoch << 32;
+    const float Ec = active ? E[c] : 0.f;
+    if (row == 0 && active) st_word(cc.rec + cc.pos * W + c, tag | __float_as_uint(Ec));
+    float acc = 0.f;
+    if (cc.pos == 0) {
+        acc = (active && cc.known) ? cc.known[c] : 0.f;
+    } else {
+        // pending window weight (Phi_T^4)^windows, in LDS: lane l holds
+        // entries 4 l .. 4 l + 3 of the D x D row-major matrix
+        const int DD = D * D;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int e = 4 * lane + u;
+            if (e < DD) Mw[e] = (e / D == e % D) ? 1.f : 0.f;
+        }
+        const unsigned long long rmask0 = (D >= 16 ? 0xFFFFull : ((1ull << D) - 1ull));
+        int64_t base = cc.pos - 1;
+        while (true) {
+            const int64_t q = base - row;
+            float va = 0.f, vi = 0.f;
+            bool ha = false, hi = false;
+            if (cc.depth > 0 && q < cc.pos - cc.depth) {  // beyond the look-back depth: a zero prefix
+                hi = ha = true;
+            } else if (q < 0) {  // before tile 0: the prefix entering tile 0
+                hi = ha = true;
+                vi = (q == -1 && cc.known && active) ? cc.known[c] : 0.f;
+            }
+            int st[4];
+            int first = 4;
+            int64_t spins = 0;
+            bool poll = true;  // this lane's row still misses a record
+            while (true) {
+                if (poll && active && q >= 0) {
+                    const uint64_t *p = cc.rec + q * W;
+                    const uint64_t wa = ld_word(p + c), wi = ld_word(p + D + c);
+                    if ((wa >> 32) == cc.epoch) {
+                        ha = true;
+                        va = __uint_as_float((uint32_t)wa);
+                    }
+                    if ((wi >> 32) == cc.epoch) {
+                        hi = true;
+                        vi = __uint_as_float((uint32_t)wi);
+                    }
+                }
+                // a row is complete when every component's word is out (the
+                // words of one record may become visible in any order)
+                const unsigned long long bi = __ballot(!active || hi), ba = __ballot(!active || ha);
+                first = 4;
+                bool need = false;
+#pragma unroll
+                for (int r = 3; r >= 0; --r) {
+                    const unsigned long long rm = rmask0 << (16 * r);
+                    st[r] = ((bi & rm) == rm) ? 2 : (((ba & rm) == rm) ? 1 : 0);
+                    if (st[r] == 2) first = r;
+                }
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    if (r <= first && st[r] == 0) need = true;
+                if (!need) break;
+                if (++spins > SPIN_MAX) {  // never expected: report and finish
+                    if (lane == 0) atomicOr(&cc.hdr[HDR_ERROR], 1u);
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(4);
+                poll = st[row] == 0;
+            }
+            // row r contributes Phi_T^r times its aggregate (rows before the
+            // first complete prefix) or its prefix (that row); later rows 0
+            float v = (row < first) ? va : (row == first ? vi : 0.f);
+            if (!active) v = 0.f;
+            float t1 = row_matvec(T, D, c, v, (row + 1) & 3);  // rows 0, 2 += Phi_T * rows 1, 3
+            if (row == 0 || row == 2) v += t1;
+            float t2 = row_matvec(T + DD, D, c, v, 2);  // row 0 += Phi_T^2 * row 2
+            if (row == 0) v += t2;
+            // acc += (window weight) * R, R = row 0's vector
+            acc += row_matvec(Mw, D, c, v, 0);
+            if (first < 4) break;
+            // next window: M <- M Phi_T^4 in place.  Every lane reads before
+            // any lane writes: the wave's LDS accesses are issued in program
+            // order.
+            float nm[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int e = 4 * lane + u;
+                if (e < DD) {
+                    const int i = e / D, j = e % D;
+                    for (int d = 0; d < D; ++d) nm[u] = fmaf(Mw[i * D + d], T[2 * DD + d * D + j], nm[u]);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int e = 4 * lane + u;
+                if (e < DD) Mw[e] = nm[u];
+            }
+            base -= 4;
+        }
+    }
+    // tile-entering state, and the inclusive prefix Phi_T P + E
+    if (row == 0 && active) P[c] = acc;
+    const float inc = Ec + row_matvec(T, D, c, acc, 0);
+    if (row == 0 && active) st_word(cc.rec + cc.pos * W + D + c, tag | __float_as_uint(inc));
 }
 
 }  // namespace tfx

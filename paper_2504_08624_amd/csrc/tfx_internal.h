@@ -46,7 +46,8 @@ enum FirMode { FIR_NONE = 0, FIR_DIRECT = 1, FIR_FFT = 2, FIR_TOEPLITZ = 3 };
 struct alignas(16) SecTab {
     float coef[5];
     int32_t hiq;             // 1: pole radius > 0.999 -> carry in FP64
-    int32_t pad[2];
+    int32_t depth;           // look-back depth d: PhiT^d <= 2^-60, older tiles drop out (0 = none)
+    int32_t pad;
     float fold[64][4];       // Phi^k, k = 0..63
     float psi[GWAVES][4];    // Psi^w, w < GWAVES
     float lb[9][4];          // PhiT^(2^j), j = 0..8
@@ -60,14 +61,45 @@ struct alignas(16) SecTab {
 struct alignas(16) SecLds {
     float coef[5];
     int32_t hiq;
-    int32_t pad[2];
+    int32_t depth;
+    int32_t pad;
     float fold[64][4];
     float psi[GWAVES][4];
     float lb[9][4];
 };
 static_assert(offsetof(SecTab, lb) == offsetof(SecLds, lb), "SecLds must be the leading part of SecTab");
 static_assert(sizeof(SecLds) <= offsetof(SecTab, fold_d), "SecLds must be the leading part of SecTab");
+// The part of SecLds the cascade-level path reads (no look-back powers).
+struct alignas(16) SecLdsC {
+    float coef[5];
+    int32_t hiq;
+    int32_t depth;
+    int32_t pad;
+    float fold[64][4];
+    float psi[GWAVES][4];
+};
+static_assert(offsetof(SecTab, psi) == offsetof(SecLdsC, psi), "SecLdsC must be the leading part of SecTab");
+static_assert(sizeof(SecLdsC) % 16 == 0, "SecLdsC is copied in 16-byte pieces");
 constexpr int LDS_SECTIONS = 32;  // sections staged in LDS at a time
+
+// Cascades of up to CASC_MAX sections (without FP64-carry sections) carry
+// their whole 2S-component state across tiles in one look-back per tile.
+//
+// Look-back depth: when every entry of the tile transition's d-th power is
+// at most 2^-60 (about 1e-18), a tile d or more tiles back changes the
+// state entering this tile by less than 2^-60 of its own state: 10^10 times
+// below one fp32 rounding.  Such tiles are left out of the look-back, so
+// for fast-decaying filters a tile needs only its d nearest predecessors'
+// aggregates and never waits for a chain of inclusive prefixes.
+constexpr double DEPTH_EPS = 8.673617379884035e-19;  // 2^-60
+// Powers of the cascade's tile transition A_c^3072 (state order: section s
+// at components 2s, 2s+1), zero-padded to 16 x 16.
+constexpr int CASC_MAX = 8;
+struct alignas(16) CascTab {
+    int32_t depth;       // look-back depth d: max |Phi_T^d| <= 2^-60 (0 = none within 64 tiles)
+    int32_t pad[3];
+    float T[3][16][16];  // Phi_T, Phi_T^2, Phi_T^4
+};
 
 // Header words of a workspace: look-back error bit, look-back epoch, and
 // whether any section needs the FP64 carry (the filter kernels come in two
@@ -114,7 +146,7 @@ struct ChainPlan {
 
 // Workspace layout of a chain/SOS/FIR call.
 struct WsLayout {
-    size_t hdr, tab, recs, taps, merge, twid, hspec, tw64, ttab, total;
+    size_t hdr, tab, recs, casc, taps, merge, twid, hspec, tw64, ttab, total;
     int64_t ntiles, cpad;
 };
 WsLayout ws_layout(int64_t C, int64_t N, int32_t S, int32_t M_merged, int32_t n_fir, int32_t fir_mode);

@@ -33,7 +33,7 @@ __device__ void put4(float *f, double *d, const double *m) {
 __device__ void build_section(SecTab *tb, const float *co, int Lc) {
     const double a1 = co[3], a2 = co[4];
     for (int i = 0; i < 5; ++i) tb->coef[i] = co[i];
-    tb->pad[0] = tb->pad[1] = 0;
+    tb->pad = 0;
     const double A[4] = {-a1, 1.0, -a2, 0.0};
     double P[4] = {A[0], A[1], A[2], A[3]};
     for (int t = 1; t < Lc; ++t) mat2_mul(P, A, P);
@@ -50,6 +50,17 @@ __device__ void build_section(SecTab *tb, const float *co, int Lc) {
         mat2_mul(W, Psi, W);
     }
     double B[4] = {W[0], W[1], W[2], W[3]};  // PhiT = A^T
+    {  // look-back depth
+        double Q[4] = {W[0], W[1], W[2], W[3]};
+        tb->depth = 0;
+        for (int k = 1; k <= 64; ++k) {
+            if (fmax(fmax(fabs(Q[0]), fabs(Q[1])), fmax(fabs(Q[2]), fabs(Q[3]))) <= DEPTH_EPS) {
+                tb->depth = k;
+                break;
+            }
+            mat2_mul(Q, W, Q);
+        }
+    }
     for (int j = 0; j < 9; ++j) {
         put4(tb->lb[j], tb->lb_d[j], B);
         mat2_mul(B, B, B);
@@ -94,6 +105,91 @@ __global__ void prep_kernel(PrepArgs a) {
         }
         build_section(&a.tab[gid], a.sos.ptr[st] + 5 * s, L);
     }
+}
+
+// Tile-transition powers of the whole cascade for the cascade-level
+// look-back, in FP64.  The cascade's one-sample transition F (zero input):
+// block (i, i) = A_i; block (i, j), j < i = B_i (prod_{j<l<i} D_l) C, since
+// section i's input is section i-1's output; Phi_T = F^3072 = (F^8 F^16)^128.
+// One block of 256 threads, one matrix element each.
+__device__ void mm16(const double (*A)[16], const double (*B)[16], double (*R)[16], int i, int j) {
+    double acc = 0.0;
+    for (int k = 0; k < 16; ++k) acc += A[i][k] * B[k][j];
+    __syncthreads();  // every read of A and B done (R may alias neither, but callers reuse buffers)
+    R[i][j] = acc;
+    __syncthreads();
+}
+
+__global__ void casc_table_kernel(StageList sos, int32_t S, CascTab *out) {
+    __shared__ double co[CASC_MAX][5];
+    __shared__ double M0[16][16], M1[16][16], M2[16][16], M3[16][16];
+    const int tid = threadIdx.x, i = tid >> 4, j = tid & 15;
+    if (tid < S * 5) {
+        int s = tid / 5, st = 0;
+        const int k = tid % 5;
+        while (s >= sos.len[st]) {
+            s -= sos.len[st];
+            ++st;
+        }
+        co[tid / 5][k] = sos.ptr[st][5 * s + k];
+    }
+    __syncthreads();
+    const int D = 2 * S;
+    double f = 0.0;
+    if (i < D && j < D) {
+        const int si = i >> 1, ri = i & 1, sj = j >> 1, cj = j & 1;
+        const double b0 = co[si][0], b1 = co[si][1], b2 = co[si][2], a1 = co[si][3], a2 = co[si][4];
+        if (si == sj) {
+            f = ri == 0 ? (cj == 0 ? -a1 : 1.0) : (cj == 0 ? -a2 : 0.0);
+        } else if (sj < si && cj == 0) {
+            double pr = ri == 0 ? b1 - a1 * b0 : b2 - a2 * b0;
+            for (int l = sj + 1; l < si; ++l) pr *= co[l][0];
+            f = pr;
+        }
+    }
+    M0[i][j] = f;
+    __syncthreads();
+    mm16(M0, M0, M1, i, j);  // F^2
+    mm16(M1, M1, M0, i, j);  // F^4
+    mm16(M0, M0, M2, i, j);  // F^8
+    mm16(M2, M2, M1, i, j);  // F^16
+    mm16(M1, M2, M3, i, j);  // F^24
+    for (int t = 0; t < 7; ++t) {  // F^(24 * 128) = F^3072
+        mm16(M3, M3, M0, i, j);
+        M3[i][j] = M0[i][j];
+        __syncthreads();
+    }
+    out->T[0][i][j] = (float)M3[i][j];
+    {  // look-back depth: the first d with max |Phi_T^d| <= 2^-60
+        __shared__ double amax[256];
+        __shared__ int dep;
+        if (tid == 0) dep = 0;
+        M0[i][j] = M3[i][j];
+        __syncthreads();
+        for (int k = 1; k <= 64; ++k) {
+            amax[tid] = fabs(M0[i][j]);
+            __syncthreads();
+            for (int w = 128; w >= 1; w >>= 1) {
+                if (tid < w) amax[tid] = fmax(amax[tid], amax[tid + w]);
+                __syncthreads();
+            }
+            const bool hit = amax[0] <= DEPTH_EPS;
+            __syncthreads();
+            if (hit) {
+                if (tid == 0) dep = k;
+                break;
+            }
+            mm16(M0, M3, M1, i, j);
+            M0[i][j] = M1[i][j];
+            __syncthreads();
+        }
+        __syncthreads();
+        if (tid == 0) out->depth = dep;
+    }
+    mm16(M3, M3, M1, i, j);
+    out->T[1][i][j] = (float)M1[i][j];
+    mm16(M1, M1, M2, i, j);
+    out->T[2][i][j] = (float)M2[i][j];
 }
 
 struct MergeArgs {
@@ -269,6 +365,11 @@ hipError_t launch_tables(const ChainPlan &p, const WsLayout &lay, const float *h
         if (nb < 1) nb = 1;
         hipLaunchKernelGGL(prep_kernel, dim3((unsigned)nb), dim3(256), 0, p.stream, pa);
         if ((e = hipGetLastError()) != hipSuccess) return e;
+        if (p.S <= CASC_MAX) {
+            hipLaunchKernelGGL(casc_table_kernel, dim3(1), dim3(256), 0, p.stream, p.sos, p.S,
+                               reinterpret_cast<CascTab *>(ws + lay.casc));
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+        }
     }
     return hipSuccess;
 }

@@ -49,6 +49,38 @@ def test_sos_parity(S, N):
     assert_close(y, O.sos(x, sec), TOL_IIR_F32, "sos S=%d N=%d" % (S, N))
 
 
+def _mixed_sections(key, S, nres, r_lo, r_hi):
+    """nres resonators with poles at radius r_lo..r_hi (unit gain at the pole
+    angle) followed by mild sections (pole radius 0.3-0.6, unit DC gain); all
+    zeros at radius 0.5.  Unlike cascades of many unit-circle-zero resonators
+    (gains of 1e-20 and below), the whole cascade stays well conditioned in
+    fp32 (a sequential fp32 filter loses at most ~1.5e-5)."""
+    g = signals.rng(*key)
+    r = np.concatenate([g.uniform(r_lo, r_hi, nres), g.uniform(0.3, 0.6, S - nres)])
+    th = g.uniform(0.1, np.pi - 0.1, S)
+    ph = g.uniform(0.0, np.pi, S)
+    rows = design.from_polar(r, th, np.full(S, 0.5), ph, np.ones(S))
+    for i in range(S):
+        gain = abs(design.sos_response(rows[i:i + 1], [th[i] if i < nres else 0.0])[0])
+        rows[i, 0:3] /= gain
+    return rows.astype(np.float32)
+
+
+@pytest.mark.parametrize("S,nres,r_lo,r_hi", [(3, 3, 0.997, 0.999), (8, 2, 0.997, 0.999), (10, 2, 0.995, 0.999),
+                                               (12, 1, 0.998, 0.999)])
+def test_sos_slow_decay_deep_lookback(S, nres, r_lo, r_hi):
+    # poles just below the FP64-carry threshold: the tile transition decays
+    # slowly, so the look-back reaches several tiles back (up to 8 sections as
+    # one cascade state, beyond that section by section); impulses every
+    # 5000 samples excite the long tails
+    C, N = 3, 120 * T + 11
+    x = _x(C, N, (105, S))
+    x[:, ::5000] += 1.0
+    sec = _mixed_sections((106, S), S, nres, r_lo, r_hi)
+    y = _cpu(tfx.sos(_gpu(x), _gpu(sec)))
+    assert_close(y, O.sos(x, sec), TOL_IIR_F32, "sos S=%d r in [%g, %g]" % (S, r_lo, r_hi))
+
+
 def test_sos_many_tiles_lookback_windows():
     # 200 tiles per channel: look-back crosses several 64-tile windows
     C, N = 2, 200 * T + 5

@@ -156,3 +156,55 @@ def test_chunked_scan_model_long_lookback():
     y, _ = model_channel(x, sos, L=2, lanes=2, waves=2, rng=rng)
     ref = O.sos(x[None], sos)[0]
     assert np.max(np.abs(y - ref)) < 1e-9 * np.max(np.abs(ref))
+
+
+# ------------------------------------------------ cascade-level carry
+
+def _cascade_transition(sec):
+    """One-sample transition of a cascade's free response (zero input), state
+    order (s1, s2) of section 0, then section 1, ...: block (i, i) = A_i,
+    block (i, j < i) = B_i (prod_{j<l<i} D_l) C, C = (1, 0), D_l = b0 of
+    section l, B_i = (b1 - a1 b0, b2 - a2 b0) of section i."""
+    S = len(sec)
+    F = np.zeros((2 * S, 2 * S))
+    for i, (b0, b1, b2, a1, a2) in enumerate(sec):
+        F[2 * i:2 * i + 2, 2 * i:2 * i + 2] = [[-a1, 1.0], [-a2, 0.0]]
+        B = np.array([b1 - a1 * b0, b2 - a2 * b0])
+        for j in range(i):
+            pr = np.prod([sec[l][0] for l in range(j + 1, i)]) if i > j + 1 else 1.0
+            F[2 * i:2 * i + 2, 2 * j] = B * pr
+    return F
+
+
+@pytest.mark.parametrize("S", [1, 2, 5, 8])
+def test_cascade_transition_is_the_free_response(S):
+    # the state of the whole cascade after n samples of zero input, started
+    # from an arbitrary state, is F^n times that state (run by the oracle)
+    from paper_2504_08624_amd import design, signals
+    sec = design.random_sections(signals.rng(71, S), S, 0.5, 0.99)
+    st = signals.rng(72, S).standard_normal((1, S, 2))
+    n = 300
+    _, s_end = O.sos(np.zeros((1, n)), sec, state_in=st, return_state=True)
+    F = _cascade_transition(sec)
+    np.testing.assert_allclose(np.linalg.matrix_power(F, n) @ st.reshape(-1), s_end.reshape(-1),
+                               rtol=1e-10, atol=1e-12)
+
+
+def test_cascade_look_back_two_phase_equals_oracle():
+    # per tile: (A) run the cascade from a zero tile-entering state -> the
+    # cascade's tile aggregate E_t; (B) P_{t+1} = F^T P_t + E_t; (C) run the
+    # cascade from P_t.  The outputs equal the oracle's.
+    from paper_2504_08624_amd import design, signals
+    S, T, ntiles = 4, 96, 7
+    sec = design.random_sections(signals.rng(73), S, 0.5, 0.995)
+    x = signals.rng(74).standard_normal(T * ntiles)
+    FT = np.linalg.matrix_power(_cascade_transition(sec), T)
+    P = np.zeros(2 * S)
+    y = np.empty_like(x)
+    for t in range(ntiles):
+        seg = x[t * T:(t + 1) * T][None, :]
+        _, E = O.sos(seg, sec, state_in=np.zeros((1, S, 2)), return_state=True)
+        yt = O.sos(seg, sec, state_in=P.reshape(1, S, 2))
+        y[t * T:(t + 1) * T] = yt[0]
+        P = FT @ P + E.reshape(-1)
+    np.testing.assert_allclose(y, O.sos(x[None, :], sec)[0], rtol=1e-9, atol=1e-12)
