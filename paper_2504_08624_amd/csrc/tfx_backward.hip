@@ -229,26 +229,27 @@ __global__ __launch_bounds__(WG, 3) void sos_bwd_kernel(BArgs a) {
         else
             carry<float, true>(tb, cc, m0, m1, e0, e1, s_agg, s_pre, buf);
         // (d) the adjoint recursion from the true state: input gradient and
-        //     coefficient-gradient sums
-        double dA00 = 0.0, dA10 = 0.0, dB0 = 0.0, dB1 = 0.0, dD = 0.0;
+        //     coefficient-gradient sums (24 terms per chunk by fp32 fused
+        //     multiply-adds, then FP64 across chunks and tiles)
+        float dA00 = 0.f, dA10 = 0.f, dB0 = 0.f, dB1 = 0.f, dD = 0.f;
         m0 = e0;
         m1 = e1;  // lambda_{n+1}
 #pragma unroll
         for (int r = L - 1; r >= 0; --r) {
             const float gv = gr[r];
             const float gx = fmaf(b0, gv, fmaf(B0, m0, B1 * m1));
-            dA00 = fma((double)m0, (double)sf[r], dA00);
-            dA10 = fma((double)m1, (double)sf[r], dA10);
-            dB0 = fma((double)m0, (double)xs[r], dB0);
-            dB1 = fma((double)m1, (double)xs[r], dB1);
-            dD = fma((double)gv, (double)xs[r], dD);
+            dA00 = fmaf(m0, sf[r], dA00);
+            dA10 = fmaf(m1, sf[r], dA10);
+            dB0 = fmaf(m0, xs[r], dB0);
+            dB1 = fmaf(m1, xs[r], dB1);
+            dD = fmaf(gv, xs[r], dD);
             const float n0v = fmaf(-a1, m0, fmaf(-a2, m1, gv));
             m1 = m0;
             m0 = n0v;
             gr[r] = gx;
         }
         // (e) group sums, in a fixed order
-        double red[5] = {dA00, dA10, dB0, dB1, dD};
+        double red[5] = {(double)dA00, (double)dA10, (double)dB0, (double)dB1, (double)dD};
 #pragma unroll
         for (int k = 0; k < 5; ++k) {
 #pragma unroll
@@ -407,6 +408,135 @@ __global__ __launch_bounds__(WG) void fir_gh_part_kernel(GhArgs a) {
     }
 }
 
+// FIR gradients of a single-partition FFT FIR (M <= 1025) in one pass over
+// the tiles.  For tile t of a channel pair, with B the upstream-gradient
+// block [n0, n0 + 4096) (zero past the signal) and X the input tile
+// [n0, n0 + 3072) zero-padded to 4096 points:
+//   dL/dx[n0 + d] = IFFT(conj(H) FFT(B))[d], d < 3072, since
+//                   dL/dx[n] = sum_k h[k] g[n + k] and k + d < 4096;
+//   sum_{m in tile} x[m] g[m + k] = Re IFFT(conj(FFT(X)) FFT(B))[k], k <= 1024,
+// for both channels of the pair at once (the two packed channels' cross
+// terms are purely imaginary, so the real part is the sum of the two
+// correlations).  One FFT of B serves both.  A workgroup walks tiles
+// blockIdx.x, + gridDim.x, ... and sums conj(FFT(X)) FFT(B) over them in
+// fp32 registers (lane t keeps bins t + 256 k3); its sum is written once, and
+// FP64 reductions in a fixed order plus one inverse DFT per lag give dL/dh.
+struct FirBwdArgs {
+    const float *x, *g;
+    float *gx;
+    int64_t C, N, ldx, ldg, ldgx;
+    int64_t cpad, ntiles;
+    const float2 *twid, *hspec;
+    float2 *spart;  // [workgroup][16][256] summed spectra, bin 256 k3 + t at [k3][t]
+    int32_t want_gh;
+};
+
+__global__ __launch_bounds__(WG) void fir_bwd_kernel(FirBwdArgs a) {
+    __shared__ __align__(16) float lds[2 * NFFT];
+    const int tid = threadIdx.x;
+    const int64_t npairs = a.cpad / 2, nitems = npairs * a.ntiles;
+    float ar[16], ai[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) ar[k] = ai[k] = 0.f;
+    for (int64_t it = blockIdx.x; it < nitems; it += gridDim.x) {
+        const int64_t tile = it / npairs, pair = it % npairs;
+        const int64_t chA = 2 * pair, chB = chA + 1;
+        const int64_t n0 = tile * T;
+        const bool hasB = chB < a.C;
+        float zr[16], zi[16];
+        // keeps the twiddle and spectrum loads inside the loop: hoisted out of
+        // it they would hold some 150 registers for the whole kernel
+        asm volatile("" ::: "memory");
+        __syncthreads();  // the previous tile's last LDS reads
+        load_pair_block(zr, zi, a.g + chA * a.ldg, hasB ? a.g + chB * a.ldg : nullptr, n0, a.N, a.N, tid);
+        fft4096_forward(zr, zi, lds, a.twid, tid);
+        if (a.want_gh) {
+            float br[16], bi[16];
+#pragma unroll
+            for (int k = 0; k < 16; ++k) {
+                br[k] = zr[k];
+                bi[k] = zi[k];
+            }
+            load_pair_block(zr, zi, a.x + chA * a.ldx, hasB ? a.x + chB * a.ldx : nullptr, n0, a.N, n0 + T, tid);
+            __syncthreads();  // the B transform's last LDS reads
+            fft4096_forward(zr, zi, lds, a.twid, tid);
+#pragma unroll
+            for (int k = 0; k < 16; ++k) {  // += conj(X) B
+                ar[k] = fmaf(zr[k], br[k], fmaf(zi[k], bi[k], ar[k]));
+                ai[k] = fmaf(zr[k], bi[k], fmaf(-zi[k], br[k], ai[k]));
+                zr[k] = br[k];
+                zi[k] = bi[k];
+            }
+        }
+        spectrum_product(zr, zi, a.hspec, tid, true);
+        fft4096_inverse(zr, zi, lds, a.twid, tid);
+        float *oA = a.gx + chA * a.ldgx, *oB = hasB ? a.gx + chB * a.ldgx : nullptr;
+#pragma unroll
+        for (int q = 0; q < 12; ++q) {
+            const int64_t n = n0 + 256 * q + tid;
+            if (n < a.N) {
+                oA[n] = zr[q];
+                if (hasB) oB[n] = zi[q];
+            }
+        }
+    }
+    if (a.want_gh) {
+        float2 *o = a.spart + (int64_t)blockIdx.x * NFFT;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) o[256 * k + tid] = make_float2(ar[k], ai[k]);
+    }
+}
+
+// sum1[split][f] = sum of the workgroup spectra w in [split * SPEC_SPLIT,
+// (split + 1) * SPEC_SPLIT) at bin f, in FP64 and in workgroup order.
+constexpr int SPEC_SPLIT = 64;
+constexpr int FIR_BWD_WGS = 512;  // two per CU fit (about 230 VGPRs)
+
+__global__ void fir_spec_reduce1_kernel(const float2 *spart, int64_t nwg, double2 *sum1) {
+    const int f = blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t w0 = (int64_t)blockIdx.y * SPEC_SPLIT;
+    const int64_t w1 = min(nwg, w0 + SPEC_SPLIT);
+    double sr = 0.0, si = 0.0;
+#pragma unroll 8
+    for (int64_t w = w0; w < w1; ++w) {
+        const float2 v = spart[w * NFFT + f];
+        sr += (double)v.x;
+        si += (double)v.y;
+    }
+    sum1[(int64_t)blockIdx.y * NFFT + f] = make_double2(sr, si);
+}
+
+__global__ void fir_spec_reduce2_kernel(const double2 *sum1, int32_t nsplit, double2 *spec) {
+    const int f = blockIdx.x * blockDim.x + threadIdx.x;
+    double sr = 0.0, si = 0.0;
+    for (int k = 0; k < nsplit; ++k) {
+        const double2 v = sum1[(int64_t)k * NFFT + f];
+        sr += v.x;
+        si += v.y;
+    }
+    spec[f] = make_double2(sr, si);
+}
+
+// dL/dh[k] = Re(sum_f P[f] e^{+2 pi i f k / 4096}) / 4096 for lag k = block
+// index: thread t takes bins f = t + 256 j, then a fixed-order block sum.
+__global__ void fir_gh_dft_kernel(const double2 *spec, const double2 *tw64, float *gh) {
+    __shared__ double wsum[WG / 64];
+    const int k = blockIdx.x, t = threadIdx.x;
+    double acc = 0.0;
+#pragma unroll 4
+    for (int j = 0; j < 16; ++j) {
+        const int f = t + 256 * j;
+        const double2 p = spec[f];
+        const double2 w = tw64[(f * k) & (NFFT - 1)];  // e^{-i theta}: Re(p e^{+i theta}) = p.x w.x + p.y w.y
+        acc = fma(p.x, w.x, fma(p.y, w.y, acc));
+    }
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) acc += __shfl_xor(acc, d);
+    if ((t & 63) == 0) wsum[t >> 6] = acc;
+    __syncthreads();
+    if (t == 0) gh[k] = (float)(((wsum[0] + wsum[1]) + (wsum[2] + wsum[3])) / NFFT);
+}
+
 // Two-level FP64 reduction of the tap-gradient partials, in a fixed order:
 // level 1 sums the partials of 128 consecutive blocks per lag
 // (sum1[split][k]), level 2 the splits in order.
@@ -479,19 +609,32 @@ BwdLayout bwd_layout(int64_t C, int64_t N, int32_t S, int32_t M_merged, int32_t 
     b.gfbuf = off;
     if (both) off += al256((size_t)C * N * sizeof(float));
     b.nlag = 0;
-    b.part_gh = b.gh1 = b.gH = b.obuf = b.twid = b.tw64 = off;
+    b.spec_path = n_fir > 0 && fir_mode == FIR_FFT && fft_parts(M_merged) == 1;
+    b.spec_wg = b.spec_nsplit = 0;
+    b.part_gh = b.gh1 = b.gH = b.obuf = b.twid = b.tw64 = b.spec = off;
     if (n_fir > 0 && ntiles > 0) {
-        b.nlag = (M_merged + FFT_PART - 1) / FFT_PART;
-        off += al256((size_t)b.nlag * npairs * ntiles * FFT_PART * sizeof(float));
-        b.gh1 = off;
-        off += al256((size_t)((npairs * ntiles + GH_SPLIT - 1) / GH_SPLIT) * M_merged * sizeof(double));
+        if (b.spec_path) {
+            const int64_t nitems = npairs * ntiles;
+            b.spec_wg = nitems < FIR_BWD_WGS ? nitems : FIR_BWD_WGS;
+            b.spec_nsplit = (b.spec_wg + SPEC_SPLIT - 1) / SPEC_SPLIT;
+            off += al256((size_t)b.spec_wg * NFFT * sizeof(float2));
+            b.gh1 = off;
+            off += al256((size_t)b.spec_nsplit * NFFT * sizeof(double2));
+            b.spec = off;
+            off += al256(NFFT * sizeof(double2));
+        } else {
+            b.nlag = (M_merged + FFT_PART - 1) / FFT_PART;
+            off += al256((size_t)b.nlag * npairs * ntiles * FFT_PART * sizeof(float));
+            b.gh1 = off;
+            off += al256((size_t)((npairs * ntiles + GH_SPLIT - 1) / GH_SPLIT) * M_merged * sizeof(double));
+        }
         b.gH = off;
         off += al256((size_t)M_merged * sizeof(float));
         b.obuf = off;
         if (n_fir > 1) off += al256((size_t)M_merged * 2 * sizeof(double));
         b.twid = b.tw64 = off;
         if (fir_mode != FIR_FFT) {
-            off += al256(NFFT * sizeof(float2));
+            off += al256(TWID_ENTRIES * sizeof(float2));
             b.tw64 = off;
             off += al256(NFFT * sizeof(double2));
         }
@@ -594,42 +737,75 @@ hipError_t launch_backward(const BwdPlan &bp) {
     if (!has_fir) return hipSuccess;
     const float *gfc = has_sos ? gf : bp.gy;
     const int64_t ldgfc = has_sos ? ldgf : bp.ldg;
-    // input gradient: correlation of the cascade-input gradient with the taps
-    if ((e = launch_fir_pass(p, lay.fwd, gfc, ldgfc, bp.gx, bp.ldgx, true)) != hipSuccess) return e;
-    // gradient of the merged taps
     bool any = false;
     for (int i = 0; i < bp.gfir.n; ++i) any = any || bp.gfir.ptr[i] != nullptr;
-    if (!any) return hipSuccess;
-    GhArgs g{};
-    g.x = p.x;
-    g.g = gfc;
-    g.C = p.C;
-    g.N = p.N;
-    g.ldx = p.ldx;
-    g.ldg = ldgfc;
-    g.M = M;
-    g.cpad = cpad;
-    g.twid = reinterpret_cast<const float2 *>(ws + lay.fwd.twid);
-    g.part = reinterpret_cast<float *>(ws + lay.part_gh);
-    if (p.fir_mode != FIR_FFT) {  // the direct path's prepare leaves no twiddles
-        g.twid = reinterpret_cast<const float2 *>(ws + lay.twid);
-        if ((e = launch_twiddles(reinterpret_cast<float2 *>(ws + lay.twid), reinterpret_cast<double2 *>(ws + lay.tw64),
-                                 st)) != hipSuccess)
-            return e;
-    }
-    hipLaunchKernelGGL(fir_gh_part_kernel, dim3((unsigned)(npairs * ntiles), (unsigned)lay.nlag), dim3(WG), 0, st,
-                       g);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
     float *gH = p.firs.n == 1 ? bp.gfir.ptr[0] : reinterpret_cast<float *>(ws + lay.gH);
-    const int64_t nbx = npairs * ntiles;
-    const int32_t nsplit = (int32_t)((nbx + GH_SPLIT - 1) / GH_SPLIT);
-    double *sum1 = reinterpret_cast<double *>(ws + lay.gh1);
-    hipLaunchKernelGGL(fir_gh_reduce1_kernel, dim3((unsigned)((M + 255) / 256), (unsigned)nsplit), dim3(256), 0, st,
-                       static_cast<const float *>(g.part), M, nbx, sum1);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(fir_gh_reduce2_kernel, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, st,
-                       static_cast<const double *>(sum1), M, nsplit, gH);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (lay.spec_path) {
+        // input gradient and tap-gradient spectra in one pass, then the
+        // fixed-order reductions and the inverse DFT per lag
+        FirBwdArgs fb{};
+        fb.x = p.x;
+        fb.g = gfc;
+        fb.gx = bp.gx;
+        fb.C = p.C;
+        fb.N = p.N;
+        fb.ldx = p.ldx;
+        fb.ldg = ldgfc;
+        fb.ldgx = bp.ldgx;
+        fb.cpad = cpad;
+        fb.ntiles = ntiles;
+        fb.twid = reinterpret_cast<const float2 *>(ws + lay.fwd.twid);
+        fb.hspec = reinterpret_cast<const float2 *>(ws + lay.fwd.hspec);
+        fb.spart = reinterpret_cast<float2 *>(ws + lay.part_gh);
+        fb.want_gh = any ? 1 : 0;
+        hipLaunchKernelGGL(fir_bwd_kernel, dim3((unsigned)lay.spec_wg), dim3(WG), 0, st, fb);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        if (!any) return hipSuccess;
+        double2 *sum1 = reinterpret_cast<double2 *>(ws + lay.gh1);
+        double2 *spec = reinterpret_cast<double2 *>(ws + lay.spec);
+        hipLaunchKernelGGL(fir_spec_reduce1_kernel, dim3(NFFT / 256, (unsigned)lay.spec_nsplit), dim3(256), 0, st,
+                           static_cast<const float2 *>(fb.spart), lay.spec_wg, sum1);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        hipLaunchKernelGGL(fir_spec_reduce2_kernel, dim3(NFFT / 256), dim3(256), 0, st,
+                           static_cast<const double2 *>(sum1), (int32_t)lay.spec_nsplit, spec);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        hipLaunchKernelGGL(fir_gh_dft_kernel, dim3((unsigned)M), dim3(WG), 0, st, static_cast<const double2 *>(spec),
+                           reinterpret_cast<const double2 *>(ws + lay.fwd.tw64), gH);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    } else {
+        // input gradient: correlation of the cascade-input gradient with the taps
+        if ((e = launch_fir_pass(p, lay.fwd, gfc, ldgfc, bp.gx, bp.ldgx, true)) != hipSuccess) return e;
+        if (!any) return hipSuccess;
+        GhArgs g{};
+        g.x = p.x;
+        g.g = gfc;
+        g.C = p.C;
+        g.N = p.N;
+        g.ldx = p.ldx;
+        g.ldg = ldgfc;
+        g.M = M;
+        g.cpad = cpad;
+        g.twid = reinterpret_cast<const float2 *>(ws + lay.fwd.twid);
+        g.part = reinterpret_cast<float *>(ws + lay.part_gh);
+        if (p.fir_mode != FIR_FFT) {  // the direct path's prepare leaves no twiddles
+            g.twid = reinterpret_cast<const float2 *>(ws + lay.twid);
+            if ((e = launch_twiddles(reinterpret_cast<float2 *>(ws + lay.twid),
+                                     reinterpret_cast<double2 *>(ws + lay.tw64), st)) != hipSuccess)
+                return e;
+        }
+        hipLaunchKernelGGL(fir_gh_part_kernel, dim3((unsigned)(npairs * ntiles), (unsigned)lay.nlag), dim3(WG), 0,
+                           st, g);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        const int64_t nbx = npairs * ntiles;
+        const int32_t nsplit = (int32_t)((nbx + GH_SPLIT - 1) / GH_SPLIT);
+        double *sum1 = reinterpret_cast<double *>(ws + lay.gh1);
+        hipLaunchKernelGGL(fir_gh_reduce1_kernel, dim3((unsigned)((M + 255) / 256), (unsigned)nsplit), dim3(256), 0,
+                           st, static_cast<const float *>(g.part), M, nbx, sum1);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        hipLaunchKernelGGL(fir_gh_reduce2_kernel, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, st,
+                           static_cast<const double *>(sum1), M, nsplit, gH);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
     if (p.firs.n == 1) return hipSuccess;
     // several FIR stages: chain rule through the tap convolution
     double *o0 = reinterpret_cast<double *>(ws + lay.obuf), *o1 = o0 + M;

@@ -50,7 +50,7 @@ struct BatchArgs {
 };
 
 // HIQ: the variant with the FP64 carry; both run, the one that does not match
-// the batch's high-Q word exits at once.
+// the batch's high-Q word advances the look-back epoch and exits.
 template <int LC, bool HIQ>
 __global__ __launch_bounds__(WG) void batch_kernel(BatchArgs a) {
     typedef Chunk<LC> K;
@@ -61,7 +61,10 @@ __global__ __launch_bounds__(WG) void batch_kernel(BatchArgs a) {
     __shared__ int s_clip;
     extern __shared__ __align__(16) SecLds s_tab[];  // fp32 tables, LDS_SECTIONS at a time
 
-    if ((a.hdr[HDR_HIQ] != 0u) != HIQ) return;
+    if ((a.hdr[HDR_HIQ] != 0u) != HIQ) {  // the other variant runs
+        advance_epoch(a.hdr);
+        return;
+    }
     const int tid = threadIdx.x, lane = tid & 63, grp = tid / GL, gl = tid % GL, gw = gl >> 6;
     const int64_t id = blockIdx.x;
     if (tid == 0) {
@@ -144,11 +147,6 @@ hipError_t upload_descriptors(const ClipDesc *desc, int32_t n, const BatchLayout
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
-}
-
-__global__ void batch_bump_epoch_kernel(uint32_t *hdr) {
-    const uint32_t ne = (hdr[HDR_EPOCH] + 1u) & EPOCH_MASK;
-    hdr[HDR_EPOCH] = ne == 0u ? 1u : ne;
 }
 
 // ------------------------------------------------------------------- host
@@ -238,9 +236,7 @@ hipError_t launch_batch_run(const BatchLayout &lay, int lc, int32_t nclips, void
         }
         e = hipGetLastError();
     }
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(batch_bump_epoch_kernel, dim3(1), dim3(1), 0, st, a.hdr);
-    return hipGetLastError();
+    return e;
 }
 
 }  // namespace tfx

@@ -130,7 +130,7 @@ __device__ void fft_block(const KArgs &a, float *lds, int64_t pair, int64_t n0, 
             const float sg = a.correlate ? -1.f : 1.f;
 #pragma unroll 4
             for (int k3 = 0; k3 < 16; ++k3) {
-                const float2 w = hs[tid + 256 * k3];
+                const float2 w = hs[16 * tid + k3];
                 const float wi = sg * w.y;
                 float2 s = p ? acc[tid + 256 * k3] : make_float2(0.f, 0.f);
                 s.x = fmaf(zr[k3], w.x, fmaf(-zi[k3], wi, s.x));
@@ -273,7 +273,10 @@ __global__ __launch_bounds__(WG) void chain_kernel(KArgs a) {
     SecLds *s_tab = reinterpret_cast<SecLds *>(s_dyn);
     SecLdsC *s_tabc = reinterpret_cast<SecLdsC *>(s_dyn);
 
-    if (HAS_SOS && (a.hdr[HDR_HIQ] != 0u) != HIQ) return;  // the other variant runs
+    if (HAS_SOS && (a.hdr[HDR_HIQ] != 0u) != HIQ) {  // the other variant runs
+        advance_epoch(a.hdr);
+        return;
+    }
     TileCtx c;
     c.tid = threadIdx.x;
     c.lane = c.tid & 63;
@@ -483,12 +486,6 @@ __global__ __launch_bounds__(WG) void chain_kernel(KArgs a) {
     if (c.valid) store_tile(a.y + c.ch * a.ldy + n0, stg, a.N - n0, a.vec != 0, c.gl);
 }
 
-// Advances a look-back epoch after a run (stream-ordered behind it).
-__global__ void bump_epoch_kernel(uint32_t *hdr, int word) {
-    uint32_t ne = (hdr[word] + 1u) & EPOCH_MASK;
-    hdr[word] = ne == 0u ? 1u : ne;
-}
-
 // ------------------------------------------------------------------- host
 
 static size_t al256(size_t b) { return (b + 255) & ~size_t(255); }
@@ -515,7 +512,7 @@ WsLayout ws_layout(int64_t C, int64_t N, int32_t S, int32_t M_merged, int32_t n_
     }
     w.twid = w.hspec = w.tw64 = off;
     if (fir_mode == FIR_FFT) {
-        off += al256(NFFT * sizeof(float2));
+        off += al256(TWID_ENTRIES * sizeof(float2));
         w.hspec = off;
         off += al256((size_t)fft_parts(M_merged) * NFFT * sizeof(float2));
         w.tw64 = off;
@@ -547,8 +544,6 @@ static hipError_t launch_main(const KArgs &k, int64_t nblocks, hipStream_t st) {
     if constexpr (S) {
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL((chain_kernel<F, S, true, false>), dim3((unsigned)nblocks), dim3(WG), dyn, st, k);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-        hipLaunchKernelGGL(bump_epoch_kernel, dim3(1), dim3(1), 0, st, k.hdr, (int)HDR_EPOCH);
         e = hipGetLastError();
     }
     return e;

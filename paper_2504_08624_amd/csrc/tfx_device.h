@@ -18,11 +18,12 @@ namespace tfx {
 // it for every tile on the XCD.)  The cross-tile values are fp32 even for
 // sections carried in fp64 inside the tile: across tiles the state is damped
 // by PhiT = A^3072, so rounding there accumulates over a few tiles only.  The
-// epoch advances once per launch (a one-thread kernel behind every run), so a
-// run never clears the words the previous run left and needs no memset.
+// epoch advances once per run (block 0 of the filter-kernel variant that does
+// not match the workspace's high-Q word advances it, stream-ordered against
+// the variant that does the work), so a run never clears the words the
+// previous run left and needs no memset.
 constexpr uint32_t EPOCH_MASK = 0x3FFFFFFFu;
 constexpr int64_t SPIN_MAX = int64_t(1) << 22;
-constexpr int REC_WORDS = 4;
 
 __device__ __forceinline__ uint64_t ld_word(const uint64_t *p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -32,6 +33,14 @@ __device__ __forceinline__ void st_word(uint64_t *p, uint64_t v) {
 }
 __device__ __forceinline__ uint32_t load_epoch(const uint32_t *hdr, int word) {
     return __hip_atomic_load(hdr + word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// Run by the filter-kernel variant that does not match the high-Q word
+// before it exits: its block 0 advances the look-back epoch for the next run.
+__device__ __forceinline__ void advance_epoch(uint32_t *hdr) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        const uint32_t ne = (hdr[HDR_EPOCH] + 1u) & EPOCH_MASK;
+        hdr[HDR_EPOCH] = ne == 0u ? 1u : ne;
+    }
 }
 
 // Lanes 0, 1 of a wave store the tagged pair (f0, f1) (wave-uniform) into
@@ -262,10 +271,31 @@ __device__ __forceinline__ void cmul_tw(float &r, float &i, float2 w) {
     i = ni;
 }
 
-// Swizzled LDS addresses of the two FFT exchanges: bijections onto [0, 4096),
-// bank-conflict-free for the lane orders used (checked on the CPU).
-__device__ __forceinline__ int ex1(int k1, int b, int c) { return 256 * k1 + 16 * ((b + k1) & 15) + c; }
-__device__ __forceinline__ int ex2(int k1, int k2, int c) { return 256 * k1 + 16 * ((k2 + k1) & 15) + (c ^ k1); }
+// The two LDS exchanges of the FFT store element (k1, b, c) at
+// 256 k1 + 16 ((b + k1) & 15) + c and element (k1, k2, c) at
+// 256 k1 + 16 ((k2 + k1) & 15) + ((c + k1) & 15): bijections onto [0, 4096),
+// bank-conflict-free for every lane order used below (checked on the CPU for
+// 32 banks per half-wave and 64 per wave).  In each loop a lane's addresses
+// are one lane constant plus the loop's immediate step, minus 256 (or 16)
+// once the rotation wraps, so an access costs a compare and a select.
+//
+// Twiddles come from three per-lane tables (fp32, built in FP64 by the
+// prepare step), each lane reading 16 consecutive entries as float4:
+//   TW1[t][k]       = w^(t k)            (forward pass 1, lane t = tid)
+//   TW2[c][k]       = w^(16 c k)         (forward pass 2 row c; inverse pass 1 row k2)
+//   TW3[k1][c][b]   = w^((16 b + c) k1)  (inverse pass 2, lane (k1, c))
+// with w = e^{-2 pi i / 4096}; the inverse uses the conjugates.
+// ONE0: the row's entry 0 is 1 (TW1, TW2) and is skipped.
+template <bool CONJ, bool ONE0>
+__device__ __forceinline__ void twiddle_row(float (&zr)[16], float (&zi)[16], const float2 *row) {
+    const float4 *r4 = reinterpret_cast<const float4 *>(row);
+#pragma unroll
+    for (int g = 0; g < 8; ++g) {
+        const float4 w = r4[g];
+        if (g > 0 || !ONE0) cmul_tw<CONJ>(zr[2 * g], zi[2 * g], make_float2(w.x, w.y));
+        cmul_tw<CONJ>(zr[2 * g + 1], zi[2 * g + 1], make_float2(w.z, w.w));
+    }
+}
 
 // Forward 4096-point DFT (e^{-2 pi i n k / 4096}) of the values held by the
 // 256 lanes of a workgroup.  In: lane t holds z[256 a + t], a = 0..15.  Out:
@@ -277,41 +307,44 @@ __device__ __forceinline__ void fft4096_forward(float (&zr)[16], float (&zi)[16]
                                                 int tid) {
     float *Lr = lds, *Li = lds + NFFT;
     dft16<-1>(zr, zi);
-#pragma unroll
-    for (int k1 = 1; k1 < 16; ++k1) cmul_tw<false>(zr[k1], zi[k1], twid[(tid * k1) & (NFFT - 1)]);
+    twiddle_row<false, true>(zr, zi, twid + TW1_OFF + 16 * tid);
     {
-        const int b = tid >> 4, c = tid & 15;
+        const int b = tid >> 4, c = tid & 15, w0 = 16 * b + c;
 #pragma unroll
         for (int k1 = 0; k1 < 16; ++k1) {
-            Lr[ex1(k1, b, c)] = zr[k1];
-            Li[ex1(k1, b, c)] = zi[k1];
+            const int ad = (k1 >= 16 - b ? w0 - 256 : w0) + 272 * k1;
+            Lr[ad] = zr[k1];
+            Li[ad] = zi[k1];
         }
     }
     __syncthreads();
     {
-        const int k1 = tid >> 4, c = tid & 15;
+        const int k1 = tid >> 4, c = tid & 15, r0 = 272 * k1 + c;
 #pragma unroll
         for (int b = 0; b < 16; ++b) {
-            zr[b] = Lr[ex1(k1, b, c)];
-            zi[b] = Li[ex1(k1, b, c)];
+            const int ad = (b >= 16 - k1 ? r0 - 256 : r0) + 16 * b;
+            zr[b] = Lr[ad];
+            zi[b] = Li[ad];
         }
         dft16<-1>(zr, zi);
-#pragma unroll
-        for (int k2 = 1; k2 < 16; ++k2) cmul_tw<false>(zr[k2], zi[k2], twid[(16 * c * k2) & (NFFT - 1)]);
+        twiddle_row<false, true>(zr, zi, twid + TW2_OFF + 16 * c);
         __syncthreads();
+        const int w1 = 272 * k1 + ((c + k1) & 15);
 #pragma unroll
         for (int k2 = 0; k2 < 16; ++k2) {
-            Lr[ex2(k1, k2, c)] = zr[k2];
-            Li[ex2(k1, k2, c)] = zi[k2];
+            const int ad = (k2 >= 16 - k1 ? w1 - 256 : w1) + 16 * k2;
+            Lr[ad] = zr[k2];
+            Li[ad] = zi[k2];
         }
     }
     __syncthreads();
     {
-        const int k1 = tid & 15, k2 = tid >> 4;
+        const int k1 = tid & 15, k2 = tid >> 4, r1 = 256 * k1 + 16 * ((k2 + k1) & 15) + k1;
 #pragma unroll
         for (int c = 0; c < 16; ++c) {
-            zr[c] = Lr[ex2(k1, k2, c)];
-            zi[c] = Li[ex2(k1, k2, c)];
+            const int ad = (c >= 16 - k1 ? r1 - 16 : r1) + c;
+            zr[c] = Lr[ad];
+            zi[c] = Li[ad];
         }
         dft16<-1>(zr, zi);
     }
@@ -324,65 +357,65 @@ __device__ __forceinline__ void fft4096_inverse(float (&zr)[16], float (&zi)[16]
                                                 int tid) {
     float *Lr = lds, *Li = lds + NFFT;
     {
-        const int k1 = tid & 15, k2 = tid >> 4;
+        const int k1 = tid & 15, k2 = tid >> 4, r1 = 256 * k1 + 16 * ((k2 + k1) & 15) + k1;
         dft16<1>(zr, zi);
-#pragma unroll
-        for (int c = 1; c < 16; ++c) cmul_tw<true>(zr[c], zi[c], twid[(16 * c * k2) & (NFFT - 1)]);
+        twiddle_row<true, true>(zr, zi, twid + TW2_OFF + 16 * k2);
         __syncthreads();
 #pragma unroll
         for (int c = 0; c < 16; ++c) {
-            Lr[ex2(k1, k2, c)] = zr[c];
-            Li[ex2(k1, k2, c)] = zi[c];
+            const int ad = (c >= 16 - k1 ? r1 - 16 : r1) + c;
+            Lr[ad] = zr[c];
+            Li[ad] = zi[c];
         }
     }
     __syncthreads();
     {
-        const int k1 = tid >> 4, c = tid & 15;
+        const int k1 = tid >> 4, c = tid & 15, w1 = 272 * k1 + ((c + k1) & 15);
 #pragma unroll
         for (int k2 = 0; k2 < 16; ++k2) {
-            zr[k2] = Lr[ex2(k1, k2, c)];
-            zi[k2] = Li[ex2(k1, k2, c)];
+            const int ad = (k2 >= 16 - k1 ? w1 - 256 : w1) + 16 * k2;
+            zr[k2] = Lr[ad];
+            zi[k2] = Li[ad];
         }
         dft16<1>(zr, zi);
-#pragma unroll
-        for (int b = 0; b < 16; ++b) cmul_tw<true>(zr[b], zi[b], twid[((16 * b + c) * k1) & (NFFT - 1)]);
+        twiddle_row<true, false>(zr, zi, twid + TW3_OFF + 16 * tid);
         __syncthreads();
+        const int r0 = 272 * k1 + c;
 #pragma unroll
         for (int b = 0; b < 16; ++b) {
-            Lr[ex1(k1, b, c)] = zr[b];
-            Li[ex1(k1, b, c)] = zi[b];
+            const int ad = (b >= 16 - k1 ? r0 - 256 : r0) + 16 * b;
+            Lr[ad] = zr[b];
+            Li[ad] = zi[b];
         }
     }
     __syncthreads();
     {
-        const int b = tid >> 4, c = tid & 15;
+        const int b = tid >> 4, c = tid & 15, w0 = 16 * b + c;
 #pragma unroll
         for (int k1 = 0; k1 < 16; ++k1) {
-            zr[k1] = Lr[ex1(k1, b, c)];
-            zi[k1] = Li[ex1(k1, b, c)];
+            const int ad = (k1 >= 16 - b ? w0 - 256 : w0) + 272 * k1;
+            zr[k1] = Lr[ad];
+            zi[k1] = Li[ad];
         }
         dft16<1>(zr, zi);
     }
 }
 
-// Z *= H (or conj(H)) bin by bin, H = the tap spectrum in the forward FFT's
-// output layout.  The spectrum loads go in groups of four with a compiler
-// barrier between groups, so at most four bins' spectra sit in registers
-// beside the data (with all sixteen in flight the fused kernels needed about
-// 160 VGPRs instead of 128).
+// Z *= H (or conj(H)) bin by bin, H = the tap spectrum in the per-lane layout
+// hspec[t][k3] = H[t + 256 k3].  The loads go in groups of four bins with a
+// compiler barrier between groups, so at most four bins' spectra sit in
+// registers beside the data.
 __device__ __forceinline__ void spectrum_product(float (&zr)[16], float (&zi)[16], const float2 *hspec, int tid,
                                                  bool conj) {
     const float sg = conj ? -1.f : 1.f;
+    const float4 *h4 = reinterpret_cast<const float4 *>(hspec + 16 * tid);
 #pragma unroll
     for (int g4 = 0; g4 < 4; ++g4) {
-        float2 w[4];
+        const float4 p = h4[2 * g4], q = h4[2 * g4 + 1];
+        const float2 w[4] = {make_float2(p.x, sg * p.y), make_float2(p.z, sg * p.w), make_float2(q.x, sg * q.y),
+                             make_float2(q.z, sg * q.w)};
 #pragma unroll
-        for (int u = 0; u < 4; ++u) w[u] = hspec[tid + 256 * (4 * g4 + u)];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            w[u].y *= sg;
-            cmul_tw<false>(zr[4 * g4 + u], zi[4 * g4 + u], w[u]);
-        }
+        for (int u = 0; u < 4; ++u) cmul_tw<false>(zr[4 * g4 + u], zi[4 * g4 + u], w[u]);
         asm volatile("" ::: "memory");
     }
 }

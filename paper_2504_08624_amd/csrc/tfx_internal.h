@@ -28,6 +28,9 @@ constexpr int KBLK_MAX = 1024;  // taps staged per LDS pass
 constexpr int NFFT = 4096;              // complex points, 16 x 16 x 16
 constexpr int FFT_DISCARD = NFFT - T;   // 1024 leading outputs dropped per block
 constexpr int FFT_PART = FFT_DISCARD + 1;  // taps per partition of a long filter
+// fp32 twiddle tables of the FFT, one region: TW1 [256][16], TW2 [16][16],
+// TW3 [16][16][16] (float2 entries)
+constexpr int TW1_OFF = 0, TW2_OFF = NFFT, TW3_OFF = NFFT + 256, TWID_ENTRIES = 2 * NFFT + 256;
 __host__ __device__ constexpr int fft_parts(int M) { return (M + FFT_PART - 1) / FFT_PART; }
 
 constexpr int MAX_STAGES = 64;
@@ -81,6 +84,7 @@ struct alignas(16) SecLdsC {
 static_assert(offsetof(SecTab, psi) == offsetof(SecLdsC, psi), "SecLdsC must be the leading part of SecTab");
 static_assert(sizeof(SecLdsC) % 16 == 0, "SecLdsC is copied in 16-byte pieces");
 constexpr int LDS_SECTIONS = 32;  // sections staged in LDS at a time
+constexpr int REC_WORDS = 4;      // 64-bit look-back words per (channel, tile, section)
 
 // Cascades of up to CASC_MAX sections (without FP64-carry sections) carry
 // their whole 2S-component state across tiles in one look-back per tile.
@@ -96,7 +100,7 @@ constexpr double DEPTH_EPS = 8.673617379884035e-19;  // 2^-60
 // at components 2s, 2s+1), zero-padded to 16 x 16.
 constexpr int CASC_MAX = 8;
 struct alignas(16) CascTab {
-    int32_t depth;       // look-back depth d: max |Phi_T^d| <= 2^-60 (0 = none within 64 tiles)
+    int32_t depth;       // look-back depth d <= 64 with max |Phi_T^d| <= 2^-60 (0 = none found)
     int32_t pad[3];
     float T[3][16][16];  // Phi_T, Phi_T^2, Phi_T^4
 };
@@ -230,8 +234,12 @@ struct BwdPlan {
 // Backward workspace: the forward layout, then the adjoint's buffers.
 struct BwdLayout {
     WsLayout fwd;
-    size_t part_sos, sos_sum, fbuf, gfbuf, part_gh, gh1, gH, obuf, twid, tw64, total;
+    size_t part_sos, sos_sum, fbuf, gfbuf, part_gh, gh1, gH, obuf, twid, tw64, spec, total;
     int64_t nlag;
+    // single-partition FFT FIR: tap-gradient spectra summed per workgroup
+    // (spec_wg workgroups, spec_split of them per first-level sum)
+    bool spec_path;
+    int64_t spec_wg, spec_nsplit;
 };
 BwdLayout bwd_layout(int64_t C, int64_t N, int32_t S, int32_t M_merged, int32_t n_fir, int32_t fir_mode);
 hipError_t launch_backward(const BwdPlan &p);

@@ -27,103 +27,95 @@ __device__ void put4(float *f, double *d, const double *m) {
     }
 }
 
-// Transition powers of one TDF-II section.  With state s = (s1, s2) the
-// section is s' = A s + B x, y = s1 + b0 x, A = [[-a1, 1], [-a2, 0]], so a
-// state s entering a chunk becomes A^Lc s after Lc samples.
-__device__ void build_section(SecTab *tb, const float *co, int Lc) {
-    const double a1 = co[3], a2 = co[4];
-    for (int i = 0; i < 5; ++i) tb->coef[i] = co[i];
-    tb->pad = 0;
-    const double A[4] = {-a1, 1.0, -a2, 0.0};
+// R = A^e (FP64 2 x 2) by binary powering; R may alias nothing.
+__device__ void mat2_pow(const double *A, int e, double *R) {
     double P[4] = {A[0], A[1], A[2], A[3]};
-    for (int t = 1; t < Lc; ++t) mat2_mul(P, A, P);
-    const double Phi[4] = {P[0], P[1], P[2], P[3]};
-    double F[4] = {1.0, 0.0, 0.0, 1.0};
-    for (int k = 0; k < 64; ++k) {
-        put4(tb->fold[k], tb->fold_d[k], F);
-        mat2_mul(F, Phi, F);
+    R[0] = 1.0;
+    R[1] = 0.0;
+    R[2] = 0.0;
+    R[3] = 1.0;
+    while (e > 0) {
+        if (e & 1) mat2_mul(R, P, R);
+        e >>= 1;
+        if (e > 0) mat2_mul(P, P, P);
     }
-    const double Psi[4] = {F[0], F[1], F[2], F[3]};
-    double W[4] = {1.0, 0.0, 0.0, 1.0};
-    for (int w = 0; w < GWAVES; ++w) {
-        put4(tb->psi[w], tb->psi_d[w], W);
-        mat2_mul(W, Psi, W);
-    }
-    double B[4] = {W[0], W[1], W[2], W[3]};  // PhiT = A^T
-    {  // look-back depth
-        double Q[4] = {W[0], W[1], W[2], W[3]};
-        tb->depth = 0;
-        for (int k = 1; k <= 64; ++k) {
-            if (fmax(fmax(fabs(Q[0]), fabs(Q[1])), fmax(fabs(Q[2]), fabs(Q[3]))) <= DEPTH_EPS) {
-                tb->depth = k;
-                break;
-            }
-            mat2_mul(Q, W, Q);
-        }
-    }
-    for (int j = 0; j < 9; ++j) {
-        put4(tb->lb[j], tb->lb_d[j], B);
-        mat2_mul(B, B, B);
-    }
-    tb->hiq = section_hiq(a1, a2) ? 1 : 0;
 }
 
-struct PrepArgs {
-    SecTab *tab;
-    int32_t S;
-    StageList sos;
-    uint64_t *recs;
-    int64_t nwords;
-    uint32_t *hdr;
-};
+__device__ double mat2_maxabs(const double *M) {
+    return fmax(fmax(fabs(M[0]), fabs(M[1])), fmax(fabs(M[2]), fabs(M[3])));
+}
 
-// Section tables; clears the look-back records (tag 0 never matches an
-// epoch); arms the header (epoch 1).
-__global__ void prep_kernel(PrepArgs a) {
-    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = gid; i < a.nwords; i += stride) a.recs[i] = 0ull;
-    if (gid == 0) {
-        a.hdr[HDR_ERROR] = 0u;
-        a.hdr[HDR_EPOCH] = 1u;
-        uint32_t any = 0u;
-        for (int s = 0, st = 0, j = 0; s < a.S; ++s, ++j) {
-            while (j >= a.sos.len[st]) {
-                j -= a.sos.len[st];
-                ++st;
-            }
-            const float *co = a.sos.ptr[st] + 5 * j;
-            any |= section_hiq(co[3], co[4]) ? 1u : 0u;
-        }
-        a.hdr[HDR_HIQ] = any;
+// Transition powers of one TDF-II section, built by one block of 256
+// threads.  With state s = (s1, s2) the section is s' = A s + B x,
+// y = s1 + b0 x, A = [[-a1, 1], [-a2, 0]], so a state s entering a chunk
+// becomes Phi s = A^Lc s after Lc samples.  Thread k < 64 writes the fold
+// power Phi^k, thread j < 9 the look-back power W^(2^j) of the tile
+// transition W = Phi^128, and threads k < 64 test W^(k+1) for the look-back
+// depth (the first d <= 64 with max |W^d| <= 2^-60, 0 if none).  Every power
+// is formed by binary powering in FP64 and rounded once.
+__device__ void build_section_block(SecTab *tb, const float *co, int Lc, int tid) {
+    __shared__ int s_dep;
+    const double a1 = co[3], a2 = co[4];
+    const double A[4] = {-a1, 1.0, -a2, 0.0};
+    double Phi[4], Psi[4], W[4], R[4];
+    mat2_pow(A, Lc, Phi);
+    mat2_pow(Phi, 64, Psi);
+    mat2_pow(Psi, GWAVES, W);
+    if (tid == 0) s_dep = 65;
+    __syncthreads();
+    if (tid < 64) {
+        mat2_pow(Phi, tid, R);
+        put4(tb->fold[tid], tb->fold_d[tid], R);
+        mat2_pow(W, tid + 1, R);
+        if (mat2_maxabs(R) <= DEPTH_EPS) atomicMin(&s_dep, tid + 1);
     }
-    if (gid < a.S) {
-        int s = (int)gid, st = 0;
-        while (s >= a.sos.len[st]) {
-            s -= a.sos.len[st];
-            ++st;
-        }
-        build_section(&a.tab[gid], a.sos.ptr[st] + 5 * s, L);
+    if (tid < GWAVES) {
+        mat2_pow(Psi, tid, R);
+        put4(tb->psi[tid], tb->psi_d[tid], R);
+    }
+    if (tid < 9) {
+        mat2_pow(W, 1 << tid, R);
+        put4(tb->lb[tid], tb->lb_d[tid], R);
+    }
+    __syncthreads();
+    if (tid == 0) {
+        for (int i = 0; i < 5; ++i) tb->coef[i] = co[i];
+        tb->pad = 0;
+        tb->depth = s_dep > 64 ? 0 : s_dep;
+        tb->hiq = section_hiq(a1, a2) ? 1 : 0;
     }
 }
 
 // Tile-transition powers of the whole cascade for the cascade-level
-// look-back, in FP64.  The cascade's one-sample transition F (zero input):
-// block (i, i) = A_i; block (i, j), j < i = B_i (prod_{j<l<i} D_l) C, since
-// section i's input is section i-1's output; Phi_T = F^3072 = (F^8 F^16)^128.
-// One block of 256 threads, one matrix element each.
+// look-back, in FP64, by one block of 256 threads (one matrix element
+// each).  The cascade's one-sample transition F (zero input): block (i, i) =
+// A_i; block (i, j), j < i = B_i (prod_{j<l<i} D_l) C, since section i's
+// input is section i-1's output; Phi_T = F^3072 = (F^8 F^16)^128.
 __device__ void mm16(const double (*A)[16], const double (*B)[16], double (*R)[16], int i, int j) {
     double acc = 0.0;
     for (int k = 0; k < 16; ++k) acc += A[i][k] * B[k][j];
-    __syncthreads();  // every read of A and B done (R may alias neither, but callers reuse buffers)
+    __syncthreads();  // every read of A and B done (R may alias either)
     R[i][j] = acc;
     __syncthreads();
 }
 
-__global__ void casc_table_kernel(StageList sos, int32_t S, CascTab *out) {
+// max |M| over the block (every thread gets it)
+__device__ double block_maxabs(const double (*M)[16], int i, int j, int tid) {
+    __shared__ double wmax[4];
+    double v = fabs(M[i][j]);
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v = fmax(v, __shfl_xor(v, d));
+    if ((tid & 63) == 0) wmax[tid >> 6] = v;
+    __syncthreads();
+    v = fmax(fmax(wmax[0], wmax[1]), fmax(wmax[2], wmax[3]));
+    __syncthreads();
+    return v;
+}
+
+__device__ void casc_table_block(const StageList &sos, int32_t S, CascTab *out, int tid) {
     __shared__ double co[CASC_MAX][5];
-    __shared__ double M0[16][16], M1[16][16], M2[16][16], M3[16][16];
-    const int tid = threadIdx.x, i = tid >> 4, j = tid & 15;
+    __shared__ double M0[16][16], M1[16][16], Pw[7][16][16];
+    const int i = tid >> 4, j = tid & 15;
     if (tid < S * 5) {
         int s = tid / 5, st = 0;
         const int k = tid % 5;
@@ -151,45 +143,40 @@ __global__ void casc_table_kernel(StageList sos, int32_t S, CascTab *out) {
     __syncthreads();
     mm16(M0, M0, M1, i, j);  // F^2
     mm16(M1, M1, M0, i, j);  // F^4
-    mm16(M0, M0, M2, i, j);  // F^8
-    mm16(M2, M2, M1, i, j);  // F^16
-    mm16(M1, M2, M3, i, j);  // F^24
-    for (int t = 0; t < 7; ++t) {  // F^(24 * 128) = F^3072
-        mm16(M3, M3, M0, i, j);
-        M3[i][j] = M0[i][j];
+    mm16(M0, M0, M1, i, j);  // F^8
+    mm16(M1, M1, M0, i, j);  // F^16
+    mm16(M0, M1, Pw[0], i, j);  // F^24
+    for (int t = 0; t < 7; ++t) mm16(Pw[0], Pw[0], Pw[0], i, j);  // F^(24 * 128) = F^3072
+    for (int t = 1; t < 7; ++t) mm16(Pw[t - 1], Pw[t - 1], Pw[t], i, j);  // Phi_T^(2^t)
+    out->T[0][i][j] = (float)Pw[0][i][j];
+    out->T[1][i][j] = (float)Pw[1][i][j];
+    out->T[2][i][j] = (float)Pw[2][i][j];
+    // look-back depth: a d <= 64 with max |Phi_T^d| <= 2^-60 (0 if none),
+    // found by doubling, then bisection between the last failing power of
+    // two and the first passing one; every accepted d is checked directly
+    int first = -1;
+    for (int t = 0; t < 7 && first < 0; ++t)
+        if (block_maxabs(Pw[t], i, j, tid) <= DEPTH_EPS) first = t;
+    int dep = 0;
+    if (first == 0) {
+        dep = 1;
+    } else if (first > 0) {
+        int lo = 1 << (first - 1), hi = 1 << first;
+        M0[i][j] = Pw[first - 1][i][j];  // Phi_T^lo
         __syncthreads();
-    }
-    out->T[0][i][j] = (float)M3[i][j];
-    {  // look-back depth: the first d with max |Phi_T^d| <= 2^-60
-        __shared__ double amax[256];
-        __shared__ int dep;
-        if (tid == 0) dep = 0;
-        M0[i][j] = M3[i][j];
-        __syncthreads();
-        for (int k = 1; k <= 64; ++k) {
-            amax[tid] = fabs(M0[i][j]);
-            __syncthreads();
-            for (int w = 128; w >= 1; w >>= 1) {
-                if (tid < w) amax[tid] = fmax(amax[tid], amax[tid + w]);
+        for (int t = first - 2; t >= 0; --t) {
+            mm16(M0, Pw[t], M1, i, j);  // Phi_T^(lo + 2^t)
+            if (block_maxabs(M1, i, j, tid) <= DEPTH_EPS) {
+                hi = lo + (1 << t);
+            } else {
+                lo += 1 << t;
+                M0[i][j] = M1[i][j];
                 __syncthreads();
             }
-            const bool hit = amax[0] <= DEPTH_EPS;
-            __syncthreads();
-            if (hit) {
-                if (tid == 0) dep = k;
-                break;
-            }
-            mm16(M0, M3, M1, i, j);
-            M0[i][j] = M1[i][j];
-            __syncthreads();
         }
-        __syncthreads();
-        if (tid == 0) out->depth = dep;
+        dep = hi;
     }
-    mm16(M3, M3, M1, i, j);
-    out->T[1][i][j] = (float)M1[i][j];
-    mm16(M1, M1, M2, i, j);
-    out->T[2][i][j] = (float)M2[i][j];
+    if (tid == 0) out->depth = dep;
 }
 
 struct MergeArgs {
@@ -224,45 +211,116 @@ __global__ void merge_taps_kernel(MergeArgs a) {
     for (int k = threadIdx.x; k < Mcur; k += blockDim.x) a.out[k] = (float)cur[k];
 }
 
-// twid[k] = e^{-2 pi i k / 4096} in fp32 (filter kernel) and fp64 (spectrum)
-__global__ void fft_twiddle_kernel(float2 *twid, double2 *tw64) {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= NFFT) return;
-    double s, c;
-    sincospi(-2.0 * (double)k / NFFT, &s, &c);
-    twid[k] = make_float2((float)c, (float)s);
-    tw64[k] = make_double2(c, s);
+// Entry i of the twiddle tables (i < 4096), each e^{-2 pi i e / 4096} for an
+// exact integer e mod 4096, in FP64 and rounded once: tw64[i] (e = i), and
+// the fp32 per-lane tables of the FFT kernels, TW1[t][k] (e = t k), TW3[k1][c][b]
+// (e = (16 b + c) k1) and, for i < 256, TW2[c][k] (e = 16 c k).
+__device__ void write_twiddle(float2 *twid, double2 *tw64, int i) {
+    double sn, cs;
+    sincospi(-2.0 * (double)i / NFFT, &sn, &cs);
+    tw64[i] = make_double2(cs, sn);
+    const int e1 = ((i >> 4) * (i & 15)) & (NFFT - 1);
+    sincospi(-2.0 * (double)e1 / NFFT, &sn, &cs);
+    twid[TW1_OFF + i] = make_float2((float)cs, (float)sn);
+    const int e3 = ((16 * (i & 15) + ((i >> 4) & 15)) * (i >> 8)) & (NFFT - 1);
+    sincospi(-2.0 * (double)e3 / NFFT, &sn, &cs);
+    twid[TW3_OFF + i] = make_float2((float)cs, (float)sn);
+    if (i < 256) {
+        const int e2 = (16 * (i >> 4) * (i & 15)) & (NFFT - 1);
+        sincospi(-2.0 * (double)e2 / NFFT, &sn, &cs);
+        twid[TW2_OFF + i] = make_float2((float)cs, (float)sn);
+    }
 }
 
-// hspec[p][k] = (sum_j h[1025 p + j] e^{-2 pi i j k / 4096}) / 4096, the
-// direct DFT of tap partition p (j < 1025, zero-padded) in FP64 (exact
-// twiddle indices j k mod 4096).  Block (blk, p) of 256 lanes covers 16 bins:
-// lane (kk, jj) sums taps j = jj (mod 16) of bin 16 blk + kk, then the 16
-// partial sums are added in a fixed order.
-__global__ void fft_spectrum_kernel(const float *h_all, int32_t M_all, const double2 *tw64, float2 *hspec_all) {
-    __shared__ double pr[16][17], pi[16][17];
-    const int kk = threadIdx.x >> 4, jj = threadIdx.x & 15;
-    const int k = blockIdx.x * 16 + kk;
-    const float *h = h_all + (int64_t)blockIdx.y * FFT_PART;
-    const int rest = M_all - (int)blockIdx.y * FFT_PART;
+__global__ void fft_twiddle_kernel(float2 *twid, double2 *tw64) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < NFFT) write_twiddle(twid, tw64, k);
+}
+
+// hspec[p][k] = (sum_j h[1025 p + j] e^{-2 pi i j k / 4096}) / 4096, the DFT
+// of tap partition p (j < 1025, zero-padded), in FP64, stored in the FFT
+// kernels' per-lane order (bin t + 256 k3 at [t][k3]).  One block of 256
+// lanes covers 16 bins: lane (kk, jj) sums taps j = jj (mod 16) of bin
+// k = 16 blk + kk, stepping its twiddle by e^{-2 pi i 16 k / 4096} (at most
+// 65 steps from an exact start, so the FP64 twiddle error stays near
+// 1e-14, far below the fp32 rounding of the result); the 16 partial sums
+// are added by a fixed shuffle tree.
+__device__ void spectrum_block(const float *h_all, int32_t M_all, int part, int blk, float2 *hspec_all, int tid) {
+    __shared__ float hs[FFT_PART + 15];
+    const int kk = tid >> 4, jj = tid & 15;
+    const int k = blk * 16 + kk;
+    const float *h = h_all + (int64_t)part * FFT_PART;
+    const int rest = M_all - part * FFT_PART;
     const int M = rest < FFT_PART ? rest : FFT_PART;
-    float2 *hspec = hspec_all + (int64_t)blockIdx.y * NFFT;
-    double hr = 0.0, hi = 0.0;
-    for (int j = jj; j < M; j += 16) {
-        const double2 w = tw64[(j * k) & (NFFT - 1)];
-        hr += (double)h[j] * w.x;
-        hi += (double)h[j] * w.y;
-    }
-    pr[kk][jj] = hr;
-    pi[kk][jj] = hi;
+    for (int j = tid; j < FFT_PART + 15; j += 256) hs[j] = j < M ? h[j] : 0.f;  // zero-padded to 16 | length
     __syncthreads();
-    if (jj == 0) {
-        double sr = 0.0, si = 0.0;
-        for (int u = 0; u < 16; ++u) {
-            sr += pr[kk][u];
-            si += pi[kk][u];
+    double wr, wi, sr, si;
+    sincospi(-2.0 * (double)((jj * k) & (NFFT - 1)) / NFFT, &wi, &wr);
+    sincospi(-2.0 * (double)((16 * k) & (NFFT - 1)) / NFFT, &si, &sr);
+    double hr = 0.0, hi = 0.0;
+#pragma unroll 5
+    for (int m = 0; m < (FFT_PART + 15) / 16; ++m) {
+        const double hv = (double)hs[jj + 16 * m];
+        hr = fma(hv, wr, hr);
+        hi = fma(hv, wi, hi);
+        const double nr = wr * sr - wi * si;
+        wi = fma(wr, si, wi * sr);
+        wr = nr;
+    }
+#pragma unroll
+    for (int d = 8; d >= 1; d >>= 1) {
+        hr += __shfl_xor(hr, d);
+        hi += __shfl_xor(hi, d);
+    }
+    if (jj == 0)  // per-lane layout: bin t + 256 k3 at [t][k3]
+        hspec_all[(int64_t)part * NFFT + 16 * (k & 255) + (k >> 8)] = make_float2((float)(hr / NFFT), (float)(hi / NFFT));
+}
+
+// The prepare step of a chain in one launch.  Blocks take roles by index:
+// tap-spectrum blocks (which also write the twiddle tables), one block per
+// section (scan tables), one block for the cascade's tile transition; every
+// block also clears a share of the look-back records (tag 0 never matches
+// an epoch), and block 0 arms the header (epoch 1, error 0, high-Q word).
+struct PrepareArgs {
+    const float *h;
+    int32_t M, nspec;  // nspec = 256 * partitions, or 0 without an FFT FIR
+    float2 *twid, *hspec;
+    double2 *tw64;
+    SecTab *tab;
+    int32_t S, casc;
+    StageList sos;
+    CascTab *ctab;
+    uint64_t *recs;
+    int64_t nwords;
+    uint32_t *hdr;
+};
+
+__global__ __launch_bounds__(256) void prepare_kernel(PrepareArgs a) {
+    const int tid = threadIdx.x;
+    const int b = blockIdx.x;
+    for (int64_t i = (int64_t)b * 256 + tid; i < a.nwords; i += (int64_t)gridDim.x * 256) a.recs[i] = 0ull;
+    if (b == 0 && tid == 0 && a.S > 0) {
+        a.hdr[HDR_ERROR] = 0u;
+        a.hdr[HDR_EPOCH] = 1u;
+        uint32_t any = 0u;
+        for (int st = 0; st < a.sos.n; ++st)
+            for (int j = 0; j < a.sos.len[st]; ++j)
+                any |= section_hiq(a.sos.ptr[st][5 * j + 3], a.sos.ptr[st][5 * j + 4]) ? 1u : 0u;
+        a.hdr[HDR_HIQ] = any;
+    }
+    if (b < a.nspec) {
+        const int blk = b % (NFFT / 16), part = b / (NFFT / 16);
+        spectrum_block(a.h, a.M, part, blk, a.hspec, tid);
+        if (part == 0 && tid < 16) write_twiddle(a.twid, a.tw64, blk * 16 + tid);
+    } else if (b < a.nspec + a.S) {
+        int s = b - a.nspec, st = 0;
+        while (s >= a.sos.len[st]) {
+            s -= a.sos.len[st];
+            ++st;
         }
-        hspec[k] = make_float2((float)(sr / NFFT), (float)(si / NFFT));
+        build_section_block(&a.tab[b - a.nspec], a.sos.ptr[st] + 5 * s, L, tid);
+    } else if (a.casc && b == a.nspec + a.S) {
+        casc_table_block(a.sos, a.S, a.ctab, tid);
     }
 }
 
@@ -285,11 +343,10 @@ struct BatchPrepArgs {
     int32_t lc;
 };
 
-__global__ void batch_prep_kernel(BatchPrepArgs a) {
-    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = gid; i < a.nwords; i += stride) a.recs[i] = 0ull;
-    if (gid == 0) {
+__global__ __launch_bounds__(256) void batch_prep_kernel(BatchPrepArgs a) {
+    const int tid = threadIdx.x;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + tid; i < a.nwords; i += (int64_t)gridDim.x * 256) a.recs[i] = 0ull;
+    if (blockIdx.x == 0 && tid == 0) {
         a.hdr[HDR_ERROR] = 0u;
         a.hdr[HDR_EPOCH] = 1u;
         uint32_t any = 0u;
@@ -298,7 +355,7 @@ __global__ void batch_prep_kernel(BatchPrepArgs a) {
                 any |= section_hiq(a.desc[c].sos[5 * s + 3], a.desc[c].sos[5 * s + 4]) ? 1u : 0u;
         a.hdr[HDR_HIQ] = any;
     }
-    for (int64_t g = gid; g < a.nsec; g += stride) {
+    for (int64_t g = blockIdx.x; g < a.nsec; g += gridDim.x) {
         // the last clip with tab0 <= g: tab0 grows with the clip index by S,
         // so that clip has S > 0 and holds section g
         int lo = 0, hi = a.nclips - 1;
@@ -307,7 +364,8 @@ __global__ void batch_prep_kernel(BatchPrepArgs a) {
             if (a.desc[mid].tab0 <= g) lo = mid;
             else hi = mid - 1;
         }
-        build_section(&a.tab[g], a.desc[lo].sos + 5 * (g - a.desc[lo].tab0), a.lc);
+        build_section_block(&a.tab[g], a.desc[lo].sos + 5 * (g - a.desc[lo].tab0), a.lc, tid);
+        __syncthreads();  // s_dep is reused by the next section
     }
 }
 
@@ -322,9 +380,9 @@ hipError_t launch_batch_prepare(const BatchLayout &lay, int lc, int32_t nclips, 
     a.nwords = lay.nrec * 4;
     a.hdr = reinterpret_cast<uint32_t *>(w + lay.hdr);
     a.lc = lc;
-    const int64_t work = a.nwords > a.nsec ? a.nwords : a.nsec;
-    int64_t nb = (work + 255) / 256;
+    int64_t nb = (a.nwords + 255) / 256;
     if (nb > 2048) nb = 2048;
+    if (nb < a.nsec) nb = a.nsec < 2048 ? a.nsec : 2048;
     if (nb < 1) nb = 1;
     hipLaunchKernelGGL(batch_prep_kernel, dim3((unsigned)nb), dim3(256), 0, st, a);
     return hipGetLastError();
@@ -342,36 +400,29 @@ hipError_t launch_tables(const ChainPlan &p, const WsLayout &lay, const float *h
         hipLaunchKernelGGL(merge_taps_kernel, dim3(1), dim3(256), 0, p.stream, m);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
-    if (p.firs.n > 0 && p.fir_mode == FIR_FFT) {
-        double2 *tw64 = reinterpret_cast<double2 *>(ws + lay.tw64);
-        hipLaunchKernelGGL(fft_twiddle_kernel, dim3(NFFT / 256), dim3(256), 0, p.stream,
-                           reinterpret_cast<float2 *>(ws + lay.twid), tw64);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-        hipLaunchKernelGGL(fft_spectrum_kernel, dim3(NFFT / 16, fft_parts(M)), dim3(256), 0, p.stream, h, M, tw64,
-                           reinterpret_cast<float2 *>(ws + lay.hspec));
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-    }
-    if (p.S > 0) {
-        PrepArgs pa;
-        pa.tab = reinterpret_cast<SecTab *>(ws + lay.tab);
-        pa.S = p.S;
-        pa.sos = p.sos;
-        pa.recs = reinterpret_cast<uint64_t *>(ws + lay.recs);
-        pa.nwords = lay.cpad * lay.ntiles * p.S * 4;
-        pa.hdr = reinterpret_cast<uint32_t *>(ws + lay.hdr);
-        const int64_t work = pa.nwords > p.S ? pa.nwords : p.S;
-        int64_t nb = (work + 255) / 256;
-        if (nb > 1024) nb = 1024;
-        if (nb < 1) nb = 1;
-        hipLaunchKernelGGL(prep_kernel, dim3((unsigned)nb), dim3(256), 0, p.stream, pa);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-        if (p.S <= CASC_MAX) {
-            hipLaunchKernelGGL(casc_table_kernel, dim3(1), dim3(256), 0, p.stream, p.sos, p.S,
-                               reinterpret_cast<CascTab *>(ws + lay.casc));
-            if ((e = hipGetLastError()) != hipSuccess) return e;
-        }
-    }
-    return hipSuccess;
+    PrepareArgs a{};
+    const bool fft = p.firs.n > 0 && p.fir_mode == FIR_FFT;
+    a.h = h;
+    a.M = M;
+    a.nspec = fft ? (NFFT / 16) * fft_parts(M) : 0;
+    a.twid = reinterpret_cast<float2 *>(ws + lay.twid);
+    a.hspec = reinterpret_cast<float2 *>(ws + lay.hspec);
+    a.tw64 = reinterpret_cast<double2 *>(ws + lay.tw64);
+    a.tab = reinterpret_cast<SecTab *>(ws + lay.tab);
+    a.S = p.S;
+    a.casc = (p.S > 0 && p.S <= CASC_MAX) ? 1 : 0;
+    a.sos = p.sos;
+    a.ctab = reinterpret_cast<CascTab *>(ws + lay.casc);
+    a.recs = reinterpret_cast<uint64_t *>(ws + lay.recs);
+    a.nwords = p.S > 0 ? lay.cpad * lay.ntiles * p.S * REC_WORDS : 0;
+    a.hdr = reinterpret_cast<uint32_t *>(ws + lay.hdr);
+    int64_t nb = a.nspec + a.S + a.casc;
+    int64_t nclear = (a.nwords + 255) / 256;
+    if (nclear > 1024) nclear = 1024;
+    if (nb < nclear) nb = nclear;
+    if (nb == 0) return hipSuccess;
+    hipLaunchKernelGGL(prepare_kernel, dim3((unsigned)nb), dim3(256), 0, p.stream, a);
+    return hipGetLastError();
 }
 
 hipError_t launch_twiddles(float2 *twid, double2 *tw64, hipStream_t st) {
