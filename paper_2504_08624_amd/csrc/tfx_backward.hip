@@ -470,15 +470,7 @@ __global__ __launch_bounds__(WG) void fir_bwd_kernel(FirBwdArgs a) {
         }
         spectrum_product(zr, zi, a.hspec, tid, true);
         fft4096_inverse(zr, zi, lds, a.twid, tid);
-        float *oA = a.gx + chA * a.ldgx, *oB = hasB ? a.gx + chB * a.ldgx : nullptr;
-#pragma unroll
-        for (int q = 0; q < 12; ++q) {
-            const int64_t n = n0 + 256 * q + tid;
-            if (n < a.N) {
-                oA[n] = zr[q];
-                if (hasB) oB[n] = zi[q];
-            }
-        }
+        store_pair_tile<0>(zr, zi, a.gx + chA * a.ldgx, hasB ? a.gx + chB * a.ldgx : nullptr, n0, a.N, tid);
     }
     if (a.want_gh) {
         float2 *o = a.spart + (int64_t)blockIdx.x * NFFT;
@@ -517,24 +509,34 @@ __global__ void fir_spec_reduce2_kernel(const double2 *sum1, int32_t nsplit, dou
     spec[f] = make_double2(sr, si);
 }
 
-// dL/dh[k] = Re(sum_f P[f] e^{+2 pi i f k / 4096}) / 4096 for lag k = block
-// index: thread t takes bins f = t + 256 j, then a fixed-order block sum.
-__global__ void fir_gh_dft_kernel(const double2 *spec, const double2 *tw64, float *gh) {
-    __shared__ double wsum[WG / 64];
-    const int k = blockIdx.x, t = threadIdx.x;
-    double acc = 0.0;
+// dL/dh[k] = Re(sum_f P[f] e^{+2 pi i f k / 4096}) / 4096 for the lags
+// k = 4 blockIdx.x + u, u < 4: thread t takes bins f = t + 256 j for all four
+// lags, then a fixed-order block sum per lag.
+constexpr int GH_DFT_LAGS = 4;
+__global__ void fir_gh_dft_kernel(const double2 *spec, const double2 *tw64, int32_t M, float *gh) {
+    __shared__ double wsum[GH_DFT_LAGS][WG / 64];
+    const int k0 = blockIdx.x * GH_DFT_LAGS, t = threadIdx.x;
+    double acc[GH_DFT_LAGS] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll 4
     for (int j = 0; j < 16; ++j) {
         const int f = t + 256 * j;
         const double2 p = spec[f];
-        const double2 w = tw64[(f * k) & (NFFT - 1)];  // e^{-i theta}: Re(p e^{+i theta}) = p.x w.x + p.y w.y
-        acc = fma(p.x, w.x, fma(p.y, w.y, acc));
+#pragma unroll
+        for (int u = 0; u < GH_DFT_LAGS; ++u) {
+            // e^{-i theta}: Re(p e^{+i theta}) = p.x w.x + p.y w.y
+            const double2 w = tw64[(f * (k0 + u)) & (NFFT - 1)];
+            acc[u] = fma(p.x, w.x, fma(p.y, w.y, acc[u]));
+        }
     }
 #pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) acc += __shfl_xor(acc, d);
-    if ((t & 63) == 0) wsum[t >> 6] = acc;
+    for (int u = 0; u < GH_DFT_LAGS; ++u) {
+#pragma unroll
+        for (int d = 32; d >= 1; d >>= 1) acc[u] += __shfl_xor(acc[u], d);
+        if ((t & 63) == 0) wsum[u][t >> 6] = acc[u];
+    }
     __syncthreads();
-    if (t == 0) gh[k] = (float)(((wsum[0] + wsum[1]) + (wsum[2] + wsum[3])) / NFFT);
+    if (t < GH_DFT_LAGS && k0 + t < M)
+        gh[k0 + t] = (float)(((wsum[t][0] + wsum[t][1]) + (wsum[t][2] + wsum[t][3])) / NFFT);
 }
 
 // Two-level FP64 reduction of the tap-gradient partials, in a fixed order:
@@ -769,8 +771,9 @@ hipError_t launch_backward(const BwdPlan &bp) {
         hipLaunchKernelGGL(fir_spec_reduce2_kernel, dim3(NFFT / 256), dim3(256), 0, st,
                            static_cast<const double2 *>(sum1), (int32_t)lay.spec_nsplit, spec);
         if ((e = hipGetLastError()) != hipSuccess) return e;
-        hipLaunchKernelGGL(fir_gh_dft_kernel, dim3((unsigned)M), dim3(WG), 0, st, static_cast<const double2 *>(spec),
-                           reinterpret_cast<const double2 *>(ws + lay.fwd.tw64), gH);
+        hipLaunchKernelGGL(fir_gh_dft_kernel, dim3((unsigned)((M + GH_DFT_LAGS - 1) / GH_DFT_LAGS)), dim3(WG), 0, st,
+                           static_cast<const double2 *>(spec), reinterpret_cast<const double2 *>(ws + lay.fwd.tw64),
+                           M, gH);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     } else {
         // input gradient: correlation of the cascade-input gradient with the taps

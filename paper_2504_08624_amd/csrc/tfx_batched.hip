@@ -41,17 +41,52 @@ __device__ void batch_section(const TB &tb, float (&v)[LC], const CarryCtx &cc, 
     }
 }
 
+// One section of the cascade-level form over a lane's chunk: zero-state
+// response, in-tile carry from the tile-entering state (P0, P1), and the
+// chunk's zero-input correction (skipped when only the state is needed).
+template <int LC>
+__device__ void batch_casc_section(const SecLdsC &tb, float (&v)[LC], int lane, int gw, float P0, float P1,
+                                   double (*s_agg)[GWAVES][2], int buf, bool correct, float &E0, float &E1) {
+    const float b0 = tb.coef[0], b1 = tb.coef[1], b2 = tb.coef[2];
+    const float a1 = tb.coef[3], a2 = tb.coef[4];
+    float s1 = 0.f, s2 = 0.f;
+#pragma unroll
+    for (int r = 0; r < LC; ++r) {
+        const float xv = v[r];
+        const float yv = fmaf(b0, xv, s1);
+        s1 = fmaf(b1, xv, fmaf(-a1, yv, s2));
+        s2 = fmaf(b2, xv, -a2 * yv);
+        v[r] = yv;
+    }
+    float z1, z2;
+    carry_local<float, SecLdsC>(tb, lane, gw, s1, s2, P0, P1, z1, z2, E0, E1, s_agg, buf);
+    if (correct) {
+#pragma unroll
+        for (int r = 0; r < LC; ++r) {
+            v[r] += z1;
+            const float n1 = fmaf(-a1, z1, z2);
+            z2 = -a2 * z1;
+            z1 = n1;
+        }
+    }
+}
+
 struct BatchArgs {
     const ClipDesc *desc;
     int32_t nclips;
     const SecTab *tab;
+    const CascTab *ctab;  // per clip (cascade-level variant)
     uint64_t *recs;
     uint32_t *hdr;
 };
 
 // HIQ: the variant with the FP64 carry; both run, the one that does not match
 // the batch's high-Q word advances the look-back epoch and exits.
-template <int LC, bool HIQ>
+// CASC: every clip's cascade (at most CASC_MAX sections, none needing FP64)
+// in the three phases of the chain kernel's cascade-level form: the cascade
+// over the tile from a zero state (tile aggregate), one look-back of the
+// whole 2S-component state, the cascade again from the known state.
+template <int LC, bool HIQ, bool CASC>
 __global__ __launch_bounds__(WG) void batch_kernel(BatchArgs a) {
     typedef Chunk<LC> K;
     __shared__ __align__(16) float lds[GROUPS * K::STG];
@@ -59,7 +94,11 @@ __global__ __launch_bounds__(WG) void batch_kernel(BatchArgs a) {
     __shared__ double s_pre[2 * GROUPS][2];
     __shared__ uint32_t s_epoch;
     __shared__ int s_clip;
-    extern __shared__ __align__(16) SecLds s_tab[];  // fp32 tables, LDS_SECTIONS at a time
+    // dynamic: fp32 tables (LDS_SECTIONS at a time; CASC: all of them without
+    // their look-back powers, then the cascade look-back area)
+    extern __shared__ __align__(16) unsigned char s_dyn[];
+    SecLds *s_tab = reinterpret_cast<SecLds *>(s_dyn);
+    SecLdsC *s_tabc = reinterpret_cast<SecLdsC *>(s_dyn);
 
     if ((a.hdr[HDR_HIQ] != 0u) != HIQ) {  // the other variant runs
         advance_epoch(a.hdr);
@@ -67,15 +106,24 @@ __global__ __launch_bounds__(WG) void batch_kernel(BatchArgs a) {
     }
     const int tid = threadIdx.x, lane = tid & 63, grp = tid / GL, gl = tid % GL, gw = gl >> 6;
     const int64_t id = blockIdx.x;
-    if (tid == 0) {
-        s_epoch = load_epoch(a.hdr, HDR_EPOCH);
-        int lo = 0, hi = a.nclips - 1;  // the last clip whose first block is <= id
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) / 2;
-            if (a.desc[mid].blk0 <= id) lo = mid;
-            else hi = mid - 1;
+    if (tid < 64) {
+        // the last clip whose first block is <= id (first blocks never
+        // decrease): a 64-way search by the first wave, two rounds for up
+        // to 4096 clips
+        int lo = 0, n = a.nclips;
+        while (n > 1) {
+            const int step = (n + 63) / 64;
+            const int j = lo + tid * step;
+            const bool ok = j < lo + n && a.desc[j].blk0 <= id;
+            const int cnt = __popcll(__ballot(ok));  // >= 1: desc[lo].blk0 <= id
+            const int nlo = lo + (cnt - 1) * step;
+            n = min(step, lo + n - nlo);
+            lo = nlo;
         }
-        s_clip = lo;
+        if (tid == 0) {
+            s_clip = lo;
+            s_epoch = load_epoch(a.hdr, HDR_EPOCH);
+        }
     }
     __syncthreads();
     const ClipDesc &d = a.desc[s_clip];
@@ -87,35 +135,83 @@ __global__ __launch_bounds__(WG) void batch_kernel(BatchArgs a) {
     const int64_t n0 = tile * K::T;
     float *stg = lds + grp * K::STG;
     float v[LC];
-    stage_tables(s_tab, a.tab, (int)d.tab0, min(d.S, LDS_SECTIONS), tid, WG);
-    stage_tile<LC>(stg, d.x + ch * d.ldx + n0, d.N - n0, valid, d.vec != 0, gl);
-    __syncthreads();
-    load_chunk<LC>(stg, gl, v);
-    for (int s = 0; s < d.S; ++s) {
-        if (s > 0 && s % LDS_SECTIONS == 0) {  // next block of tables
-            __syncthreads();
-            stage_tables(s_tab, a.tab, (int)d.tab0 + s, min(d.S - s, LDS_SECTIONS), tid, WG);
-            __syncthreads();
+    if constexpr (CASC) {
+        const int S = d.S, D = 2 * S, DD = D * D;
+        float *cr = reinterpret_cast<float *>(s_dyn + S * sizeof(SecLdsC));
+        float *cT = cr, *cM = cr + 3 * DD + grp * DD, *cE = cr + (3 + GROUPS) * DD + 32 * grp, *cP = cE + 16;
+        const CascTab &ct = a.ctab[s_clip];
+        stage_tables(s_tabc, a.tab, (int)d.tab0, S, tid, WG);
+        for (int e = tid; e < 3 * DD; e += WG) {
+            const int k = e / DD, i = (e % DD) / D, j = e % D;
+            cT[e] = ct.T[k][i][j];
         }
-        const SecLds &tb = s_tab[s % LDS_SECTIONS];
-        CarryCtx cc;
-        cc.lane = lane;
-        cc.gw = gw;
-        cc.grp = grp;
-        cc.lookback = true;
-        cc.pos = tile;
-        cc.recs = a.recs;
-        cc.rec0 = d.rec0 + ch * d.ntiles * d.S + s;
-        cc.rstride = d.S;
-        cc.epoch = epoch;
-        cc.hdr = a.hdr;
-        cc.known0 = cc.known1 = 0.0;
-        cc.prefix_out = nullptr;
-        const int buf = (s & 1) * GROUPS + grp;
-        if (HIQ && tb.hiq)
-            batch_section<LC, double>(a.tab[d.tab0 + s], v, cc, s_agg, s_pre, buf);
-        else
-            batch_section<LC, float>(tb, v, cc, s_agg, s_pre, buf);
+        stage_tile<LC>(stg, d.x + ch * d.ldx + n0, d.N - n0, valid, d.vec != 0, gl);
+        __syncthreads();
+        load_chunk<LC>(stg, gl, v);
+        if (S > 0) {  // (no state otherwise: y = x; block-uniform)
+            // (A) zero tile-entering state: the cascade's tile aggregate
+            for (int s = 0; s < S; ++s) {
+                float E0, E1;
+                batch_casc_section<LC>(s_tabc[s], v, lane, gw, 0.f, 0.f, s_agg, (s & 1) * GROUPS + grp, s + 1 < S, E0,
+                                       E1);
+                if (gl == 0) {
+                    cE[2 * s] = E0;
+                    cE[2 * s + 1] = E1;
+                }
+            }
+            // (B) one look-back of the cascade state (first wave of each group)
+            if (gw == 0) {
+                CascCtx cc;
+                cc.lane = lane;
+                cc.D = D;
+                cc.depth = ct.depth;
+                cc.rec = a.recs + (d.rec0 + ch * d.ntiles * S) * REC_WORDS;
+                cc.pos = tile;
+                cc.epoch = epoch;
+                cc.hdr = a.hdr;
+                cc.known = nullptr;
+                casc_lookback(cc, cT, cE, cP, cM);
+            }
+            __syncthreads();
+            // (C) every section from its known tile-entering state
+            load_chunk<LC>(stg, gl, v);
+            for (int s = 0; s < S; ++s) {
+                float E0, E1;
+                batch_casc_section<LC>(s_tabc[s], v, lane, gw, cP[2 * s], cP[2 * s + 1], s_agg, (s & 1) * GROUPS + grp,
+                                       true, E0, E1);
+            }
+        }
+    } else {
+        stage_tables(s_tab, a.tab, (int)d.tab0, min(d.S, LDS_SECTIONS), tid, WG);
+        stage_tile<LC>(stg, d.x + ch * d.ldx + n0, d.N - n0, valid, d.vec != 0, gl);
+        __syncthreads();
+        load_chunk<LC>(stg, gl, v);
+        for (int s = 0; s < d.S; ++s) {
+            if (s > 0 && s % LDS_SECTIONS == 0) {  // next block of tables
+                __syncthreads();
+                stage_tables(s_tab, a.tab, (int)d.tab0 + s, min(d.S - s, LDS_SECTIONS), tid, WG);
+                __syncthreads();
+            }
+            const SecLds &tb = s_tab[s % LDS_SECTIONS];
+            CarryCtx cc;
+            cc.lane = lane;
+            cc.gw = gw;
+            cc.grp = grp;
+            cc.lookback = true;
+            cc.pos = tile;
+            cc.recs = a.recs;
+            cc.rec0 = d.rec0 + ch * d.ntiles * d.S + s;
+            cc.rstride = d.S;
+            cc.epoch = epoch;
+            cc.hdr = a.hdr;
+            cc.known0 = cc.known1 = 0.0;
+            cc.prefix_out = nullptr;
+            const int buf = (s & 1) * GROUPS + grp;
+            if (HIQ && tb.hiq)
+                batch_section<LC, double>(a.tab[d.tab0 + s], v, cc, s_agg, s_pre, buf);
+            else
+                batch_section<LC, float>(tb, v, cc, s_agg, s_pre, buf);
+        }
     }
     __syncthreads();
     store_chunk<LC>(stg, gl, v);
@@ -209,6 +305,9 @@ BatchLayout batch_plan(const ClipIn *clips, int32_t n, int lc, int order, ClipDe
     off += al256b(sizeof(SecTab) * (size_t)tab);
     lay.recs = off;
     off += al256b((size_t)rec * REC_WORDS * sizeof(uint64_t));
+    lay.casc = off;
+    lay.casc_on = lay.smax > 0 && lay.smax <= CASC_MAX;
+    if (lay.casc_on) off += al256b(sizeof(CascTab) * (size_t)n);
     lay.total = off;
     return lay;
 }
@@ -222,20 +321,33 @@ hipError_t launch_batch_run(const BatchLayout &lay, int lc, int32_t nclips, void
     a.tab = reinterpret_cast<const SecTab *>(w + lay.tab);
     a.recs = reinterpret_cast<uint64_t *>(w + lay.recs);
     a.hdr = reinterpret_cast<uint32_t *>(w + lay.hdr);
+    a.ctab = reinterpret_cast<const CascTab *>(w + lay.casc);
     const dim3 grid((unsigned)lay.nblocks), block(WG);
     const size_t dyn = sizeof(SecLds) * (size_t)(lay.smax < LDS_SECTIONS ? lay.smax : LDS_SECTIONS);
+    const size_t dync = sizeof(SecLdsC) * (size_t)lay.smax + sizeof(float) * (size_t)casc_floats(2 * lay.smax);
+    const bool cs = lay.casc_on;
     hipError_t e = hipSuccess;
-    for (int hiq = 0; hiq < 2 && e == hipSuccess; ++hiq) {
-        switch (lc * 2 + hiq) {
-            case 32: hipLaunchKernelGGL((batch_kernel<16, false>), grid, block, dyn, st, a); break;
-            case 33: hipLaunchKernelGGL((batch_kernel<16, true>), grid, block, dyn, st, a); break;
-            case 64: hipLaunchKernelGGL((batch_kernel<32, false>), grid, block, dyn, st, a); break;
-            case 65: hipLaunchKernelGGL((batch_kernel<32, true>), grid, block, dyn, st, a); break;
-            case 49: hipLaunchKernelGGL((batch_kernel<24, true>), grid, block, dyn, st, a); break;
-            default: hipLaunchKernelGGL((batch_kernel<24, false>), grid, block, dyn, st, a); break;
-        }
-        e = hipGetLastError();
+    switch (lc) {
+        case 16:
+            if (cs) hipLaunchKernelGGL((batch_kernel<16, false, true>), grid, block, dync, st, a);
+            else hipLaunchKernelGGL((batch_kernel<16, false, false>), grid, block, dyn, st, a);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+            hipLaunchKernelGGL((batch_kernel<16, true, false>), grid, block, dyn, st, a);
+            break;
+        case 32:
+            if (cs) hipLaunchKernelGGL((batch_kernel<32, false, true>), grid, block, dync, st, a);
+            else hipLaunchKernelGGL((batch_kernel<32, false, false>), grid, block, dyn, st, a);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+            hipLaunchKernelGGL((batch_kernel<32, true, false>), grid, block, dyn, st, a);
+            break;
+        default:
+            if (cs) hipLaunchKernelGGL((batch_kernel<24, false, true>), grid, block, dync, st, a);
+            else hipLaunchKernelGGL((batch_kernel<24, false, false>), grid, block, dyn, st, a);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+            hipLaunchKernelGGL((batch_kernel<24, true, false>), grid, block, dyn, st, a);
+            break;
     }
+    e = hipGetLastError();
     return e;
 }
 

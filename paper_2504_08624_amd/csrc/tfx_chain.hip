@@ -59,7 +59,6 @@ constexpr bool is_fft() { return FIRM == FIR_FFT || FIRM == FIR_FFT_PARTS; }
 
 // LDS of the cascade-level look-back (floats): Phi_T, Phi_T^2, Phi_T^4 and a
 // window weight per group (D x D each), tile aggregate and prefix per group.
-__host__ __device__ constexpr int casc_floats(int D) { return (3 + GROUPS) * D * D + 2 * GROUPS * 16; }
 // After the FFT the tail of its buffers beyond the two staging areas is free.
 constexpr int FFT_TAIL_FLOATS = 2 * NFFT - GROUPS * STG_FLOATS;
 __host__ __device__ constexpr bool casc_in_tail(int FIRM, int S) {
@@ -373,16 +372,7 @@ __global__ __launch_bounds__(WG) void chain_kernel(KArgs a) {
         fft_block<FIRM == FIR_FFT_PARTS>(a, lds, pair, n0, c.tid, zr, zi);
         if (!HAS_SOS) {
             const int64_t chA = 2 * pair, chB = chA + 1;
-            float *yA = a.y + chA * a.ldy;
-            float *yB = a.y + chB * a.ldy;
-#pragma unroll
-            for (int q = 4; q < 16; ++q) {
-                const int64_t n = n0 + 256 * (q - 4) + c.tid;
-                if (n < a.N) {
-                    yA[n] = zr[q];
-                    if (chB < a.C) yB[n] = zi[q];
-                }
-            }
+            store_pair_tile<4>(zr, zi, a.y + chA * a.ldy, chB < a.C ? a.y + chB * a.ldy : nullptr, n0, a.N, c.tid);
             return;
         }
         __syncthreads();  // FFT buffers become the two staging areas

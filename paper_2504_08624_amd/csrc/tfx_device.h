@@ -421,15 +421,58 @@ __device__ __forceinline__ void spectrum_product(float (&zr)[16], float (&zi)[16
 }
 
 // Loads the complex block z[m] = xa[base + m] + i xb[base + m], m = 256 q + tid
-// (zeros outside [0, N); xb may be null) into the forward FFT input layout.
+// (zeros outside [0, N) and past limit; xb may be null) into the forward FFT
+// input layout.  A block wholly inside takes no per-element checks.
 __device__ __forceinline__ void load_pair_block(float (&zr)[16], float (&zi)[16], const float *xa, const float *xb,
                                                 int64_t base, int64_t N, int64_t limit, int tid) {
+    const int64_t hi = N < limit ? N : limit;
+    if (base >= 0 && base + NFFT <= hi) {
+        const float *pa = xa + base + tid;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) zr[q] = pa[256 * q];
+        if (xb) {
+            const float *pb = xb + base + tid;
+#pragma unroll
+            for (int q = 0; q < 16; ++q) zi[q] = pb[256 * q];
+        } else {
+#pragma unroll
+            for (int q = 0; q < 16; ++q) zi[q] = 0.f;
+        }
+        return;
+    }
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
         const int64_t n = base + 256 * q + tid;
-        const bool in = n >= 0 && n < N && n < limit;
+        const bool in = n >= 0 && n < hi;
         zr[q] = in ? xa[n] : 0.f;
         zi[q] = (in && xb) ? xb[n] : 0.f;
+    }
+}
+
+// Stores the 3072 outputs of a tile held as zr/zi[q0 .. q0 + 12) (lane tid
+// holds sample 256 (q - q0) + tid) to ya[n0 + .] and, when yb is set,
+// yb[n0 + .], up to N.  A tile wholly inside takes no per-element checks.
+template <int Q0>
+__device__ __forceinline__ void store_pair_tile(const float (&zr)[16], const float (&zi)[16], float *ya, float *yb,
+                                                int64_t n0, int64_t N, int tid) {
+    if (n0 + 12 * 256 <= N) {
+        float *pa = ya + n0 + tid;
+#pragma unroll
+        for (int q = 0; q < 12; ++q) pa[256 * q] = zr[Q0 + q];
+        if (yb) {
+            float *pb = yb + n0 + tid;
+#pragma unroll
+            for (int q = 0; q < 12; ++q) pb[256 * q] = zi[Q0 + q];
+        }
+        return;
+    }
+#pragma unroll
+    for (int q = 0; q < 12; ++q) {
+        const int64_t n = n0 + 256 * q + tid;
+        if (n < N) {
+            ya[n] = zr[Q0 + q];
+            if (yb) yb[n] = zi[Q0 + q];
+        }
     }
 }
 

@@ -99,6 +99,9 @@ constexpr double DEPTH_EPS = 8.673617379884035e-19;  // 2^-60
 // Powers of the cascade's tile transition A_c^3072 (state order: section s
 // at components 2s, 2s+1), zero-padded to 16 x 16.
 constexpr int CASC_MAX = 8;
+// LDS floats of a cascade look-back area for D = 2S components: T (3 D x D),
+// one window weight per channel group (D x D), E and P per group (16 each).
+__host__ __device__ constexpr int casc_floats(int D) { return (3 + GROUPS) * D * D + 2 * GROUPS * 16; }
 struct alignas(16) CascTab {
     int32_t depth;       // look-back depth d <= 64 with max |Phi_T^d| <= 2^-60 (0 = none found)
     int32_t pad[3];
@@ -191,9 +194,10 @@ struct alignas(16) ClipDesc {
 };
 
 struct BatchLayout {
-    size_t hdr, desc, tab, recs, total;
+    size_t hdr, desc, tab, recs, casc, total;
     int64_t nblocks, nsec, nrec;
     int32_t smax;  // longest cascade of the batch
+    bool casc_on;  // every cascade has at most CASC_MAX sections: one CascTab per clip
 };
 
 // host-side clip record (mirrors the public tfx_clip)

@@ -90,7 +90,7 @@ __device__ void build_section_block(SecTab *tb, const float *co, int Lc, int tid
 // look-back, in FP64, by one block of 256 threads (one matrix element
 // each).  The cascade's one-sample transition F (zero input): block (i, i) =
 // A_i; block (i, j), j < i = B_i (prod_{j<l<i} D_l) C, since section i's
-// input is section i-1's output; Phi_T = F^3072 = (F^8 F^16)^128.
+// input is section i-1's output; Phi_T = F^(128 Lc) = (F^Lc)^128.
 __device__ void mm16(const double (*A)[16], const double (*B)[16], double (*R)[16], int i, int j) {
     double acc = 0.0;
     for (int k = 0; k < 16; ++k) acc += A[i][k] * B[k][j];
@@ -112,19 +112,13 @@ __device__ double block_maxabs(const double (*M)[16], int i, int j, int tid) {
     return v;
 }
 
-__device__ void casc_table_block(const StageList &sos, int32_t S, CascTab *out, int tid) {
+// co(s, k): coefficient k of section s; Lc: the chunk length (tile 128 Lc).
+template <class Co>
+__device__ void casc_table_block(Co co_at, int32_t S, int Lc, CascTab *out, int tid) {
     __shared__ double co[CASC_MAX][5];
     __shared__ double M0[16][16], M1[16][16], Pw[7][16][16];
     const int i = tid >> 4, j = tid & 15;
-    if (tid < S * 5) {
-        int s = tid / 5, st = 0;
-        const int k = tid % 5;
-        while (s >= sos.len[st]) {
-            s -= sos.len[st];
-            ++st;
-        }
-        co[tid / 5][k] = sos.ptr[st][5 * s + k];
-    }
+    if (tid < S * 5) co[tid / 5][tid % 5] = co_at(tid / 5, tid % 5);
     __syncthreads();
     const int D = 2 * S;
     double f = 0.0;
@@ -139,14 +133,14 @@ __device__ void casc_table_block(const StageList &sos, int32_t S, CascTab *out, 
             f = pr;
         }
     }
-    M0[i][j] = f;
+    M1[i][j] = f;
+    Pw[0][i][j] = i == j ? 1.0 : 0.0;
     __syncthreads();
-    mm16(M0, M0, M1, i, j);  // F^2
-    mm16(M1, M1, M0, i, j);  // F^4
-    mm16(M0, M0, M1, i, j);  // F^8
-    mm16(M1, M1, M0, i, j);  // F^16
-    mm16(M0, M1, Pw[0], i, j);  // F^24
-    for (int t = 0; t < 7; ++t) mm16(Pw[0], Pw[0], Pw[0], i, j);  // F^(24 * 128) = F^3072
+    for (int e = Lc; e > 0; e >>= 1) {  // Pw[0] = F^Lc by binary powering
+        if (e & 1) mm16(Pw[0], M1, Pw[0], i, j);
+        if (e > 1) mm16(M1, M1, M1, i, j);
+    }
+    for (int t = 0; t < 7; ++t) mm16(Pw[0], Pw[0], Pw[0], i, j);  // F^(128 Lc), the tile transition
     for (int t = 1; t < 7; ++t) mm16(Pw[t - 1], Pw[t - 1], Pw[t], i, j);  // Phi_T^(2^t)
     out->T[0][i][j] = (float)Pw[0][i][j];
     out->T[1][i][j] = (float)Pw[1][i][j];
@@ -320,7 +314,17 @@ __global__ __launch_bounds__(256) void prepare_kernel(PrepareArgs a) {
         }
         build_section_block(&a.tab[b - a.nspec], a.sos.ptr[st] + 5 * s, L, tid);
     } else if (a.casc && b == a.nspec + a.S) {
-        casc_table_block(a.sos, a.S, a.ctab, tid);
+        const StageList &sl = a.sos;
+        casc_table_block(
+            [&](int s, int k) {
+                int st = 0;
+                while (s >= sl.len[st]) {
+                    s -= sl.len[st];
+                    ++st;
+                }
+                return (double)sl.ptr[st][5 * s + k];
+            },
+            a.S, L, a.ctab, tid);
     }
 }
 
@@ -341,8 +345,11 @@ struct BatchPrepArgs {
     int64_t nwords;
     uint32_t *hdr;
     int32_t lc;
+    CascTab *ctab;  // per clip, or null
 };
 
+// Blocks g < nsec build section g; blocks nsec + c build clip c's cascade
+// tables (when ctab is set); every block clears a share of the records.
 __global__ __launch_bounds__(256) void batch_prep_kernel(BatchPrepArgs a) {
     const int tid = threadIdx.x;
     for (int64_t i = (int64_t)blockIdx.x * 256 + tid; i < a.nwords; i += (int64_t)gridDim.x * 256) a.recs[i] = 0ull;
@@ -355,17 +362,27 @@ __global__ __launch_bounds__(256) void batch_prep_kernel(BatchPrepArgs a) {
                 any |= section_hiq(a.desc[c].sos[5 * s + 3], a.desc[c].sos[5 * s + 4]) ? 1u : 0u;
         a.hdr[HDR_HIQ] = any;
     }
-    for (int64_t g = blockIdx.x; g < a.nsec; g += gridDim.x) {
-        // the last clip with tab0 <= g: tab0 grows with the clip index by S,
-        // so that clip has S > 0 and holds section g
-        int lo = 0, hi = a.nclips - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) / 2;
-            if (a.desc[mid].tab0 <= g) lo = mid;
-            else hi = mid - 1;
+    const int64_t nroles = a.nsec + (a.ctab ? a.nclips : 0);
+    for (int64_t g = blockIdx.x; g < nroles; g += gridDim.x) {
+        if (g < a.nsec) {
+            // the last clip with tab0 <= g: tab0 grows with the clip index by
+            // S, so that clip has S > 0 and holds section g
+            int lo = 0, hi = a.nclips - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) / 2;
+                if (a.desc[mid].tab0 <= g) lo = mid;
+                else hi = mid - 1;
+            }
+            build_section_block(&a.tab[g], a.desc[lo].sos + 5 * (g - a.desc[lo].tab0), a.lc, tid);
+        } else {
+            const ClipDesc &d = a.desc[g - a.nsec];
+            if (d.S > 0) {
+                const float *co = d.sos;
+                casc_table_block([&](int s, int k) { return (double)co[5 * s + k]; }, d.S, a.lc,
+                                 &a.ctab[g - a.nsec], tid);
+            }
         }
-        build_section_block(&a.tab[g], a.desc[lo].sos + 5 * (g - a.desc[lo].tab0), a.lc, tid);
-        __syncthreads();  // s_dep is reused by the next section
+        __syncthreads();  // the role's shared memory is reused by the next one
     }
 }
 
@@ -380,9 +397,11 @@ hipError_t launch_batch_prepare(const BatchLayout &lay, int lc, int32_t nclips, 
     a.nwords = lay.nrec * 4;
     a.hdr = reinterpret_cast<uint32_t *>(w + lay.hdr);
     a.lc = lc;
+    a.ctab = lay.casc_on ? reinterpret_cast<CascTab *>(w + lay.casc) : nullptr;
+    const int64_t nroles = a.nsec + (a.ctab ? nclips : 0);
     int64_t nb = (a.nwords + 255) / 256;
     if (nb > 2048) nb = 2048;
-    if (nb < a.nsec) nb = a.nsec < 2048 ? a.nsec : 2048;
+    if (nb < nroles) nb = nroles < 2048 ? nroles : 2048;
     if (nb < 1) nb = 1;
     hipLaunchKernelGGL(batch_prep_kernel, dim3((unsigned)nb), dim3(256), 0, st, a);
     return hipGetLastError();

@@ -260,6 +260,25 @@ def test_chain_backward_fir_only_and_sos_only():
     _chain_check(x, g, [("sos", _sections(3, (338,)))], "sos only")
 
 
+@pytest.mark.parametrize("M", [101, 1025])
+def test_chain_backward_input_gradient_only(M):
+    """Input gradient without coefficient gradients: the FFT FIR's fused
+    gradient kernel then skips the tap-gradient spectra."""
+    print("chain_backward gx only M=%d" % M, flush=True)
+    C, N = 5, 3 * T + 101
+    x = _x(C, N, (350, M))
+    g = _x(C, N, (351, M), 1.0)
+    h = design.fir_lowpass(M, 5000.0, 48000.0).astype(np.float32)
+    for stages in ([("fir", h)], [("fir", h), ("sos", _sections(2, (352, M)))]):
+        xg = _gpu(x)
+        st = [(k, _gpu(c)) for k, c in stages]
+        ck = tfx.chain(xg, st, return_ckpt=True)[1] if len(stages) > 1 else None
+        gx, grads = tfx.chain_backward(xg, _gpu(g), st, ck, need_coef=False)
+        assert all(gr is None for gr in grads)
+        rgx, _ = O.chain_backward(g, x, stages)
+        assert_close(_cpu(gx), rgx, TOL_GRAD, "gx only, %d stages" % len(stages))
+
+
 def test_backward_deterministic():
     w = workloads.chain_mid(C=2, N=6 * T + 1)
     g = _gpu(_x(2, w.x.shape[1], (339,), 1.0))
