@@ -41,36 +41,6 @@ __device__ void batch_section(const TB &tb, float (&v)[LC], const CarryCtx &cc, 
     }
 }
 
-// One section of the cascade-level form over a lane's chunk: zero-state
-// response, in-tile carry from the tile-entering state (P0, P1), and the
-// chunk's zero-input correction (skipped when only the state is needed).
-template <int LC>
-__device__ void batch_casc_section(const SecLdsC &tb, float (&v)[LC], int lane, int gw, float P0, float P1,
-                                   double (*s_agg)[GWAVES][2], int buf, bool correct, float &E0, float &E1) {
-    const float b0 = tb.coef[0], b1 = tb.coef[1], b2 = tb.coef[2];
-    const float a1 = tb.coef[3], a2 = tb.coef[4];
-    float s1 = 0.f, s2 = 0.f;
-#pragma unroll
-    for (int r = 0; r < LC; ++r) {
-        const float xv = v[r];
-        const float yv = fmaf(b0, xv, s1);
-        s1 = fmaf(b1, xv, fmaf(-a1, yv, s2));
-        s2 = fmaf(b2, xv, -a2 * yv);
-        v[r] = yv;
-    }
-    float z1, z2;
-    carry_local<float, SecLdsC>(tb, lane, gw, s1, s2, P0, P1, z1, z2, E0, E1, s_agg, buf);
-    if (correct) {
-#pragma unroll
-        for (int r = 0; r < LC; ++r) {
-            v[r] += z1;
-            const float n1 = fmaf(-a1, z1, z2);
-            z2 = -a2 * z1;
-            z1 = n1;
-        }
-    }
-}
-
 struct BatchArgs {
     const ClipDesc *desc;
     int32_t nclips;
@@ -137,6 +107,7 @@ __global__ __launch_bounds__(WG) void batch_kernel(BatchArgs a) {
     float v[LC];
     if constexpr (CASC) {
         const int S = d.S, D = 2 * S, DD = D * D;
+        // tables, then the cascade look-back area
         float *cr = reinterpret_cast<float *>(s_dyn + S * sizeof(SecLdsC));
         float *cT = cr, *cM = cr + 3 * DD + grp * DD, *cE = cr + (3 + GROUPS) * DD + 32 * grp, *cP = cE + 16;
         const CascTab &ct = a.ctab[s_clip];
@@ -149,11 +120,20 @@ __global__ __launch_bounds__(WG) void batch_kernel(BatchArgs a) {
         __syncthreads();
         load_chunk<LC>(stg, gl, v);
         if (S > 0) {  // (no state otherwise: y = x; block-uniform)
-            // (A) zero tile-entering state: the cascade's tile aggregate
+            // (A) zero tile-entering state: the cascade's tile aggregate; the
+            //     last section only needs its state
+            float eA0 = 0.f, eA1 = 0.f;
             for (int s = 0; s < S; ++s) {
-                float E0, E1;
-                batch_casc_section<LC>(s_tabc[s], v, lane, gw, 0.f, 0.f, s_agg, (s & 1) * GROUPS + grp, s + 1 < S, E0,
-                                       E1);
+                float e0, e1, E0, E1;
+                const int buf = (s & 1) * GROUPS + grp;
+                if (s + 1 < S)
+                    casc_section_a<LC, true>(s_tabc[s], v, lane, gw, s_agg, buf, e0, e1, E0, E1);
+                else
+                    casc_section_a<LC, false>(s_tabc[s], v, lane, gw, s_agg, buf, e0, e1, E0, E1);
+                if (s == 0) {
+                    eA0 = e0;
+                    eA1 = e1;
+                }
                 if (gl == 0) {
                     cE[2 * s] = E0;
                     cE[2 * s + 1] = E1;
@@ -173,12 +153,20 @@ __global__ __launch_bounds__(WG) void batch_kernel(BatchArgs a) {
                 casc_lookback(cc, cT, cE, cP, cM);
             }
             __syncthreads();
-            // (C) every section from its known tile-entering state
+            // (C) every section from its known tile-entering state; section 0
+            //     reuses phase A's carry (its input is unchanged)
             load_chunk<LC>(stg, gl, v);
             for (int s = 0; s < S; ++s) {
-                float E0, E1;
-                batch_casc_section<LC>(s_tabc[s], v, lane, gw, cP[2 * s], cP[2 * s + 1], s_agg, (s & 1) * GROUPS + grp,
-                                       true, E0, E1);
+                const SecLdsC &tb = s_tabc[s];
+                float c1, c2;
+                if (s == 0) {
+                    float e0 = eA0, e1 = eA1;
+                    fold_prefix(tb, lane, gw, cP[0], cP[1], e0, e1);
+                    section_from<LC>(tb.coef, v, e0, e1, -1, c1, c2);
+                } else {
+                    casc_section_c<LC, false>(tb, v, lane, gw, cP[2 * s], cP[2 * s + 1], s_agg,
+                                              (s & 1) * GROUPS + grp, -1, c1, c2);
+                }
             }
         }
     } else {

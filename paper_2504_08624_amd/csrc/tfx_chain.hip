@@ -168,13 +168,13 @@ struct TileCtx {
 // KNOWN: the section's tile-entering state `known` has been produced by the
 // cascade-level look-back (no look-back here; the checkpoint is written by
 // the caller).
-template <typename CT, class TB, bool KNOWN = false>
+template <typename CT, class TB, bool STOUT, bool KNOWN = false>
 __device__ void run_section(const KArgs &a, const TB &tb, int s, float (&v)[L], const TileCtx &c,
                             double (*s_agg)[GWAVES][2], double (*s_pre)[2], const float *known = nullptr) {
     const float b0 = tb.coef[0], b1 = tb.coef[1], b2 = tb.coef[2];
     const float a1 = tb.coef[3], a2 = tb.coef[4];
     float s1 = 0.f, s2 = 0.f, c1 = 0.f, c2 = 0.f;
-    if (c.is_last) {
+    if (STOUT && c.is_last) {
 #pragma unroll
         for (int r = 0; r < L; ++r) {
             const float xv = v[r];
@@ -222,7 +222,7 @@ __device__ void run_section(const KArgs &a, const TB &tb, int s, float (&v)[L], 
     } else {
         carry<CT, false, TB>(tb, cc, s1, s2, z1, z2, s_agg, s_pre, (s & 1) * GROUPS + c.grp);
     }
-    if (c.is_last) {
+    if (STOUT && c.is_last) {
 #pragma unroll
         for (int r = 0; r < L; ++r) {
             v[r] += z1;
@@ -259,7 +259,7 @@ __device__ void run_section(const KArgs &a, const TB &tb, int s, float (&v)[L], 
 // section again from its now known tile-entering state, with no look-back.
 // This trades a second in-tile pass for S - 1 fewer cross-tile round trips,
 // which dominate the per-section form.
-template <int FIRM, bool HAS_SOS, bool HIQ, bool CASC>
+template <int FIRM, bool HAS_SOS, bool HIQ, bool CASC, bool STOUT>
 __global__ __launch_bounds__(WG) void chain_kernel(KArgs a) {
     __shared__ __align__(16) float lds[lds_floats<FIRM>()];
     __shared__ double s_agg[2 * GROUPS][GWAVES][2];
@@ -388,7 +388,7 @@ __global__ __launch_bounds__(WG) void chain_kernel(KArgs a) {
     }
 
     if (HAS_SOS && CASC) {
-        c.is_last = (c.tile == a.ntiles - 1);
+        c.is_last = STOUT && (c.tile == a.ntiles - 1);
         const int64_t plast = a.N - 1 - n0;
         c.r_last = c.is_last ? (int)(plast % L) : 0;
         c.owner = c.is_last ? (int)(plast / L) : -1;
@@ -402,34 +402,23 @@ __global__ __launch_bounds__(WG) void chain_kernel(KArgs a) {
             const int k = e / DD, i = (e % DD) / D, j = e % D;
             cT[e] = a.casc->T[k][i][j];
         }
-        // (A) zero tile-entering state: the cascade's tile aggregate
+        // (A) zero tile-entering state: the cascade's tile aggregate; the
+        //     last section only needs its state
+        float eA0 = 0.f, eA1 = 0.f;
         for (int s = 0; s < a.S; ++s) {
-            const SecLdsC &tb = s_tabc[s];
-            const float b0 = tb.coef[0], b1 = tb.coef[1], b2 = tb.coef[2], a1 = tb.coef[3], a2 = tb.coef[4];
-            float s1 = 0.f, s2 = 0.f;
-#pragma unroll
-            for (int r = 0; r < L; ++r) {
-                const float xv = v[r];
-                const float yv = fmaf(b0, xv, s1);
-                s1 = fmaf(b1, xv, fmaf(-a1, yv, s2));
-                s2 = fmaf(b2, xv, -a2 * yv);
-                v[r] = yv;
+            float e0, e1, E0, E1;
+            const int buf = (s & 1) * GROUPS + c.grp;
+            if (s + 1 < a.S)
+                casc_section_a<L, true>(s_tabc[s], v, c.lane, c.gw, s_agg, buf, e0, e1, E0, E1);
+            else
+                casc_section_a<L, false>(s_tabc[s], v, c.lane, c.gw, s_agg, buf, e0, e1, E0, E1);
+            if (s == 0) {
+                eA0 = e0;
+                eA1 = e1;
             }
-            float z1, z2, E0, E1;
-            carry_local<float, SecLdsC>(tb, c.lane, c.gw, s1, s2, 0.f, 0.f, z1, z2, E0, E1, s_agg,
-                                        (s & 1) * GROUPS + c.grp);
             if (c.gl == 0) {
                 cE[2 * s] = E0;
                 cE[2 * s + 1] = E1;
-            }
-            if (s + 1 < a.S) {
-#pragma unroll
-                for (int r = 0; r < L; ++r) {
-                    v[r] += z1;
-                    const float n1 = fmaf(-a1, z1, z2);
-                    z2 = -a2 * z1;
-                    z1 = n1;
-                }
             }
         }
         // (B) one look-back of the cascade state (first wave of each group)
@@ -447,12 +436,32 @@ __global__ __launch_bounds__(WG) void chain_kernel(KArgs a) {
             if (a.ckpt && c.valid && c.lane < D) a.ckpt[(c.ch * a.ntiles + c.tile) * a.S * 2 + c.lane] = cP[c.lane];
         }
         __syncthreads();
-        // (C) every section from its known tile-entering state
+        // (C) every section from its known tile-entering state; section 0
+        //     reuses phase A's carry (its input is unchanged)
         load_chunk(stg, c.gl, v);
-        for (int s = 0; s < a.S; ++s)
-            run_section<float, SecLdsC, true>(a, s_tabc[s], s, v, c, s_agg, s_pre, cP + 2 * s);
+        const int r_cap = c.gl == c.owner ? c.r_last : -1;
+        for (int s = 0; s < a.S; ++s) {
+            const SecLdsC &tb = s_tabc[s];
+            float c1 = 0.f, c2 = 0.f;
+            if (s == 0) {
+                float e0 = eA0, e1 = eA1;
+                fold_prefix(tb, c.lane, c.gw, cP[0], cP[1], e0, e1);
+                if (STOUT && c.is_last) section_from<L, true>(tb.coef, v, e0, e1, r_cap, c1, c2);
+                else section_from<L>(tb.coef, v, e0, e1, -1, c1, c2);
+            } else {
+                const int buf = (s & 1) * GROUPS + c.grp;
+                if (STOUT && c.is_last)
+                    casc_section_c<L, true>(tb, v, c.lane, c.gw, cP[2 * s], cP[2 * s + 1], s_agg, buf, r_cap, c1, c2);
+                else
+                    casc_section_c<L, false>(tb, v, c.lane, c.gw, cP[2 * s], cP[2 * s + 1], s_agg, buf, -1, c1, c2);
+            }
+            if (STOUT && r_cap >= 0 && c.valid && a.state_out) {
+                a.state_out[(c.ch * a.S + s) * 2 + 0] = c1;
+                a.state_out[(c.ch * a.S + s) * 2 + 1] = c2;
+            }
+        }
     } else if (HAS_SOS) {
-        c.is_last = (c.tile == a.ntiles - 1);
+        c.is_last = STOUT && (c.tile == a.ntiles - 1);
         const int64_t plast = a.N - 1 - n0;
         c.r_last = c.is_last ? (int)(plast % L) : 0;
         c.owner = c.is_last ? (int)(plast / L) : -1;
@@ -464,9 +473,9 @@ __global__ __launch_bounds__(WG) void chain_kernel(KArgs a) {
             }
             const SecLds &tl = s_tab[s % LDS_SECTIONS];
             if (HIQ && tl.hiq)
-                run_section<double>(a, a.tab[s], s, v, c, s_agg, s_pre);
+                run_section<double, SecTab, STOUT>(a, a.tab[s], s, v, c, s_agg, s_pre);
             else
-                run_section<float>(a, tl, s, v, c, s_agg, s_pre);
+                run_section<float, SecLds, STOUT>(a, tl, s, v, c, s_agg, s_pre);
         }
     }
 
@@ -517,26 +526,34 @@ WsLayout ws_layout(int64_t C, int64_t N, int32_t S, int32_t M_merged, int32_t n_
 // kernel of the prepare step (tfx_tables.hip)
 hipError_t launch_state_passthrough(const float *in, float *out, int64_t n, hipStream_t st);
 
-template <int F, bool S>
-static hipError_t launch_main(const KArgs &k, int64_t nblocks, hipStream_t st) {
+template <int F, bool S, bool STOUT>
+static hipError_t launch_variants(const KArgs &k, int64_t nblocks, hipStream_t st) {
     const size_t dyn = S ? sizeof(SecLds) * (size_t)(k.S < LDS_SECTIONS ? k.S : LDS_SECTIONS) : 0;
     if constexpr (S) {
         const size_t dync = sizeof(SecLdsC) * (size_t)k.S +
                             (casc_in_tail(F, k.S) ? 0 : sizeof(float) * (size_t)casc_floats(2 * k.S));
         if (k.S <= CASC_MAX)
-            hipLaunchKernelGGL((chain_kernel<F, S, false, true>), dim3((unsigned)nblocks), dim3(WG), dync, st, k);
+            hipLaunchKernelGGL((chain_kernel<F, S, false, true, STOUT>), dim3((unsigned)nblocks), dim3(WG), dync, st, k);
         else
-            hipLaunchKernelGGL((chain_kernel<F, S, false, false>), dim3((unsigned)nblocks), dim3(WG), dyn, st, k);
+            hipLaunchKernelGGL((chain_kernel<F, S, false, false, STOUT>), dim3((unsigned)nblocks), dim3(WG), dyn, st, k);
     } else {
-        hipLaunchKernelGGL((chain_kernel<F, S, false, false>), dim3((unsigned)nblocks), dim3(WG), dyn, st, k);
+        hipLaunchKernelGGL((chain_kernel<F, S, false, false, false>), dim3((unsigned)nblocks), dim3(WG), dyn, st, k);
     }
     hipError_t e = hipGetLastError();
     if constexpr (S) {
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL((chain_kernel<F, S, true, false>), dim3((unsigned)nblocks), dim3(WG), dyn, st, k);
+        hipLaunchKernelGGL((chain_kernel<F, S, true, false, STOUT>), dim3((unsigned)nblocks), dim3(WG), dyn, st, k);
         e = hipGetLastError();
     }
     return e;
+}
+
+// STOUT: the variants that record the final state of every section (only
+// when the caller asks for it, so the common variants carry no such code).
+template <int F, bool S>
+static hipError_t launch_main(const KArgs &k, int64_t nblocks, hipStream_t st) {
+    if (S && k.state_out) return launch_variants<F, S, true>(k, nblocks, st);
+    return launch_variants<F, S, false>(k, nblocks, st);
 }
 
 int32_t merged_taps(const StageList &f) {

@@ -705,6 +705,115 @@ __device__ void carry_local(const TB &tb, int lane, int gw, float z0, float z1, 
     e1 = (float)s1;
 }
 
+// ---------------------------------------------- cascade-level section form
+// TDF-II over the chunk from (s1, s2), in place; with CAP the state after
+// sample r_cap (if 0 <= r_cap < LC) is returned in (c1, c2).
+template <int LC, bool CAP = false>
+__device__ __forceinline__ void section_from(const float *co, float (&v)[LC], float s1, float s2, int r_cap,
+                                             float &c1, float &c2) {
+    const float b0 = co[0], b1 = co[1], b2 = co[2], a1 = co[3], a2 = co[4];
+#pragma unroll
+    for (int r = 0; r < LC; ++r) {
+        const float xv = v[r];
+        const float yv = fmaf(b0, xv, s1);
+        s1 = fmaf(b1, xv, fmaf(-a1, yv, s2));
+        s2 = fmaf(b2, xv, -a2 * yv);
+        v[r] = yv;
+        if (CAP && r == r_cap) {
+            c1 = s1;
+            c2 = s2;
+        }
+    }
+}
+
+// e += Phi^lane Psi^gw P: how a tile-entering state P moves a lane's
+// chunk-entering state (carry_local is linear in its prefix).
+template <class TB>
+__device__ __forceinline__ void fold_prefix(const TB &tb, int lane, int gw, float P0, float P1, float &e0, float &e1) {
+    float x0 = 0.f, x1 = 0.f;
+    madd2<false>(x0, x1, Tab<float>::psi(tb, gw), P0, P1);
+    madd2<false>(e0, e1, Tab<float>::fold(tb, lane), x0, x1);
+}
+
+// Phase-A form of a section (zero tile-entering state): zero-state response
+// over the chunk, the in-tile carry to the chunk-entering state e, and the
+// zero-input response of e added in place.  !RUN: only the state is needed
+// (the last section), so the zero-state pass keeps no output and no
+// correction follows.
+template <int LC, bool RUN>
+__device__ __forceinline__ void casc_section_a(const SecLdsC &tb, float (&v)[LC], int lane, int gw,
+                                               double (*s_agg)[GWAVES][2], int buf, float &e0, float &e1, float &E0,
+                                               float &E1) {
+    const float b0 = tb.coef[0], b1 = tb.coef[1], b2 = tb.coef[2], a1 = tb.coef[3], a2 = tb.coef[4];
+    float s1 = 0.f, s2 = 0.f;
+    if (RUN) {
+#pragma unroll
+        for (int r = 0; r < LC; ++r) {
+            const float xv = v[r];
+            const float yv = fmaf(b0, xv, s1);
+            s1 = fmaf(b1, xv, fmaf(-a1, yv, s2));
+            s2 = fmaf(b2, xv, -a2 * yv);
+            v[r] = yv;
+        }
+    } else {  // s' = A s + B x: 4 operations a sample
+        const float B0 = fmaf(-a1, b0, b1), B1 = fmaf(-a2, b0, b2);
+#pragma unroll
+        for (int r = 0; r < LC; ++r) {
+            const float xv = v[r];
+            const float n1 = fmaf(B0, xv, fmaf(-a1, s1, s2));
+            s2 = fmaf(B1, xv, -a2 * s1);
+            s1 = n1;
+        }
+    }
+    carry_local<float, SecLdsC>(tb, lane, gw, s1, s2, 0.f, 0.f, e0, e1, E0, E1, s_agg, buf);
+    if (RUN) {
+        float z1 = e0, z2 = e1;
+#pragma unroll
+        for (int r = 0; r < LC; ++r) {
+            v[r] += z1;
+            const float n1 = fmaf(-a1, z1, z2);
+            z2 = -a2 * z1;
+            z1 = n1;
+        }
+    }
+}
+
+// Phase-C form (known tile-entering state P): zero-state response, carry,
+// then the zero-input response of the chunk-entering state added in place;
+// with CAP the state after sample r_cap is returned in (c1, c2).
+template <int LC, bool CAP>
+__device__ __forceinline__ void casc_section_c(const SecLdsC &tb, float (&v)[LC], int lane, int gw, float P0,
+                                               float P1, double (*s_agg)[GWAVES][2], int buf, int r_cap, float &c1,
+                                               float &c2) {
+    const float b0 = tb.coef[0], b1 = tb.coef[1], b2 = tb.coef[2], a1 = tb.coef[3], a2 = tb.coef[4];
+    float s1 = 0.f, s2 = 0.f;
+#pragma unroll
+    for (int r = 0; r < LC; ++r) {
+        const float xv = v[r];
+        const float yv = fmaf(b0, xv, s1);
+        s1 = fmaf(b1, xv, fmaf(-a1, yv, s2));
+        s2 = fmaf(b2, xv, -a2 * yv);
+        v[r] = yv;
+        if (CAP && r == r_cap) {
+            c1 = s1;
+            c2 = s2;
+        }
+    }
+    float z1, z2, E0, E1;
+    carry_local<float, SecLdsC>(tb, lane, gw, s1, s2, P0, P1, z1, z2, E0, E1, s_agg, buf);
+#pragma unroll
+    for (int r = 0; r < LC; ++r) {
+        v[r] += z1;
+        const float n1 = fmaf(-a1, z1, z2);
+        z2 = -a2 * z1;
+        z1 = n1;
+        if (CAP && r == r_cap) {  // state after the sample = zero-state + zero-input states
+            c1 += z1;
+            c2 += z2;
+        }
+    }
+}
+
 // Decoupled look-back over the whole cascade state (D = 2S <= 16 components,
 // section s at components 2s, 2s+1), by one wave.  Lanes form 4 rows of 16:
 // row r watches predecessor pos-1-r, lane c of a row component c.  Every
