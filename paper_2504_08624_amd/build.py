@@ -3,7 +3,10 @@
     python -m paper_2504_08624_amd.build
 
 Every HIP source is compiled for gfx950 only, with packed-FP32 instruction
-selection disabled (``-target-feature -packed-fp32-ops``), then linked into
+selection disabled (``-target-feature -packed-fp32-ops``) and matrix-core
+accumulators in ordinary vector registers (``-amdgpu-mfma-vgpr-form``: the
+fused Toeplitz FIR's accumulators then share registers with the cascade's
+working set instead of adding accumulator registers), then linked into
 ``paper_2504_08624_amd/libtfx.so`` next to this file.
 """
 from __future__ import annotations
@@ -23,6 +26,7 @@ LIB = os.path.join(HERE, "libtfx.so")
 ARCH = "gfx950"
 HIP_FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+             "-mllvm", "-amdgpu-mfma-vgpr-form=1",
              "-Wno-unused-command-line-argument"]
 CXX_FLAGS = ["-x", "c++", "-O2", "-std=c++17", "-fPIC", "-I", "/opt/rocm/include"]
 

@@ -53,6 +53,11 @@ namespace tfx {
 constexpr int DIRECT_GROUP_FLOATS = ((T + KBLK_MAX + L - 1) / L + 1) * CSTRIDE;
 // kernel variant of FIR_FFT for filters of more than one tap partition
 constexpr int FIR_FFT_PARTS = 4;
+// Kernel-internal FIR mode: the matrix-core (block-Toeplitz) FIR fused into the
+// chain kernel, bf16 or fp16 operands.
+constexpr int FIR_TZ_BF16 = 5, FIR_TZ_F16 = 6;
+template <int FIRM>
+constexpr bool is_tz() { return FIRM == FIR_TZ_BF16 || FIRM == FIR_TZ_F16; }
 
 template <int FIRM>
 constexpr bool is_fft() { return FIRM == FIR_FFT || FIRM == FIR_FFT_PARTS; }
@@ -94,7 +99,116 @@ struct KArgs {
     const float2 *hspec;  // [nparts][4096] spectra of the tap partitions / 4096
     int32_t nparts;
     const CascTab *casc;  // cascade tile-transition powers (cascade-level look-back)
+    const void *tzb;      // fused Toeplitz FIR: B operand table [2 Q][64][8]
+    int32_t tzQ;          // its frame lags Q
 };
+
+// Fused matrix-core FIR of a tile (both channels of the pair), written into
+// the two staging areas.  With frames of TP = 32 samples,
+//     y[32 b + i] = sum_{q, m} x[32 (b - q) + m] h[32 q + i - m],
+// a (frames x 32 Q) by (32 Q x 32) product per channel whose tap operand B is
+// the prepared table of the stand-alone Toeplitz kernel.  The tile is 96
+// frames per channel, three 32-frame accumulator tiles, six for the pair;
+// wave w takes tiles w and w + 4.  The signal operand A (frames converted to
+// bf16 / fp16) is staged in the staging areas TZ_QC lags at a time: frames
+// F0 - (q1 - 1) .. F0 + 95 of each channel, where tile u's row for lag q and
+// frame F0 + 32 t + r is 32 t + r + q1 - 1 - q.
+constexpr int TZ_QC = 64;
+constexpr int TZ_PF = 4;  // tap-fragment loads in flight
+constexpr int TZ_ROWS = T / TP + TZ_QC - 1;
+static_assert(GROUPS * TZ_ROWS * TROW * 2 <= GROUPS * STG_FLOATS * 4, "Toeplitz operands must fit in the staging");
+template <int MODE>
+__device__ void tz_tile(const KArgs &a, float *lds, int64_t pair, int64_t n0, int tid) {
+    typedef Op<MODE> O;
+    typedef typename O::T Tt;
+    typedef typename O::V V;
+    typedef Tt T4 __attribute__((ext_vector_type(4)));
+    Tt *ast = reinterpret_cast<Tt *>(lds);  // [GROUPS][TZ_ROWS][TROW]
+    const int lane = tid & 63, w = tid >> 6, r32 = lane & 31, kh = lane >> 5;
+    const int ntl = w < 2 ? 2 : 1;  // tiles of this wave: w, w + 4
+    const int64_t F0 = n0 / TP;
+    const V *bt = static_cast<const V *>(a.tzb);
+    f32x16 acc[2];
+#pragma unroll
+    for (int k = 0; k < 2; ++k)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[k][r] = 0.f;
+    for (int q0 = 0; q0 < a.tzQ; q0 += TZ_QC) {
+        const int q1 = min(a.tzQ, q0 + TZ_QC);
+        const int nrows = T / TP + (q1 - q0) - 1;
+        const int64_t fbase = F0 - (q1 - 1);
+        __syncthreads();  // the previous pass's operand reads
+#pragma unroll
+        for (int g = 0; g < GROUPS; ++g) {
+            const int64_t ch = 2 * pair + g;
+            const float *xc = a.x + ch * a.ldx;
+            Tt *ag = ast + g * TZ_ROWS * TROW;
+            for (int e = tid; e < nrows * (TP / 4); e += WG) {
+                const int row = e >> 3, c4 = e & 7;  // TP / 4 = 8 four-sample pieces a row
+                const int64_t n = (fbase + row) * TP + 4 * c4;
+                float v4[4];
+                if (ch < a.C && a.vec && n >= 0 && n + 3 < a.N) {
+                    const float4 t = *reinterpret_cast<const float4 *>(xc + n);
+                    v4[0] = t.x;
+                    v4[1] = t.y;
+                    v4[2] = t.z;
+                    v4[3] = t.w;
+                } else {
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) v4[u] = (ch < a.C && n + u >= 0 && n + u < a.N) ? xc[n + u] : 0.f;
+                }
+                T4 t4;
+#pragma unroll
+                for (int u = 0; u < 4; ++u) t4[u] = (Tt)v4[u];
+                *reinterpret_cast<T4 *>(&ag[row * TROW + 4 * c4]) = t4;
+            }
+        }
+        __syncthreads();
+        // steps st = 2 q + hh; tap fragments are loaded TZ_PF steps ahead
+        const int s0 = 2 * q0, s1 = 2 * q1;
+        V bq[TZ_PF];
+#pragma unroll
+        for (int i = 0; i < TZ_PF; ++i)
+            if (s0 + i < s1) bq[i] = bt[(int64_t)(s0 + i) * 64 + lane];
+        for (int sb = s0; sb < s1; sb += TZ_PF) {
+#pragma unroll
+            for (int i = 0; i < TZ_PF; ++i) {
+                const int st = sb + i;
+                if (st < s1) {
+                    const int q = st >> 1, hh = st & 1;
+#pragma unroll
+                    for (int k = 0; k < 2; ++k) {
+                        if (k < ntl) {
+                            const int u = w + 4 * k, g = u / 3, t = u % 3;
+                            const int row = 32 * t + r32 + (q1 - 1 - q);
+                            const V av =
+                                *reinterpret_cast<const V *>(&ast[(g * TZ_ROWS + row) * TROW + 16 * hh + 8 * kh]);
+                            acc[k] = O::mma(av, bq[i], acc[k]);
+                        }
+                    }
+                    // the fragment's last use is issued: refill its slot in place
+                    if (st + TZ_PF < s1) bq[i] = bt[(int64_t)(st + TZ_PF) * 64 + lane];
+                }
+            }
+        }
+    }
+    __syncthreads();  // every operand read done: the staging areas take the output
+    // accumulator (row i, column c): lane c + 32 (i / 4 % 2), register
+    // 4 (i / 8) + i % 4; output sample 32 (32 t + i) + c of the channel's tile
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        if (k < ntl) {
+            const int u = w + 4 * k, g = u / 3, t = u % 3;
+            float *st = lds + g * STG_FLOATS;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int i = 8 * (r >> 2) + 4 * kh + (r & 3);
+                st[cphys(32 * (32 * t + i) + r32)] = acc[k][r];
+            }
+        }
+    }
+    __syncthreads();
+}
 
 // Overlap-save block of the pair.  Convolution: the block starts 1024 samples
 // before the tile and outputs c[256 a + t], a = 4..15, are the tile.
@@ -306,6 +420,9 @@ __global__ __launch_bounds__(WG) void chain_kernel(KArgs a) {
     if (FIRM == FIR_NONE) {
         stage_tile(stg, a.x + c.ch * a.ldx + n0, a.N - n0, c.valid, a.vec != 0, c.gl);
         __syncthreads();
+        load_chunk(stg, c.gl, v);
+    } else if constexpr (is_tz<FIRM>()) {
+        tz_tile<FIRM == FIR_TZ_BF16 ? TZ_BF16 : TZ_F16>(a, lds, pair, n0, c.tid);
         load_chunk(stg, c.gl, v);
     } else if (FIRM == FIR_DIRECT) {
         const float *xc = a.x + c.ch * a.ldx;
@@ -591,7 +708,11 @@ hipError_t launch_run(const ChainPlan &p) {
     k.N = p.N;
     k.ldx = p.ldx;
     k.ldy = p.ldy;
-    if (Mtot > 0 && p.fir_mode == FIR_TOEPLITZ) {
+    // matrix-core FIR with a cascade behind it, bf16 or fp16 operands: fused
+    // into the chain kernel (the split-bf16 form and a FIR alone run the
+    // stand-alone Toeplitz kernel)
+    const bool tz_fused = Mtot > 0 && p.fir_mode == FIR_TOEPLITZ && p.S > 0 && (p.cmp == TZ_BF16 || p.cmp == TZ_F16);
+    if (Mtot > 0 && p.fir_mode == FIR_TOEPLITZ && !tz_fused) {
         // matrix-core FIR into y, then the cascade in place over y (each
         // tile reads only the samples it writes)
         hipError_t e = launch_toeplitz(p.x, p.y, p.C, p.N, p.ldx, p.ldy, Mtot, p.cmp, ws + lay.ttab, p.stream);
@@ -624,6 +745,12 @@ hipError_t launch_run(const ChainPlan &p) {
     k.casc = reinterpret_cast<const CascTab *>(ws + lay.casc);
     const int64_t nblocks = (lay.cpad / 2) * lay.ntiles;
     const bool s = p.S > 0;
+    if (tz_fused) {
+        k.tzb = ws + lay.ttab;
+        k.tzQ = toeplitz_lags(Mtot);
+        return p.cmp == TZ_BF16 ? launch_main<FIR_TZ_BF16, true>(k, nblocks, p.stream)
+                                : launch_main<FIR_TZ_F16, true>(k, nblocks, p.stream);
+    }
     switch (Mtot > 0 ? p.fir_mode : FIR_NONE) {
         case FIR_DIRECT: return s ? launch_main<FIR_DIRECT, true>(k, nblocks, p.stream)
                                   : launch_main<FIR_DIRECT, false>(k, nblocks, p.stream);

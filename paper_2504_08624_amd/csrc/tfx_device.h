@@ -123,6 +123,36 @@ __device__ __forceinline__ void stage_tables(SL *dst, const SecTab *src, int s0,
     }
 }
 
+// ------------------------------------------------------------ matrix cores
+// Operand types of the 32 x 32 x 16 matrix-core products of the Toeplitz FIR
+// (frames of TP = 32 samples; a staged frame row holds 32 operands and 8 of
+// padding, 2-byte units).
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+constexpr int TP = 32;        // frame length = output columns
+constexpr int TROW = TP + 8;  // staged frame row (2-byte units)
+
+// Compute modes of the matrix-core FIR (tfx_compute values).
+enum { TZ_BF16 = 1, TZ_F16 = 2, TZ_BF16X3 = 3 };
+
+template <int MODE> struct Op;
+template <> struct Op<TZ_BF16> {
+    typedef __bf16 T;
+    typedef bf16x8 V;
+    static __device__ __forceinline__ f32x16 mma(V a, V b, f32x16 c) {
+        return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+    }
+};
+template <> struct Op<TZ_F16> {
+    typedef _Float16 T;
+    typedef f16x8 V;
+    static __device__ __forceinline__ f32x16 mma(V a, V b, f32x16 c) {
+        return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
+    }
+};
+template <> struct Op<TZ_BF16X3> : Op<TZ_BF16> {};
+
 // ------------------------------------------------------------------ staging
 // LDS layout of lane chunks of LC samples: LC samples then 4 floats of
 // padding, so a lane's chunk starts 16 LC + 16 bytes after its neighbour's

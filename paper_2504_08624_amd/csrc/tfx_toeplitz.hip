@@ -23,41 +23,15 @@
 // each) and reuses each B fragment for all four.
 #include <hip/hip_runtime.h>
 
-#include "tfx_internal.h"
+#include "tfx_device.h"
 
 namespace tfx {
 
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
-typedef float f32x16 __attribute__((ext_vector_type(16)));
-
-constexpr int TP = 32;                      // frame length = output columns
 constexpr int TFB = 4;                      // accumulator tiles per wave
 constexpr int TWAVES = 4;                   // waves per workgroup
 constexpr int TFRAMES = TFB * 32 * TWAVES;  // frames per workgroup tile (512)
 constexpr int TQC = 192;                    // lags per LDS stage
-constexpr int TROW = TP + 8;                // LDS row: 32 operands + 8 of padding (2-byte units)
 constexpr int TROWS = TFRAMES + TQC;        // staged frames per stage
-
-// Compute modes handled here (tfx_compute values).
-enum { TZ_BF16 = 1, TZ_F16 = 2, TZ_BF16X3 = 3 };
-
-template <int MODE> struct Op;
-template <> struct Op<TZ_BF16> {
-    typedef __bf16 T;
-    typedef bf16x8 V;
-    static __device__ __forceinline__ f32x16 mma(V a, V b, f32x16 c) {
-        return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
-    }
-};
-template <> struct Op<TZ_F16> {
-    typedef _Float16 T;
-    typedef f16x8 V;
-    static __device__ __forceinline__ f32x16 mma(V a, V b, f32x16 c) {
-        return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
-    }
-};
-template <> struct Op<TZ_BF16X3> : Op<TZ_BF16> {};
 
 // B operand table: step s = 2 q + hh, lane l, element v holds
 // h[32 q + (l % 32) - 16 hh - 8 (l / 32) - v]  (0 outside [0, M)),

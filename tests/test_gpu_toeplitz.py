@@ -20,6 +20,7 @@ DEV = "cuda:0"
 T = 3072
 TOL_SPLIT = 1e-4
 TOL = {"bf16": TOL_FIR_LOWP, "f16": TOL_FIR_LOWP, "bf16x3": TOL_SPLIT}
+TOL_SAME = 1e-5  # same arithmetic up to the look-back's combination order
 
 
 def _x(C, N, key, sigma=0.1):
@@ -92,6 +93,59 @@ def test_chain_with_matrix_core_fir(compute):
     st = [(k, _gpu(c)) for k, c in w.stages]
     y = _cpu(tfx.chain(_gpu(w.x), st, compute=compute))
     assert_close(y, O.chain(w.x, w.stages), TOL[compute], "chain_mid %s" % compute)
+
+
+def _sections(S, key, r_lo=0.5, r_hi=0.99):
+    rng = np.random.default_rng(list(key))
+    rows = []
+    for _ in range(S):
+        r, th = rng.uniform(r_lo, r_hi), rng.uniform(0.05, 3.0)
+        z = rng.uniform(0.3, 1.2)
+        rows.append([1.0, -2 * z * np.cos(th * 0.7), z * z, -2 * r * np.cos(th), r * r])
+    return np.asarray(rows, np.float32)
+
+
+@pytest.mark.parametrize("compute", ["bf16", "f16"])
+@pytest.mark.parametrize("M", [1, 33, 1023, 2100])
+@pytest.mark.parametrize("C,N,S", [(1, 1, 2), (2, 100, 3), (3, 5 * T + 11, 6), (2, 2 * T + 5, 10)])
+def test_chain_fused_matrix_core_fir_matches_two_passes(compute, M, C, N, S):
+    """With a cascade behind it, the bf16 / fp16 matrix-core FIR runs inside
+    the chain kernel; its output must match the stand-alone matrix-core FIR
+    followed by the fp32 cascade (the same products in the same order and the
+    same cascade code; only the decoupled look-back, which combines a
+    predecessor's aggregate or its inclusive prefix depending on which is
+    out first, may round differently), and the oracle at the bf16/fp16 bar.
+    M = 2100 needs two operand passes (65 lags); S = 10 takes the per-section
+    look-back."""
+    print("fused tz chain %s M=%d C=%d N=%d S=%d" % (compute, M, C, N, S), flush=True)
+    x = _x(C, N, (410, M, C, N))
+    # random taps: no near-zero leading tap, so even N = 1 has a meaningful output
+    h = (np.random.default_rng(M + 23).standard_normal(M) / np.sqrt(M)).astype(np.float32)
+    sec = _sections(S, (411, M, S))
+    xg, hg, sg = _gpu(x), _gpu(h), _gpu(sec)
+    y, ck = tfx.chain(xg, [("fir", hg), ("sos", sg)], compute=compute, return_ckpt=True)
+    f = tfx.fir(xg, hg, compute=compute)
+    y2, ck2 = tfx.sos(f, sg, return_ckpt=True)
+    assert_close(_cpu(y), _cpu(y2).astype(np.float64), TOL_SAME, "fused vs two passes")
+    assert_close(_cpu(ck).reshape(C, -1), _cpu(ck2).reshape(C, -1).astype(np.float64), TOL_SAME, "checkpoints")
+    ref = O.chain(x, [("fir", h), ("sos", sec)])
+    assert_close(_cpu(y), ref, TOL[compute], "fused chain %s M=%d" % (compute, M))
+
+
+def test_chain_fused_matrix_core_fir_high_q_and_strided():
+    """A section with pole radius above 0.999 (the FP64-carry kernel variant)
+    and rows with a stride (no 16-byte alignment) through the fused path."""
+    C, N = 3, 4 * T + 7
+    x = _x(C, N + 3, (412,))
+    h = design.fir_lowpass(255, 5000.0, 48000.0).astype(np.float32)
+    sec = np.concatenate([_sections(2, (413,)), np.array([[1.0, 0.0, -1.0, -2 * 0.9995 * np.cos(0.01), 0.9995 ** 2]],
+                                                           np.float32)])
+    xb = _gpu(x)
+    xs = xb[:, 1:N + 1]
+    y = tfx.chain(xs, [("fir", _gpu(h)), ("sos", _gpu(sec))], compute="bf16")
+    y2 = tfx.sos(tfx.fir(xs, _gpu(h), compute="bf16"), _gpu(sec))
+    assert_close(_cpu(y), _cpu(y2).astype(np.float64), TOL_SAME, "fused vs two passes, high-Q")
+    assert_close(_cpu(y), O.chain(x[:, 1:N + 1], [("fir", h), ("sos", sec)]), TOL_FIR_LOWP, "fused high-Q")
 
 
 def test_low_precision_rejects_fp32_only_algorithms():
