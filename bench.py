@@ -184,6 +184,29 @@ def secondary(torch, dev, stream):
     s = timed(torch, step, 10, stream)
     out["learnable"] = {"workload": "64 x 192,000, 255-tap FIR + 8 SOS, MSE loss, grads of taps and sections",
                         "fwd_bwd_ms": round(s * 1e3, 3), "Msamples_per_s": round(x.numel() / s / 1e6, 1)}
+    del x, hh, sec, tgt
+
+    log("wave pipe")
+    w = workloads.chain_mid()
+    x = torch.from_numpy(w.x).to(dev)
+    fs = [tfx.WindowedSincFIR(300.0, num_taps=1023, cutoff_hi=6000.0), tfx.HiShelving(1000.0), tfx.LoShelving(2000.0),
+          tfx.Peaking(3000.0, q=2.0, gain_db=-3.0)]
+
+    def piped():
+        wv = tfx.Wave(x, 48000.0)
+        for f in fs:
+            wv = wv | f
+        return wv.y
+    yp = piped()
+    st = [f.stage(x.device) for f in fs]
+    s_p = timed(torch, piped, 10, stream)
+    s_c = timed(torch, lambda: tfx.chain(x, st), 10, stream)
+    ref = O.chain(w.x[:2], [(f.kind, f.coefficients("cpu").numpy()) for f in fs])
+    out["wave_pipe"] = {"workload": "8 x 5,760,000 @48 kHz: Wave | WindowedSincFIR(1023) | HiShelving | LoShelving "
+                                    "| Peaking (one fused launch)",
+                        "Msamples_per_s": round(x.numel() / s_p / 1e6, 1), "ms": round(s_p * 1e3, 4),
+                        "direct_chain_ms": round(s_c * 1e3, 4),
+                        "rel_err_2ch": rel_err(yp[:2].cpu().numpy(), ref), "tolerance": 1e-4}
     return out
 
 
