@@ -207,6 +207,33 @@ def secondary(torch, dev, stream):
                         "Msamples_per_s": round(x.numel() / s_p / 1e6, 1), "ms": round(s_p * 1e3, 4),
                         "direct_chain_ms": round(s_c * 1e3, 4),
                         "rel_err_2ch": rel_err(yp[:2].cpu().numpy(), ref), "tolerance": 1e-4}
+    del x, yp
+
+    log("stream")
+    w = workloads.chain_mid(C=8, N=48000)
+    x = torch.from_numpy(w.x).to(dev)
+    st = [(k, torch.from_numpy(c).to(dev)) for k, c in w.stages]
+    res = {"workload": "8 ch @48 kHz, chain_mid's filters (1023-tap FIR | 6 SOS), blocks carried by tfx_chain_stream"}
+    for blk in (512, 4096):
+        sm = tfx.ChainStream(st, 8, blk)
+        nb = x.shape[1] // blk
+        blocks = [x[:, i * blk:(i + 1) * blk].contiguous() for i in range(nb)]
+        ys = [sm.process(b) for b in blocks]
+        y = torch.cat(ys, dim=1).cpu().numpy()
+        sm.reset()
+        it = iter(range(10 ** 9))
+
+        def one():
+            i = next(it) % nb
+            if i == 0:
+                sm.reset()
+            sm.process(blocks[i])
+        s = timed(torch, one, 200, stream)
+        res["block_%d" % blk] = {"us_per_block": round(s * 1e6, 1), "Msamples_per_s": round(8 * blk / s / 1e6, 1),
+                                 "realtime_factor": round(blk / 48000.0 / s, 1),
+                                 "rel_err_vs_oracle": rel_err(y, O.chain(w.x[:, :nb * blk], w.stages)),
+                                 "tolerance": 1e-4}
+    out["stream"] = res
     return out
 
 

@@ -167,6 +167,31 @@ tfx_status tfx_chain_run(const float *x, float *y, int64_t C, int64_t N, int64_t
                          const tfx_stage *stages, int32_t nstages, tfx_compute cmp, float *ckpt,
                          void *ws, size_t ws_bytes, void *stream);
 
+/* Streaming (block-by-block) form of tfx_chain (the real-time block
+ * processing the paper's Sec. 5 names on its roadmap): y is the chain applied
+ * to the block x[C][N] as the continuation of everything filtered before it.
+ * The workspace is prepared once with tfx_chain_prepare(C, n_max, ...) for
+ * the longest block; every block is then one call (one filter launch, plus a
+ * small copy kernel for the history), N <= n_max, any N >= 0.
+ *   hist_in   FIR history: the M - 1 inputs just before the block, [C][M - 1]
+ *             row-major (M = the merged tap count); NULL = zeros (start of
+ *             the stream).  Ignored without FIR stages or when M == 1.
+ *   hist_out  receives the last M - 1 inputs up to the block's end (for the
+ *             next call); NULL = not written.  Must not overlap hist_in, x
+ *             or y.
+ *   state_in  the cascade's TDF-II registers before the block, [C][S][2]
+ *             (as for tfx_sos); NULL = zero.
+ *   state_out receives them after the block's last sample; NULL = not
+ *             written.  Must not overlap state_in, x or y.
+ * Same stage and precision rules as tfx_chain (the bf16/fp16 matrix-core FIR
+ * also takes its history); the coefficients must not change between the
+ * prepare and the runs.  TFX_E_INVALID_ARG if N > n_max; TFX_E_WORKSPACE if
+ * ws is smaller than the size for (C, n_max); TFX_E_ALIAS as listed. */
+tfx_status tfx_chain_stream(const float *x, float *y, int64_t C, int64_t N, int64_t ldx, int64_t ldy,
+                            const tfx_stage *stages, int32_t nstages, tfx_compute cmp, int64_t n_max,
+                            const float *hist_in, float *hist_out, const float *state_in, float *state_out,
+                            void *ws, size_t ws_bytes, void *stream);
+
 /* ------------------------------------------------------- batched clips */
 
 /* One clip of a ragged batch: its own channel count C, length N, strides and

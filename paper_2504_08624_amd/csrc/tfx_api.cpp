@@ -427,6 +427,41 @@ tfx_status tfx_chain_run(const float *x, float *y, int64_t C, int64_t N, int64_t
     return execute(p);
 }
 
+tfx_status tfx_chain_stream(const float *x, float *y, int64_t C, int64_t N, int64_t ldx, int64_t ldy,
+                            const tfx_stage *stages, int32_t nstages, tfx_compute cmp, int64_t n_max,
+                            const float *hist_in, float *hist_out, const float *state_in, float *state_out,
+                            void *ws, size_t ws_bytes, void *stream) {
+    tfx_status s = check_signal(x, y, C, N, ldx, ldy);
+    if (s) return s;
+    if (N > n_max) return fail(TFX_E_INVALID_ARG, "the block (%lld samples) is longer than n_max (%lld)",
+                                (long long)N, (long long)n_max);
+    tfx::ChainPlan p{};
+    if ((s = chain_plan(C, n_max, stages, nstages, cmp, ws, ws_bytes, stream, p))) return s;
+    const int32_t M = tfx::merged_taps(p.firs);
+    const size_t hb = M > 1 ? (size_t)C * (size_t)(M - 1) * sizeof(float) : 0;
+    const size_t sb = (size_t)C * (size_t)p.S * 2 * sizeof(float);
+    if (hb && hist_out) {
+        if (overlaps(hist_out, hb, hist_in, hist_in ? hb : 0) || overlaps(hist_out, hb, x, span_bytes(C, N, ldx)) ||
+            overlaps(hist_out, hb, y, span_bytes(C, N, ldy)))
+            return fail(TFX_E_ALIAS, "hist_out overlaps hist_in or a signal");
+    }
+    if (hb && hist_in && overlaps(hist_in, hb, y, span_bytes(C, N, ldy)))
+        return fail(TFX_E_ALIAS, "hist_in overlaps y");
+    if (sb && state_out) {
+        if (overlaps(state_out, sb, state_in, state_in ? sb : 0) || overlaps(state_out, sb, x, span_bytes(C, N, ldx)) ||
+            overlaps(state_out, sb, y, span_bytes(C, N, ldy)))
+            return fail(TFX_E_ALIAS, "state_out overlaps state_in or a signal");
+    }
+    p.N = N;
+    p.n_layout = n_max;
+    p.x = x; p.y = y; p.ldx = ldx; p.ldy = ldy;
+    p.hist_in = hb ? hist_in : nullptr;
+    p.hist_out = hb ? hist_out : nullptr;
+    p.state_in = p.S > 0 ? state_in : nullptr;
+    p.state_out = p.S > 0 ? state_out : nullptr;
+    return execute(p);
+}
+
 tfx_status tfx_chain_backward_workspace_size(int64_t C, int64_t N, const tfx_stage *stages, int32_t nstages,
                                              tfx_compute cmp, size_t *bytes) {
     if (!bytes) return fail(TFX_E_INVALID_ARG, "bytes is NULL");

@@ -101,7 +101,16 @@ struct KArgs {
     const CascTab *casc;  // cascade tile-transition powers (cascade-level look-back)
     const void *tzb;      // fused Toeplitz FIR: B operand table [2 Q][64][8]
     int32_t tzQ;          // its frame lags Q
+    const float *hist;    // streaming: the M - 1 FIR inputs before the block, [C][M - 1] (null = zeros)
+    int64_t ldh;          // M - 1
 };
+
+// FIR input x[ch][n] of the block, n < N, with the streaming history for
+// n in [-(M - 1), 0) and zeros before it.
+__device__ __forceinline__ float fir_input(const KArgs &a, const float *xc, int64_t ch, int64_t n) {
+    if (n >= 0) return n < a.N ? xc[n] : 0.f;
+    return (a.hist && n >= -a.ldh) ? a.hist[ch * a.ldh + a.ldh + n] : 0.f;
+}
 
 // Fused matrix-core FIR of a tile (both channels of the pair), written into
 // the two staging areas.  With frames of TP = 32 samples,
@@ -155,7 +164,7 @@ __device__ void tz_tile(const KArgs &a, float *lds, int64_t pair, int64_t n0, in
                     v4[3] = t.w;
                 } else {
 #pragma unroll
-                    for (int u = 0; u < 4; ++u) v4[u] = (ch < a.C && n + u >= 0 && n + u < a.N) ? xc[n + u] : 0.f;
+                    for (int u = 0; u < 4; ++u) v4[u] = ch < a.C ? fir_input(a, xc, ch, n + u) : 0.f;
                 }
                 T4 t4;
 #pragma unroll
@@ -224,9 +233,12 @@ __device__ void fft_block(const KArgs &a, float *lds, int64_t pair, int64_t n0, 
     const int64_t chA = 2 * pair, chB = 2 * pair + 1;
     const float *xA = a.x + chA * a.ldx;
     const float *xB = chB < a.C ? a.x + chB * a.ldx : nullptr;
+    const float *hA = a.hist ? a.hist + chA * a.ldh : nullptr;
+    const float *hB = (a.hist && chB < a.C) ? a.hist + chB * a.ldh : nullptr;
+    const int64_t hlen = a.hist ? a.ldh : 0;
     const int64_t base = a.correlate ? n0 : n0 - FFT_DISCARD;
     if (!PARTS) {
-        load_pair_block(zr, zi, xA, xB, base, a.N, a.N, tid);
+        load_pair_block(zr, zi, xA, xB, base, a.N, a.N, tid, hA, hB, hlen);
         fft4096_forward(zr, zi, lds, a.twid, tid);
         spectrum_product(zr, zi, a.hspec, tid, a.correlate != 0);
     } else {
@@ -237,7 +249,7 @@ __device__ void fft_block(const KArgs &a, float *lds, int64_t pair, int64_t n0, 
         for (int p = 0; p < a.nparts; ++p) {
             const int64_t shift = (int64_t)FFT_PART * p;
             __syncthreads();  // the previous pass's last LDS reads
-            load_pair_block(zr, zi, xA, xB, a.correlate ? base + shift : base - shift, a.N, a.N, tid);
+            load_pair_block(zr, zi, xA, xB, a.correlate ? base + shift : base - shift, a.N, a.N, tid, hA, hB, hlen);
             fft4096_forward(zr, zi, lds, a.twid, tid);
             const float2 *hs = a.hspec + (int64_t)p * NFFT;
             const float sg = a.correlate ? -1.f : 1.f;
@@ -441,7 +453,7 @@ __global__ __launch_bounds__(WG) void chain_kernel(KArgs a) {
                 for (int u = 0; u < 8; ++u) {
                     const int i = i0 + c.gl + GL * u;
                     const int64_t n = src0 + i;
-                    t8[u] = (c.valid && i < T + a.KBL && n >= 0 && n < a.N) ? xc[n] : 0.f;
+                    t8[u] = (c.valid && i < T + a.KBL) ? fir_input(a, xc, c.ch, n) : 0.f;
                 }
 #pragma unroll
                 for (int u = 0; u < 8; ++u) {
@@ -693,9 +705,27 @@ hipError_t launch_prepare(const ChainPlan &p) {
     return launch_toeplitz_prepare(taps_ptr(p, lay), Mtot, p.cmp, static_cast<char *>(p.ws) + lay.ttab, p.stream);
 }
 
+// Streaming: hist_out[c][j] = the input M - 1 - j samples before the
+// block's end (from the block, then from hist_in, then zeros).
+__global__ void hist_update_kernel(const float *x, int64_t ldx, const float *hin, float *hout, int64_t C, int64_t N,
+                                   int64_t H) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= C * H) return;
+    const int64_t c = e / H, j = e % H;
+    const int64_t n = N - H + j;
+    hout[e] = n >= 0 ? x[c * ldx + n] : (hin ? hin[c * H + H + n] : 0.f);
+}
+
 hipError_t launch_run(const ChainPlan &p) {
     int32_t Mtot = merged_taps(p.firs);
-    const WsLayout lay = ws_layout(p.C, p.N, p.S, Mtot, p.firs.n, p.fir_mode);
+    const WsLayout lay = ws_layout(p.C, p.n_layout ? p.n_layout : p.N, p.S, Mtot, p.firs.n, p.fir_mode);
+    if (p.hist_out && Mtot > 1) {  // stream-ordered before the filter, which reads hist_in only
+        const int64_t n = p.C * (int64_t)(Mtot - 1);
+        hipLaunchKernelGGL(hist_update_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, p.stream, p.x, p.ldx,
+                           p.hist_in, p.hist_out, p.C, p.N, (int64_t)(Mtot - 1));
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
     char *ws = static_cast<char *>(p.ws);
     if (p.N == 0) {
         if (p.state_out && p.S > 0) return launch_state_passthrough(p.state_in, p.state_out, p.C * p.S * 2, p.stream);
@@ -715,7 +745,8 @@ hipError_t launch_run(const ChainPlan &p) {
     if (Mtot > 0 && p.fir_mode == FIR_TOEPLITZ && !tz_fused) {
         // matrix-core FIR into y, then the cascade in place over y (each
         // tile reads only the samples it writes)
-        hipError_t e = launch_toeplitz(p.x, p.y, p.C, p.N, p.ldx, p.ldy, Mtot, p.cmp, ws + lay.ttab, p.stream);
+        hipError_t e = launch_toeplitz(p.x, p.y, p.C, p.N, p.ldx, p.ldy, Mtot, p.cmp, ws + lay.ttab, p.stream,
+                                       p.hist_in);
         if (e != hipSuccess || p.S == 0) return e;
         k.x = p.y;
         k.ldx = p.ldy;
@@ -732,7 +763,7 @@ hipError_t launch_run(const ChainPlan &p) {
     k.state_in = p.state_in;
     k.state_out = p.state_out;
     k.ckpt = p.ckpt;
-    k.ntiles = lay.ntiles;
+    k.ntiles = (p.N + T - 1) / T;  // the block's tiles (streaming: the layout may be for a longer block)
     k.cpad = lay.cpad;
     k.hdr = reinterpret_cast<uint32_t *>(ws + lay.hdr);
     k.tab = reinterpret_cast<const SecTab *>(ws + lay.tab);
@@ -743,7 +774,9 @@ hipError_t launch_run(const ChainPlan &p) {
     k.hspec = reinterpret_cast<const float2 *>(ws + lay.hspec);
     k.nparts = fft_parts(Mtot);
     k.casc = reinterpret_cast<const CascTab *>(ws + lay.casc);
-    const int64_t nblocks = (lay.cpad / 2) * lay.ntiles;
+    k.hist = Mtot > 1 ? p.hist_in : nullptr;
+    k.ldh = Mtot > 1 ? Mtot - 1 : 0;
+    const int64_t nblocks = (lay.cpad / 2) * k.ntiles;
     const bool s = p.S > 0;
     if (tz_fused) {
         k.tzb = ws + lay.ttab;

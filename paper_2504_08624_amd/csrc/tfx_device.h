@@ -452,9 +452,13 @@ __device__ __forceinline__ void spectrum_product(float (&zr)[16], float (&zi)[16
 
 // Loads the complex block z[m] = xa[base + m] + i xb[base + m], m = 256 q + tid
 // (zeros outside [0, N) and past limit; xb may be null) into the forward FFT
-// input layout.  A block wholly inside takes no per-element checks.
+// input layout.  With a history (streaming: the hlen samples before the
+// block, ha / hb, hb may be null) the samples at n in [-hlen, 0) come from
+// ha[hlen + n].  A block wholly inside takes no per-element checks.
 __device__ __forceinline__ void load_pair_block(float (&zr)[16], float (&zi)[16], const float *xa, const float *xb,
-                                                int64_t base, int64_t N, int64_t limit, int tid) {
+                                                int64_t base, int64_t N, int64_t limit, int tid,
+                                                const float *ha = nullptr, const float *hb = nullptr,
+                                                int64_t hlen = 0) {
     const int64_t hi = N < limit ? N : limit;
     if (base >= 0 && base + NFFT <= hi) {
         const float *pa = xa + base + tid;
@@ -474,8 +478,9 @@ __device__ __forceinline__ void load_pair_block(float (&zr)[16], float (&zi)[16]
     for (int q = 0; q < 16; ++q) {
         const int64_t n = base + 256 * q + tid;
         const bool in = n >= 0 && n < hi;
-        zr[q] = in ? xa[n] : 0.f;
-        zi[q] = (in && xb) ? xb[n] : 0.f;
+        const bool inh = n < 0 && n >= -hlen;
+        zr[q] = in ? xa[n] : (inh ? ha[hlen + n] : 0.f);
+        zi[q] = (in && xb) ? xb[n] : ((inh && hb) ? hb[hlen + n] : 0.f);
     }
 }
 

@@ -146,6 +146,9 @@ struct ChainPlan {
     const float *state_in;
     float *state_out;
     float *ckpt;
+    const float *hist_in;   // streaming: FIR inputs before the block, [C][M - 1] (null = zeros)
+    float *hist_out;        // streaming: receives the last M - 1 inputs up to the block's end
+    int64_t n_layout;       // block length the workspace layout was made for (0 = N)
     void *ws;
     size_t ws_bytes;
     hipStream_t stream;
@@ -177,7 +180,7 @@ int32_t toeplitz_lags(int32_t M);
 size_t toeplitz_table_bytes(int32_t M, int32_t cmp);
 hipError_t launch_toeplitz_prepare(const float *h, int32_t M, int32_t cmp, void *tab, hipStream_t st);
 hipError_t launch_toeplitz(const float *x, float *y, int64_t C, int64_t N, int64_t ldx, int64_t ldy, int32_t M,
-                           int32_t cmp, const void *tab, hipStream_t st);
+                           int32_t cmp, const void *tab, hipStream_t st, const float *hist = nullptr);
 
 // ---- batched ragged clips (tfx_batched.hip) -------------------------------------
 // Device descriptor of one clip, in processing order.  Blocks of the single

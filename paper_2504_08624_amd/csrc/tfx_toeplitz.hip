@@ -60,6 +60,8 @@ struct TzArgs {
     int64_t nft;          // frame tiles per channel
     const void *bhi, *blo;
     int32_t vec;          // x rows 16-byte aligned
+    const float *hist;    // streaming: the M - 1 inputs before the block, [C][M - 1] (null = zeros)
+    int64_t ldh;          // M - 1
 };
 
 // One workgroup: 512 consecutive frames (16384 outputs) of one channel.
@@ -104,7 +106,11 @@ __global__ __launch_bounds__(64 * TWAVES) void toeplitz_kernel(TzArgs a) {
                 v4[3] = t.w;
             } else {
 #pragma unroll
-                for (int u = 0; u < 4; ++u) v4[u] = (n + u >= 0 && n + u < a.N) ? xc[n + u] : 0.f;
+                for (int u = 0; u < 4; ++u) {
+                    const int64_t m = n + u;
+                    v4[u] = m >= 0 ? (m < a.N ? xc[m] : 0.f)
+                                   : ((a.hist && m >= -a.ldh) ? a.hist[ch * a.ldh + a.ldh + m] : 0.f);
+                }
             }
             T4 hi4, lo4;
 #pragma unroll
@@ -186,7 +192,7 @@ hipError_t launch_toeplitz_prepare(const float *h, int32_t M, int32_t cmp, void 
 }
 
 hipError_t launch_toeplitz(const float *x, float *y, int64_t C, int64_t N, int64_t ldx, int64_t ldy, int32_t M,
-                           int32_t cmp, const void *tab, hipStream_t st) {
+                           int32_t cmp, const void *tab, hipStream_t st, const float *hist) {
     if (N == 0) return hipSuccess;
     TzArgs a{};
     a.x = x;
@@ -202,6 +208,8 @@ hipError_t launch_toeplitz(const float *x, float *y, int64_t C, int64_t N, int64
     a.bhi = tab;
     a.blo = static_cast<const char *>(tab) + n * 2;
     a.vec = (reinterpret_cast<uintptr_t>(x) % 16 == 0 && ldx % 4 == 0) ? 1 : 0;
+    a.hist = M > 1 ? hist : nullptr;
+    a.ldh = M - 1;
     const dim3 grid((unsigned)(C * a.nft)), block(64 * TWAVES);
     switch (cmp) {
         case TZ_BF16: hipLaunchKernelGGL(toeplitz_kernel<TZ_BF16>, grid, block, 0, st, a); break;

@@ -209,6 +209,51 @@ def chain_backward(x: torch.Tensor, gy: torch.Tensor, stages, ckpt, compute: str
     return (gx[0] if squeeze else gx), grads
 
 
+class ChainStream:
+    """Block-by-block filtering of a stream with a fixed chain: every call to
+    ``process`` filters the next block as the continuation of the previous
+    ones (FIR input history and cascade registers carried on the device).
+    The device tables are prepared once for blocks of up to ``max_block``
+    samples; each block is then one ``tfx_chain_stream`` call."""
+
+    def __init__(self, stages, channels: int, max_block: int, compute: str = "f32", device="cuda:0"):
+        self.device = torch.device(device)
+        self.C, self.n_max, self.compute = int(channels), int(max_block), compute
+        self._kept, desc = _stages(stages, self.device)
+        self._arr = lib.stage_array(desc)
+        self._ns = len(desc)
+        firs = [n for k, n, _ in desc if k == lib.STAGE_FIR]
+        self.M = (firs[0] + sum(n - 1 for n in firs[1:])) if firs else 0
+        self.S = sum(n for k, n, _ in desc if k == lib.STAGE_SOS)
+        nb = lib.size_out()
+        lib.call("tfx_chain_workspace_size", self.C, self.n_max, self._arr, self._ns, lib.COMPUTE[compute], nb)
+        self._ws, self._wsb = _workspace(nb.value, self.device)
+        lib.call("tfx_chain_prepare", self.C, self.n_max, self._arr, self._ns, lib.COMPUTE[compute],
+                 _ptr(self._ws), self._wsb, _stream(self.device))
+        H = max(self.M - 1, 0)
+        self._hist = [torch.zeros((self.C, H), dtype=torch.float32, device=self.device) for _ in range(2)]
+        self._state = [torch.zeros((self.C, self.S, 2), dtype=torch.float32, device=self.device) for _ in range(2)]
+        self._cur = 0
+
+    def reset(self):
+        """Start of a new stream: zero history and registers."""
+        for t in self._hist + self._state:
+            t.zero_()
+
+    def process(self, x: torch.Tensor) -> torch.Tensor:
+        x2, squeeze, ld = _signal(x)
+        C, N = x2.shape
+        if C != self.C:
+            raise ValueError("the stream has %d channels" % self.C)
+        y = torch.empty((C, N), dtype=torch.float32, device=x.device)
+        i, o = self._cur, 1 - self._cur
+        lib.call("tfx_chain_stream", _ptr(x2), _ptr(y), C, N, ld, max(N, 1), self._arr, self._ns,
+                 lib.COMPUTE[self.compute], self.n_max, _ptr(self._hist[i]), _ptr(self._hist[o]),
+                 _ptr(self._state[i]), _ptr(self._state[o]), _ptr(self._ws), self._wsb, _stream(x.device))
+        self._cur = o
+        return y[0] if squeeze else y
+
+
 class _ChainFn(torch.autograd.Function):
     """y = chain(x, stages) with the library's adjoint as backward."""
 

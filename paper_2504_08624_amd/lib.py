@@ -60,6 +60,8 @@ _SIGS = {
     "tfx_chain_prepare": (_i32, [_i64, _i64, ctypes.POINTER(Stage), _i32, _i32, _vp, _sz, _vp]),
     "tfx_chain_run": (_i32, [_vp, _vp, _i64, _i64, _i64, _i64, ctypes.POINTER(Stage), _i32, _i32, _vp, _vp,
                              _sz, _vp]),
+    "tfx_chain_stream": (_i32, [_vp, _vp, _i64, _i64, _i64, _i64, ctypes.POINTER(Stage), _i32, _i32, _i64,
+                                _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
     "tfx_chain_backward_workspace_size": (_i32, [_i64, _i64, ctypes.POINTER(Stage), _i32, _i32,
                                                  ctypes.POINTER(_sz)]),
     "tfx_chain_backward": (_i32, [_vp, _vp, _vp, _i64, _i64, _i64, _i64, _i64, ctypes.POINTER(Stage), _i32,

@@ -143,3 +143,25 @@ def test_batched_validation_and_sizes():
     clips[1].y = clips[1].x + 8                                    # output overlaps the input
     assert _st("tfx_sos_batched_workspace_size", clips, 2, ctypes.byref(n)) == "TFX_E_ALIAS"
     assert b"clip 1" in L.tfx_last_error()
+
+
+def test_stream_argument_validation():
+    st = lib.stage_array([(lib.STAGE_FIR, 33, FAKE), (lib.STAGE_SOS, 2, FAKE + 4096)])
+    ws = 1 << 30
+    x, y = FAKE, FAKE + (1 << 30)
+    # block longer than the prepared length
+    assert _st("tfx_chain_stream", x, y, 2, 100, 100, 100, st, 2, 0, 50, None, None, None, None, FAKE, ws,
+               None) == "TFX_E_INVALID_ARG"
+    # workspace too small for (C, n_max)
+    assert _st("tfx_chain_stream", x, y, 2, 100, 100, 100, st, 2, 0, 1 << 20, None, None, None, None, FAKE, 256,
+               None) == "TFX_E_WORKSPACE"
+    n = ctypes.c_size_t()
+    assert _st("tfx_chain_workspace_size", 2, 200, st, 2, 0, ctypes.byref(n)) == "TFX_OK"
+    wsb = n.value
+    h = FAKE + (1 << 31)
+    # history out overlapping history in (2 ch x 32 floats each)
+    assert _st("tfx_chain_stream", x, y, 2, 100, 100, 100, st, 2, 0, 200, h, h + 16, None, None, FAKE, wsb,
+               None) == "TFX_E_ALIAS"
+    # state out overlapping a signal
+    assert _st("tfx_chain_stream", x, y, 2, 100, 100, 100, st, 2, 0, 200, None, None, None, y + 40, FAKE, wsb,
+               None) == "TFX_E_ALIAS"
