@@ -215,3 +215,157 @@ def max_pole_radius(sos5: np.ndarray) -> float:
         if rts.size:
             rmax = max(rmax, float(np.max(np.abs(rts))))
     return rmax
+
+
+# ------------------------------------------- further families, direct form
+
+def _groups(roots, tol=1e-9):
+    """Split roots into conjugate pairs (upper-half member) and reals."""
+    r = np.asarray(roots, dtype=np.complex128)
+    upper = [v for v in r if v.imag > tol]
+    reals = sorted([v.real for v in r if abs(v.imag) <= tol])
+    return upper, reals
+
+
+def _pair_general(zeros, poles, k):
+    """Sections of H(z) = k prod(1 - z_i/z) / prod(1 - p_j/z), any zeros.
+    Pole groups (a conjugate pair, or two real poles) are taken from the one
+    closest to the unit circle; each gets the nearest remaining zero group
+    (a conjugate pair, or up to two reals).  Sections are returned by
+    increasing pole radius, the gain k on the first one.  Groups without
+    poles (more zeros than poles) become FIR sections."""
+    pu, pr = _groups(poles)
+    zu, zr = _groups(zeros)
+    pg = [[p, np.conj(p)] for p in pu]
+    while len(pr) >= 2:
+        pg.append([pr.pop(0), pr.pop(0)])
+    if pr:
+        pg.append([pr.pop(0)])
+    zg = [[z, np.conj(z)] for z in zu]
+    while len(zr) >= 2:
+        zg.append([zr.pop(0), zr.pop(0)])
+    if zr:
+        zg.append([zr.pop(0)])
+    pg.sort(key=lambda g: -max(abs(v) for v in g))
+    secs = []
+    for g in pg:
+        c = np.mean(g)
+        if zg:
+            j = min(range(len(zg)), key=lambda i: abs(np.mean(zg[i]) - c))
+            secs.append((g, zg.pop(j)))
+        else:
+            secs.append((g, []))
+    secs.extend(([], zgrp) for zgrp in zg)
+    secs.sort(key=lambda s: max((abs(v) for v in s[0]), default=0.0))
+    rows = []
+    for ps, zs in secs:
+        a = np.real(np.poly(ps)) if ps else np.ones(1)
+        b = np.real(np.poly(zs)) if zs else np.ones(1)
+        rows.append(np.concatenate([b, np.zeros(3 - b.size), a[1:], np.zeros(3 - a.size)]))
+    if not rows:
+        rows = [np.array([1.0, 0.0, 0.0, 0.0, 0.0])]
+    rows = np.asarray(rows, dtype=np.float64)
+    rows[0, 0:3] *= k
+    return rows
+
+
+def tf2sos(b, a) -> np.ndarray:
+    """Direct-form transfer function b(z^-1) / a(z^-1) (any orders, a[0] != 0)
+    as [S, 5] sections with the same response.  Leading zero coefficients of
+    b are pure delays (sections z^-1 or z^-2)."""
+    b = np.trim_zeros(np.atleast_1d(np.asarray(b, dtype=np.float64)), "b")
+    a = np.trim_zeros(np.atleast_1d(np.asarray(a, dtype=np.float64)), "b")
+    if a.size == 0 or a[0] == 0.0:
+        raise ValueError("a[0] must be nonzero")
+    if b.size == 0:
+        return np.array([[0.0, 0.0, 0.0, 0.0, 0.0]])
+    d = 0
+    while b[d] == 0.0:
+        d += 1
+    bb = b[d:]
+    rows = _pair_general(np.roots(bb), np.roots(a), bb[0] / a[0])
+    delays = []
+    while d >= 2:
+        delays.append([0.0, 0.0, 1.0, 0.0, 0.0])
+        d -= 2
+    if d:
+        delays.append([0.0, 1.0, 0.0, 0.0, 0.0])
+    return np.concatenate([rows, np.asarray(delays).reshape(-1, 5)]) if delays else rows
+
+
+def chebyshev2(order: int, atten_db: float, fc: float, fs: float, btype: str = "lowpass") -> np.ndarray:
+    """Chebyshev type II (stopband attenuation ``atten_db``, stopband edge
+    ``fc``) low/high-pass as [S, 5] sections (bilinear, prewarped)."""
+    eps = 1.0 / np.sqrt(10.0 ** (atten_db / 10.0) - 1.0)
+    mu = np.arcsinh(1.0 / eps) / order
+    th = np.pi * (2 * np.arange(order) + 1) / (2.0 * order)
+    p1 = -np.sinh(mu) * np.sin(th) + 1j * np.cosh(mu) * np.cos(th)
+    proto_p = 1.0 / p1
+    cz = np.cos(th)
+    proto_z = np.array([1j / c for c in cz if abs(c) > 1e-12])
+    wc = 2.0 * fs * np.tan(np.pi * fc / fs)
+    nz_inf = order - proto_z.size
+    if btype == "lowpass":
+        z, p = _bilinear_zpk(wc * proto_z, wc * proto_p, fs)
+        z = np.concatenate([z, -np.ones(nz_inf)])
+        gain_w, target = 0.0, 1.0
+    elif btype == "highpass":
+        z, p = _bilinear_zpk(wc / proto_z, wc / proto_p, fs)
+        z = np.concatenate([z, np.ones(nz_inf)])
+        gain_w, target = np.pi, 1.0
+    else:
+        raise ValueError(btype)
+    rows = _pair_general(z, p, 1.0)
+    rows[0, 0:3] *= target / abs(sos_response(rows, [gain_w])[0])
+    return rows
+
+
+def butterworth_band(order: int, f1: float, f2: float, fs: float, btype: str = "bandpass") -> np.ndarray:
+    """Butterworth band-pass / band-stop between ``f1`` and ``f2`` of
+    prototype order ``order`` (2 order poles): the low-pass prototype through
+    the analog band transformation, then the bilinear map (edges prewarped)."""
+    k = np.arange(order)
+    proto = np.exp(1j * np.pi * (2 * k + order + 1) / (2.0 * order))
+    w1, w2 = (2.0 * fs * np.tan(np.pi * f / fs) for f in (f1, f2))
+    w0, bw = np.sqrt(w1 * w2), w2 - w1
+    if btype == "bandpass":
+        t = proto * bw / 2.0
+        ps = np.concatenate([t + np.sqrt(t * t - w0 * w0), t - np.sqrt(t * t - w0 * w0)])
+        _, p = _bilinear_zpk([], ps, fs)
+        z = np.concatenate([np.ones(order), -np.ones(order)])  # s = 0 and s = infinity
+        gain_w = 2.0 * np.arctan(w0 / (2.0 * fs))
+    elif btype == "bandstop":
+        t = bw / (2.0 * proto)
+        ps = np.concatenate([t + np.sqrt(t * t - w0 * w0), t - np.sqrt(t * t - w0 * w0)])
+        _, p = _bilinear_zpk([], ps, fs)
+        zc = (2.0 * fs + 1j * w0) / (2.0 * fs - 1j * w0)
+        z = np.concatenate([np.full(order, zc), np.full(order, np.conj(zc))])
+        gain_w = 0.0
+    else:
+        raise ValueError(btype)
+    rows = _pair_general(z, p, 1.0)
+    rows[0, 0:3] *= 1.0 / abs(sos_response(rows, [gain_w])[0])
+    return rows
+
+
+def _rbj(f0: float, q: float, fs: float):
+    w0 = 2.0 * np.pi * f0 / fs
+    return np.cos(w0), np.sin(w0) / (2.0 * q)
+
+
+def notch(f0: float, q: float, fs: float) -> np.ndarray:
+    """RBJ cookbook notch at ``f0`` (one section; unit gain far from f0)."""
+    c, al = _rbj(f0, q, fs)
+    return _normalise([[1.0, -2 * c, 1.0, 1 + al, -2 * c, 1 - al]])
+
+
+def allpass(f0: float, q: float, fs: float) -> np.ndarray:
+    """RBJ cookbook second-order all-pass centred at ``f0`` (one section)."""
+    c, al = _rbj(f0, q, fs)
+    return _normalise([[1 - al, -2 * c, 1 + al, 1 + al, -2 * c, 1 - al]])
+
+
+def bandpass_biquad(f0: float, q: float, fs: float) -> np.ndarray:
+    """RBJ cookbook band-pass with 0 dB peak at ``f0`` (one section)."""
+    c, al = _rbj(f0, q, fs)
+    return _normalise([[al, 0.0, -al, 1 + al, -2 * c, 1 - al]])

@@ -2,7 +2,8 @@
 
 Every filter is a ``torch.nn.Module`` holding one stage of the chain: FIR taps
 or SOS sections (rows [b0 b1 b2 a1 a2], a0 = 1).  Designed filters
-(Butterworth, Chebyshev type I, peaking, shelving, windowed-sinc FIR) are
+(Butterworth low/high/band-pass/band-stop, Chebyshev types I and II, peaking,
+shelving, notch, all-pass, band-pass biquad, windowed-sinc FIR) are
 designed in FP64 on the host from their parameters and the sample rate, and
 rounded to fp32 once per (sample rate, device).  The sample rate may be given
 at construction (``sample_rate=``) or left open and bound lazily by the pipe
@@ -153,6 +154,91 @@ class LoShelving(Filter):
 
     def _design(self, fs):
         return design.shelf(self.cutoff, self.gain_db, fs, "low", self.slope)
+
+
+class Chebyshev2(Filter):
+    """Chebyshev type II low- or high-pass (stopband ``atten_db`` down from
+    the stopband edge ``cutoff``)."""
+
+    def __init__(self, cutoff: float, sample_rate: Optional[float] = None, *, order: int = 4,
+                 atten_db: float = 40.0, btype: str = "lowpass"):
+        super().__init__(sample_rate)
+        self.cutoff, self.order, self.atten_db, self.btype = float(cutoff), int(order), float(atten_db), btype
+
+    def _design(self, fs):
+        return design.chebyshev2(self.order, self.atten_db, self.cutoff, fs, self.btype)
+
+
+class ButterworthBand(Filter):
+    """Butterworth band-pass or band-stop between ``low`` and ``high`` Hz
+    (``order`` is the prototype order: ``order`` sections)."""
+
+    def __init__(self, low: float, high: float, sample_rate: Optional[float] = None, *, order: int = 2,
+                 btype: str = "bandpass"):
+        super().__init__(sample_rate)
+        self.low, self.high, self.order, self.btype = float(low), float(high), int(order), btype
+
+    def _design(self, fs):
+        return design.butterworth_band(self.order, self.low, self.high, fs, self.btype)
+
+
+class Notch(Filter):
+    """Second-order notch at ``center`` Hz (one section)."""
+
+    def __init__(self, center: float, sample_rate: Optional[float] = None, *, q: float = 10.0):
+        super().__init__(sample_rate)
+        self.center, self.q = float(center), float(q)
+
+    def _design(self, fs):
+        return design.notch(self.center, self.q, fs)
+
+
+class AllPass(Filter):
+    """Second-order all-pass centred at ``center`` Hz (one section)."""
+
+    def __init__(self, center: float, sample_rate: Optional[float] = None, *, q: float = 0.707):
+        super().__init__(sample_rate)
+        self.center, self.q = float(center), float(q)
+
+    def _design(self, fs):
+        return design.allpass(self.center, self.q, fs)
+
+
+class BandPass(Filter):
+    """Second-order band-pass with unit gain at ``center`` Hz (one section)."""
+
+    def __init__(self, center: float, sample_rate: Optional[float] = None, *, q: float = 0.707):
+        super().__init__(sample_rate)
+        self.center, self.q = float(center), float(q)
+
+    def _design(self, fs):
+        return design.bandpass_biquad(self.center, self.q, fs)
+
+
+class DirectForm(Filter):
+    """Direct-form transfer function b(z^-1) / a(z^-1), factored into
+    sections in FP64 (an unstable denominator is an error).  Needs no sample
+    rate."""
+
+    def __init__(self, b, a):
+        super().__init__(None)
+        self.b = np.asarray(b, dtype=np.float64).reshape(-1)
+        self.a = np.asarray(a, dtype=np.float64).reshape(-1)
+        rows = design.tf2sos(self.b, self.a)
+        if design.max_pole_radius(rows) >= 1.0:
+            raise ValueError("the denominator has a pole on or outside the unit circle")
+        self._rows = rows
+
+    def bind(self, fs):
+        return self
+
+    def coefficients(self, device):
+        key = str(device)
+        t = self._cache.get(key)
+        if t is None:
+            t = torch.as_tensor(self._rows.astype(np.float32)).to(device)
+            self._cache[key] = t
+        return t
 
 
 class SOS(Filter):

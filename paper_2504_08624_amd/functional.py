@@ -341,6 +341,26 @@ def sos(x: torch.Tensor, sections, state_in=None, return_state: bool = False,
     return _sos_raw(x, sections, state_in, return_state, return_ckpt)
 
 
+def lfilter(x: torch.Tensor, b, a, compute: str = "f32") -> torch.Tensor:
+    """Direct-form IIR y = (b(z^-1) / a(z^-1)) x, zero initial state.  The
+    polynomials are factored into second-order sections in FP64 on the host
+    (roots paired nearest-zero-to-pole) and run as one fused chain; a
+    denominator of length 1 is a plain FIR.  An unstable denominator (a pole
+    on or outside the unit circle) is an error.  Differentiable in x."""
+    import numpy as np
+    from . import design
+    bb = np.atleast_1d(np.asarray(b, dtype=np.float64))
+    aa = np.trim_zeros(np.atleast_1d(np.asarray(a, dtype=np.float64)), "b")
+    if aa.size == 0 or aa[0] == 0.0:
+        raise ValueError("a[0] must be nonzero")
+    if aa.size == 1:
+        return chain(x, [("fir", (bb / aa[0]).astype(np.float32))], compute)
+    rows = design.tf2sos(bb, aa)
+    if design.max_pole_radius(rows) >= 1.0:
+        raise ValueError("the denominator has a pole on or outside the unit circle")
+    return chain(x, [("sos", rows.astype(np.float32))], compute)
+
+
 # ------------------------------------------------------------------ batched
 
 class SosBatch:

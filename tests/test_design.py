@@ -104,3 +104,102 @@ def test_random_sections_are_stable_and_normalised():
     sec = D.random_sections(g, 6, 0.5, 0.999)
     assert sec.shape == (6, 5)
     assert D.max_pole_radius(sec) < 0.999
+
+
+# ---------------------------------------------- further families, direct form
+
+def _resp_scipy(ref_sos, f, fs):
+    _, H = ss.sosfreqz(ref_sos, worN=f, fs=fs)
+    return H
+
+
+@pytest.mark.parametrize("order,atten,fc,btype", [(4, 40.0, 2000.0, "lowpass"), (5, 60.0, 300.0, "highpass"),
+                                                  (8, 50.0, 8000.0, "lowpass"), (3, 30.0, 12000.0, "highpass")])
+def test_chebyshev2_matches_scipy_and_its_stopband(order, atten, fc, btype):
+    fs = 48000.0
+    mine = D.chebyshev2(order, atten, fc, fs, btype)
+    f = np.linspace(1.0, fs / 2 - 1, 901)
+    ref = ss.cheby2(order, atten, fc, btype, fs=fs, output="sos")
+    assert np.max(np.abs(_H(mine, f, fs) - _resp_scipy(ref, f, fs))) < 1e-9
+    # the stopband edge sits exactly atten dB down, and no stopband point is higher
+    assert abs(_db(_H(mine, fc, fs)) + atten) < 1e-8
+    stop = f[f > fc * 1.0001] if btype == "lowpass" else f[f < fc * 0.9999]
+    assert np.max(_db(_H(mine, stop, fs))) < -atten + 1e-8
+    assert D.max_pole_radius(mine) < 1.0
+
+
+@pytest.mark.parametrize("order,f1,f2,btype", [(2, 300.0, 3000.0, "bandpass"), (3, 500.0, 1500.0, "bandstop"),
+                                               (4, 100.0, 12000.0, "bandpass"), (1, 1000.0, 2000.0, "bandstop")])
+def test_butterworth_band_matches_scipy_and_its_edges(order, f1, f2, btype):
+    fs = 48000.0
+    mine = D.butterworth_band(order, f1, f2, fs, btype)
+    assert mine.shape == (order, 5)
+    f = np.linspace(1.0, fs / 2 - 1, 901)
+    ref = ss.butter(order, [f1, f2], btype, fs=fs, output="sos")
+    assert np.max(np.abs(_H(mine, f, fs) - _resp_scipy(ref, f, fs))) < 1e-9
+    # both band edges are 3 dB points
+    for fe in (f1, f2):
+        assert abs(_db(_H(mine, fe, fs)) + 10 * np.log10(2)) < 1e-8
+
+
+def test_rbj_notch_bandpass_allpass_identities():
+    fs, f0, q = 48000.0, 1234.0, 3.0
+    n, bp, ap = D.notch(f0, q, fs), D.bandpass_biquad(f0, q, fs), D.allpass(f0, q, fs)
+    f = np.linspace(0.0, fs / 2, 513)
+    Hn, Hb, Ha = _H(n, f, fs), _H(bp, f, fs), _H(ap, f, fs)
+    # same denominator: notch + band-pass is the identity, notch - band-pass the all-pass
+    assert np.max(np.abs(Hn + Hb - 1)) < 1e-12
+    assert np.max(np.abs(Hn - Hb - Ha)) < 1e-12
+    assert np.max(np.abs(np.abs(Ha) - 1)) < 1e-12
+    assert abs(_H(n, f0, fs)) < 1e-12 and abs(_H(bp, f0, fs) - 1) < 1e-12
+    assert abs(_H(ap, f0, fs) + 1) < 1e-12
+    assert abs(abs(_H(n, 0.0, fs)) - 1) < 1e-12 and abs(_H(bp, 0.0, fs)) < 1e-12
+
+
+def _poly_from_roots(g, n_pairs, n_real, rmax):
+    roots = []
+    for _ in range(n_pairs):
+        r, t = rmax * np.sqrt(g.uniform(0.05, 1.0)), g.uniform(0.05, np.pi - 0.05)
+        roots += [r * np.exp(1j * t), r * np.exp(-1j * t)]
+    roots += list(g.uniform(-rmax, rmax, n_real))
+    return np.real(np.poly(roots)) if roots else np.ones(1)
+
+
+@pytest.mark.parametrize("seed,zp,zr,pp,pr,delay", [(1, 2, 1, 3, 0, 0), (2, 0, 0, 2, 1, 0), (3, 3, 2, 1, 1, 1),
+                                                    (4, 1, 0, 0, 2, 2), (5, 4, 0, 4, 0, 3), (6, 0, 1, 0, 0, 0)])
+def test_tf2sos_keeps_the_transfer_function(seed, zp, zr, pp, pr, delay):
+    g = np.random.default_rng(seed)
+    b = np.concatenate([np.zeros(delay), 0.7 * _poly_from_roots(g, zp, zr, 1.3)])
+    a = 2.0 * _poly_from_roots(g, pp, pr, 0.95)
+    rows = D.tf2sos(b, a)
+    f = np.linspace(0.0, 0.5, 777)
+    _, Href = ss.freqz(b, a, worN=2 * np.pi * f)
+    assert np.max(np.abs(_H(rows, f, 1.0) - Href)) < 1e-9 * max(1.0, np.max(np.abs(Href)))
+    # the time-domain run agrees with the direct form too
+    x = g.standard_normal(400)
+    y = x.copy()
+    for b0, b1, b2, a1, a2 in rows:
+        y = ss.lfilter([b0, b1, b2], [1.0, a1, a2], y)
+    assert np.max(np.abs(y - ss.lfilter(b, a, x))) < 1e-9 * max(1.0, np.max(np.abs(y)))
+    assert D.max_pole_radius(rows) < 0.95 + 1e-9
+
+
+def test_tf2sos_pairs_each_pole_pair_with_its_nearest_zeros():
+    # two resonances, each with a zero pair just beside it: pairing keeps them together
+    p1, p2 = 0.9 * np.exp(0.5j), 0.8 * np.exp(2.0j)
+    z1, z2 = 0.95 * np.exp(0.55j), 0.9 * np.exp(2.1j)
+    b = np.real(np.poly([z1, np.conj(z1), z2, np.conj(z2)]))
+    a = np.real(np.poly([p1, np.conj(p1), p2, np.conj(p2)]))
+    rows = D.tf2sos(b, a)
+    assert rows.shape == (2, 5)
+    for row, (p, z) in zip(rows, [(p2, z2), (p1, z1)]):   # increasing pole radius
+        assert np.allclose(sorted(np.abs(np.roots([1.0, row[3], row[4]]))), [abs(p)] * 2)
+        assert np.allclose(np.abs(np.roots(row[:3])), [abs(z)] * 2)
+
+
+def test_tf2sos_degenerate_forms():
+    assert np.allclose(D.tf2sos([2.0], [4.0]), [[0.5, 0, 0, 0, 0]])
+    assert np.allclose(D.tf2sos([0.0, 0.0, 3.0], [1.0]), [[3.0, 0, 0, 0, 0], [0, 0, 1.0, 0, 0]])
+    assert np.allclose(D.tf2sos([0.0], [1.0, 0.5]), 0.0)
+    with pytest.raises(ValueError):
+        D.tf2sos([1.0], [0.0, 1.0])

@@ -39,6 +39,12 @@ def test_designs_match_the_fp64_design_functions():
         (tfx.LoShelving(200.0, fs, gain_db=-6.0, slope=0.8), design.shelf(200.0, -6.0, fs, "low", 0.8)),
         (tfx.WindowedSincFIR(6000.0, fs, num_taps=65), design.fir_lowpass(65, 6000.0, fs)),
         (tfx.WindowedSincFIR(300.0, fs, num_taps=129, cutoff_hi=3000.0), design.fir_bandpass(129, 300.0, 3000.0, fs)),
+        (tfx.Chebyshev2(3000.0, fs, order=6, atten_db=50.0), design.chebyshev2(6, 50.0, 3000.0, fs)),
+        (tfx.ButterworthBand(200.0, 4000.0, fs, order=3, btype="bandstop"),
+         design.butterworth_band(3, 200.0, 4000.0, fs, "bandstop")),
+        (tfx.Notch(60.0, fs, q=30.0), design.notch(60.0, 30.0, fs)),
+        (tfx.AllPass(700.0, fs, q=0.5), design.allpass(700.0, 0.5, fs)),
+        (tfx.BandPass(2500.0, fs, q=4.0), design.bandpass_biquad(2500.0, 4.0, fs)),
     ]
     for f, ref in cases:
         c = f.coefficients("cpu").numpy()
@@ -77,3 +83,16 @@ def test_wave_shapes():
         tfx.Wave(torch.zeros(1, 2, 3), 16000)
     with pytest.raises(ValueError):
         tfx.Wave(torch.zeros(1, 3), 0)
+
+
+def test_direct_form_factors_once_and_rejects_unstable_denominators():
+    b, a = [0.2, 0.3, 0.1, 0.05], [1.0, -0.9, 0.4, -0.1]
+    f = tfx.DirectForm(b, a)
+    np.testing.assert_array_equal(f.coefficients("cpu").numpy(), design.tf2sos(b, a).astype(np.float32))
+    assert f.kind == "sos" and (_wave() | f).pending == [f]
+    with pytest.raises(ValueError, match="unit circle"):
+        tfx.DirectForm([1.0], [1.0, -1.5])
+    with pytest.raises(ValueError, match="unit circle"):
+        tfx.lfilter(torch.zeros(1, 8), [1.0], [1.0, 0.0, 1.0])   # poles on the circle
+    with pytest.raises(ValueError, match="nonzero"):
+        tfx.lfilter(torch.zeros(1, 8), [1.0], [0.0])

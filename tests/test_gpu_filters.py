@@ -95,3 +95,47 @@ def test_trainable_stages_get_gradients_through_the_pipe():
     gh, gs = _cpu(fir.taps.grad), _cpu(sos.sections.grad)
     assert np.linalg.norm(gh - rgh) <= 1e-4 * np.linalg.norm(rgh)
     assert np.linalg.norm(gs - np.reshape(rgs, gs.shape)) <= 1e-4 * np.linalg.norm(rgs)
+
+
+def test_further_designed_families_through_the_pipe():
+    x = _signal(3, 4 * 3072 + 29, (506,))
+    fs = [tfx.Chebyshev2(5000.0, order=6, atten_db=50.0), tfx.ButterworthBand(300.0, 3000.0, order=3),
+          tfx.Notch(1000.0, q=10.0), tfx.AllPass(2000.0, q=0.7), tfx.BandPass(800.0, q=1.5),
+          tfx.ButterworthBand(4000.0, 6000.0, order=2, btype="bandstop")]
+    w = tfx.Wave(torch.from_numpy(x).to(DEV), FS)
+    for f in fs:
+        w = w | f
+    assert_close(_cpu(w.y), O.chain(x, _stages(fs)), TOL_IIR_F32, "Chebyshev2 | bands | notch | all-pass")
+
+
+def _stable_tf(g, zeros_pairs, poles_pairs, rmax):
+    def poly(n, r):
+        roots = []
+        for _ in range(n):
+            rr, t = r * np.sqrt(g.uniform(0.1, 1.0)), g.uniform(0.1, np.pi - 0.1)
+            roots += [rr * np.exp(1j * t), rr * np.exp(-1j * t)]
+        roots.append(g.uniform(-r, r))
+        return np.real(np.poly(roots))
+    return 0.3 * poly(zeros_pairs, 1.2), poly(poles_pairs, rmax)
+
+
+@pytest.mark.parametrize("seed,zp,pp,C,N", [(11, 3, 3, 3, 3 * 3072 + 17), (12, 1, 4, 2, 5000), (13, 4, 2, 1, 100)])
+def test_lfilter_matches_the_oracle_on_its_sections(seed, zp, pp, C, N):
+    from scipy.signal import lfilter as sp_lfilter
+    from paper_2504_08624_amd import design
+    g = np.random.default_rng(seed)
+    b, a = _stable_tf(g, zp, pp, 0.97)
+    x = _signal(C, N, (507, seed))
+    y = _cpu(tfx.lfilter(torch.from_numpy(x).to(DEV), b, a))
+    rows = design.tf2sos(b, a).astype(np.float32)
+    assert_close(y, O.sos(x, rows), TOL_IIR_F32, "lfilter vs oracle cascade")
+    # the direct form in FP64 differs only by the fp32 rounding of the sections
+    ref = sp_lfilter(b, a, x.astype(np.float64), axis=1)
+    assert_close(y, ref, TOL_IIR_F32, "lfilter vs FP64 direct form")
+
+
+def test_lfilter_with_a_scalar_denominator_is_a_fir():
+    x = _signal(2, 7000, (508,))
+    h = np.hanning(21)
+    y = _cpu(tfx.lfilter(torch.from_numpy(x).to(DEV), h, [2.0]))
+    assert_close(y, O.fir(x, (h / 2.0).astype(np.float32)), 1e-5, "lfilter FIR form")
