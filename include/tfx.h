@@ -283,6 +283,49 @@ tfx_status tfx_sos_backward(const float *x, const float *gy, float *gx, int64_t 
                             const float *ckpt, float *gsos, void *ws, size_t ws_bytes,
                             void *stream);
 
+/* ------------------------------------------------------------------ STFT */
+
+/* Short-time Fourier transform, one of the signal-processing functions on
+ * the roadmap of Sec. 5 (the textbook definition; the paper gives none):
+ *
+ *   X[c,t,k] = scale * sum_{n<n_fft} w[n] xp[c, t*hop + n] exp(-2 pi i k n / n_fft),
+ *   k = 0 .. n_fft/2,   t = 0 .. T-1,
+ *
+ * xp = x, or with `center` x padded by n_fft/2 reflected samples on each
+ * side (xp[-j] = x[j], xp[N-1+j] = x[N-1-j]); w = `window` (win_length
+ * samples, or ones when window is NULL) placed in the middle of the frame
+ * (offset (n_fft - win_length)/2, zeros elsewhere); scale = 1, or
+ * n_fft^-1/2 with `normalized`.  T = 1 + (Np - n_fft)/hop (floor) with Np the
+ * padded length (T = 0 when Np < n_fft: nothing is written).  These are the
+ * conventions of torch.stft(onesided=True, pad_mode="reflect").
+ *
+ * n_fft: a power of two in [16, 4096] (TFX_E_UNSUPPORTED otherwise);
+ * hop >= 1; 1 <= win_length <= n_fft; with `center`, N > n_fft/2.
+ * x: [C][N] fp32, row stride ldx.  spec: [C][T][n_fft/2+1] complex as
+ * interleaved (re, im) fp32, frame-major (contiguous; spec must not overlap
+ * x).  Two frames share one complex FFT in LDS; no workspace. */
+tfx_status tfx_stft_frames(int64_t N, int32_t n_fft, int32_t hop, int32_t center, int64_t *T);
+tfx_status tfx_stft(const float *x, int64_t C, int64_t N, int64_t ldx, int32_t n_fft, int32_t hop,
+                    const float *window, int32_t win_length, int32_t center, int32_t normalized, float *spec,
+                    void *stream);
+
+/* Inverse by weighted overlap-add (torch.istft's conventions):
+ *   y[c, s] = sum_t w[p - t*hop] f_t[p - t*hop] / sum_t w[p - t*hop]^2,
+ *   p = s + (center ? n_fft/2 : 0),
+ * f_t = the real inverse DFT of spec[c,t,:] (imaginary parts of bins 0 and
+ * n_fft/2 ignored), times n_fft^1/2 with `normalized`; the sums run over
+ * the frames covering p.  length < 0 selects every covered sample less the
+ * centre padding (n_fft + hop*(T-1) - 2*(n_fft/2 if center)); samples past
+ * the covered range, and samples whose summed squared window is <= 1e-11,
+ * are written as 0 (callers that need torch's error on a vanishing
+ * envelope check the window themselves).  spec: [C][T][n_fft/2+1] complex,
+ * T >= 1; y: [C][length], row stride ldy; workspace (the windowed frames)
+ * from tfx_istft_workspace_size. */
+tfx_status tfx_istft_workspace_size(int64_t C, int64_t T, int32_t n_fft, size_t *bytes);
+tfx_status tfx_istft(const float *spec, int64_t C, int64_t T, int32_t n_fft, int32_t hop, const float *window,
+                     int32_t win_length, int32_t center, int32_t normalized, float *y, int64_t length, int64_t ldy,
+                     void *ws, size_t ws_bytes, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

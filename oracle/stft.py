@@ -132,3 +132,14 @@ def istft(spec, n_fft: int, hop: int, window=None, center: bool = True, normaliz
 def hann(n: int) -> np.ndarray:
     """Periodic Hann window (the usual choice for an STFT)."""
     return 0.5 - 0.5 * np.cos(2.0 * np.pi * np.arange(n) / n)
+
+
+def frame(x_row, n_fft: int, hop: int, window, center: bool, t: int, normalized: bool = False) -> np.ndarray:
+    """Spectrum of frame t of one channel alone (sampled checks of long signals)."""
+    x = np.asarray(x_row, dtype=np.float64).reshape(-1)
+    p = n_fft // 2 if center else 0
+    idx = t * hop + np.arange(n_fft) - p
+    idx = np.where(idx < 0, -idx, idx)
+    idx = np.where(idx >= x.size, 2 * (x.size - 1) - idx, idx)
+    out = np.fft.rfft(full_window(window, n_fft) * x[idx])
+    return out / np.sqrt(n_fft) if normalized else out

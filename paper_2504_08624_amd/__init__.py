@@ -9,9 +9,10 @@ from .functional import (ChainStream, SosBatch, chain, chain_backward, fir, fir_
                          sos_backward, sos_batched, tile_length)
 from .filters import (FIR, SOS, AllPass, BandPass, Butterworth, ButterworthBand, Chebyshev1, Chebyshev2,  # noqa: F401
                       DirectForm, Filter, HiShelving, LoShelving, Notch, Peaking, WindowedSincFIR)
+from .spectral import istft, stft  # noqa: F401
 from .wave import Wave  # noqa: F401
 
-__all__ = ["fir", "sos", "chain", "lfilter", "ChainStream", "fir_backward", "sos_backward", "chain_backward", "sos_batched", "SosBatch",
+__all__ = ["fir", "sos", "chain", "lfilter", "stft", "istft", "ChainStream", "fir_backward", "sos_backward", "chain_backward", "sos_batched", "SosBatch",
            "tile_length", "Wave", "Filter", "Butterworth", "Chebyshev1", "Peaking", "HiShelving", "LoShelving",
            "WindowedSincFIR", "FIR", "SOS", "Chebyshev2", "ButterworthBand", "Notch", "AllPass", "BandPass",
            "DirectForm"]

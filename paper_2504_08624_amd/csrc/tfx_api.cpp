@@ -265,6 +265,27 @@ tfx_status backward(const tfx::BwdPlan &bp) {
     return ok();
 }
 
+// STFT argument checks
+int stft_log2(int32_t n_fft) {
+    for (int l = 4; l <= 12; ++l)
+        if (n_fft == (1 << l)) return l;
+    return -1;
+}
+
+int64_t stft_count(int64_t N, int32_t n_fft, int32_t hop, int32_t center) {
+    const int64_t np = center ? N + 2 * (int64_t)(n_fft / 2) : N;
+    return np < n_fft ? 0 : 1 + (np - n_fft) / hop;
+}
+
+tfx_status stft_params(int32_t n_fft, int32_t hop, int32_t win_length, int *log2n) {
+    *log2n = stft_log2(n_fft);
+    if (*log2n < 0) return fail(TFX_E_UNSUPPORTED, "n_fft must be a power of two in [16, 4096] (got %d)", n_fft);
+    if (hop < 1) return fail(TFX_E_INVALID_ARG, "hop must be >= 1 (got %d)", hop);
+    if (win_length < 1 || win_length > n_fft)
+        return fail(TFX_E_INVALID_ARG, "win_length must be in [1, n_fft] (got %d)", win_length);
+    return TFX_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -636,6 +657,97 @@ tfx_status tfx_sos_batched_tune(const tfx_clip *clips, int32_t nclips, int32_t r
     *best = bc;
     if (best_ms) *best_ms = bms;
     return batch_do(clips, nclips, &bc, ws, ws_bytes, stream, true, false);
+}
+
+
+// ---- short-time Fourier transform ------------------------------------------------
+
+tfx_status tfx_stft_frames(int64_t N, int32_t n_fft, int32_t hop, int32_t center, int64_t *T) {
+    if (!T) return fail(TFX_E_INVALID_ARG, "T is NULL");
+    int l;
+    tfx_status s = stft_params(n_fft, hop, n_fft, &l);
+    if (s) return s;
+    if (N < 0 || N >= (int64_t(1) << 40)) return fail(TFX_E_INVALID_ARG, "N out of range");
+    *T = stft_count(N, n_fft, hop, center);
+    return ok();
+}
+
+tfx_status tfx_stft(const float *x, int64_t C, int64_t N, int64_t ldx, int32_t n_fft, int32_t hop,
+                    const float *window, int32_t win_length, int32_t center, int32_t normalized, float *spec,
+                    void *stream) {
+    tfx::StftPlan sp{};
+    tfx_status s = stft_params(n_fft, hop, win_length, &sp.log2n);
+    if (s) return s;
+    if (C < 1) return fail(TFX_E_INVALID_ARG, "C must be >= 1 (got %lld)", (long long)C);
+    if (N < 0 || N >= (int64_t(1) << 40)) return fail(TFX_E_INVALID_ARG, "N out of range (got %lld)", (long long)N);
+    if (ldx < N) return fail(TFX_E_INVALID_ARG, "ldx must be >= N");
+    if (center && N > 0 && N <= n_fft / 2)
+        return fail(TFX_E_INVALID_ARG, "centred frames reflect n_fft/2 samples: N must exceed %d (got %lld)",
+                    n_fft / 2, (long long)N);
+    const int64_t T = stft_count(N, n_fft, hop, center);
+    if (T == 0 || N == 0) return ok();
+    if (!x || !spec) return fail(TFX_E_INVALID_ARG, "x and spec must be non-null");
+    const size_t sbytes = (size_t)C * (size_t)T * (size_t)(n_fft / 2 + 1) * 2 * sizeof(float);
+    if (overlaps(x, span_bytes(C, N, ldx), spec, sbytes)) return fail(TFX_E_ALIAS, "spec overlaps x");
+    sp.hop = hop;
+    sp.win_length = win_length;
+    sp.center = center ? 1 : 0;
+    sp.normalized = normalized ? 1 : 0;
+    sp.win = window;
+    sp.C = C;
+    sp.T = T;
+    sp.x = x;
+    sp.ldx = ldx;
+    sp.nx = N;
+    sp.spec = spec;
+    sp.stream = static_cast<hipStream_t>(stream);
+    hipError_t e = tfx::launch_stft(sp);
+    return e == hipSuccess ? ok() : hip_fail(e, "stft kernel");
+}
+
+tfx_status tfx_istft_workspace_size(int64_t C, int64_t T, int32_t n_fft, size_t *bytes) {
+    if (!bytes) return fail(TFX_E_INVALID_ARG, "bytes is NULL");
+    if (C < 1 || T < 1) return fail(TFX_E_INVALID_ARG, "C and T must be >= 1");
+    if (stft_log2(n_fft) < 0) return fail(TFX_E_UNSUPPORTED, "n_fft must be a power of two in [16, 4096]");
+    *bytes = (size_t)C * (size_t)T * (size_t)n_fft * sizeof(float);
+    return ok();
+}
+
+tfx_status tfx_istft(const float *spec, int64_t C, int64_t T, int32_t n_fft, int32_t hop, const float *window,
+                     int32_t win_length, int32_t center, int32_t normalized, float *y, int64_t length, int64_t ldy,
+                     void *ws, size_t ws_bytes, void *stream) {
+    tfx::StftPlan sp{};
+    tfx_status s = stft_params(n_fft, hop, win_length, &sp.log2n);
+    if (s) return s;
+    if (C < 1 || T < 1) return fail(TFX_E_INVALID_ARG, "C and T must be >= 1");
+    const int64_t total = (int64_t)n_fft + (int64_t)hop * (T - 1);
+    if (total >= (int64_t(1) << 40)) return fail(TFX_E_INVALID_ARG, "T * hop out of range");
+    if (length < 0) length = total - (center ? 2 * (int64_t)(n_fft / 2) : 0);
+    if (length >= (int64_t(1) << 38)) return fail(TFX_E_UNSUPPORTED, "length must be below 2^38");
+    if (ldy < length) return fail(TFX_E_INVALID_ARG, "ldy must be >= length");
+    if (length == 0) return ok();
+    if (!spec || !y) return fail(TFX_E_INVALID_ARG, "spec and y must be non-null");
+    const size_t need = (size_t)C * (size_t)T * (size_t)n_fft * sizeof(float);
+    if ((s = check_ws(ws, ws_bytes, need))) return s;
+    const size_t sbytes = (size_t)C * (size_t)T * (size_t)(n_fft / 2 + 1) * 2 * sizeof(float);
+    if (overlaps(y, span_bytes(C, length, ldy), spec, sbytes)) return fail(TFX_E_ALIAS, "y overlaps spec");
+    if (overlaps(y, span_bytes(C, length, ldy), ws, need) || overlaps(spec, sbytes, ws, need))
+        return fail(TFX_E_ALIAS, "the workspace overlaps spec or y");
+    sp.hop = hop;
+    sp.win_length = win_length;
+    sp.center = center ? 1 : 0;
+    sp.normalized = normalized ? 1 : 0;
+    sp.win = window;
+    sp.C = C;
+    sp.T = T;
+    sp.spec_in = spec;
+    sp.frames = static_cast<float *>(ws);
+    sp.y = y;
+    sp.length = length;
+    sp.ldy = ldy;
+    sp.stream = static_cast<hipStream_t>(stream);
+    hipError_t e = tfx::launch_istft(sp);
+    return e == hipSuccess ? ok() : hip_fail(e, "istft kernels");
 }
 
 }  // extern "C"

@@ -222,6 +222,27 @@ hipError_t upload_descriptors(const ClipDesc *desc, int32_t n, const BatchLayout
 hipError_t launch_batch_prepare(const BatchLayout &lay, int lc, int32_t nclips, void *ws, hipStream_t st);
 hipError_t launch_batch_run(const BatchLayout &lay, int lc, int32_t nclips, void *ws, hipStream_t st);
 
+// ---- short-time Fourier transform -------------------------------------------
+struct StftPlan {
+    int log2n;              // n_fft = 2^log2n, 4 .. 12
+    int32_t hop, win_length, center, normalized;
+    const float *win;       // [win_length] or NULL (ones)
+    int64_t C, T;           // channels, frames per channel
+    // forward
+    const float *x;
+    int64_t ldx, nx;
+    float *spec;            // [C][T][n_fft/2+1] complex (re, im)
+    // inverse
+    const float *spec_in;
+    float *frames;          // workspace [C][T][n_fft]
+    float *y;
+    int64_t length, ldy;
+    hipStream_t stream;
+};
+
+hipError_t launch_stft(const StftPlan &sp);
+hipError_t launch_istft(const StftPlan &sp);
+
 // ---- adjoint -------------------------------------------------------------------
 struct GradList {
     float *ptr[MAX_STAGES];

@@ -75,6 +75,10 @@ _SIGS = {
     "tfx_sos_batched": (_i32, [ctypes.POINTER(Clip), _i32, ctypes.POINTER(BatchConfig), _vp, _sz, _vp]),
     "tfx_sos_batched_tune": (_i32, [ctypes.POINTER(Clip), _i32, _i32, _vp, _sz, _vp, ctypes.POINTER(BatchConfig),
                                     ctypes.POINTER(ctypes.c_float)]),
+    "tfx_stft_frames": (_i32, [_i64, _i32, _i32, _i32, ctypes.POINTER(_i64)]),
+    "tfx_stft": (_i32, [_vp, _i64, _i64, _i64, _i32, _i32, _vp, _i32, _i32, _i32, _vp, _vp]),
+    "tfx_istft_workspace_size": (_i32, [_i64, _i64, _i32, ctypes.POINTER(_sz)]),
+    "tfx_istft": (_i32, [_vp, _i64, _i64, _i32, _i32, _vp, _i32, _i32, _i32, _vp, _i64, _i64, _vp, _sz, _vp]),
     "tfx_sos_backward_workspace_size": (_i32, [_i64, _i64, _i32, ctypes.POINTER(_sz)]),
     "tfx_sos_backward": (_i32, [_vp, _vp, _vp, _i64, _i64, _i64, _i64, _i64, _vp, _i32, _vp, _vp, _vp, _sz,
                                 _vp]),

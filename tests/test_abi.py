@@ -165,3 +165,39 @@ def test_stream_argument_validation():
     # state out overlapping a signal
     assert _st("tfx_chain_stream", x, y, 2, 100, 100, 100, st, 2, 0, 200, None, None, None, y + 40, FAKE, wsb,
                None) == "TFX_E_ALIAS"
+
+
+def test_stft_argument_validation():
+    x, spec = FAKE, FAKE + (1 << 30)
+    T = ctypes.c_int64()
+    assert _st("tfx_stft_frames", 1000, 256, 64, 1, ctypes.byref(T)) == "TFX_OK" and T.value == 1 + 1000 // 64
+    assert _st("tfx_stft_frames", 1000, 256, 64, 0, ctypes.byref(T)) == "TFX_OK" and T.value == 1 + 744 // 64
+    assert _st("tfx_stft_frames", 100, 256, 64, 0, ctypes.byref(T)) == "TFX_OK" and T.value == 0
+    # n_fft not a power of two / out of range, hop 0, window longer than the frame
+    for n_fft in (400, 8, 8192):
+        assert _st("tfx_stft", x, 1, 1000, 1000, n_fft, 64, None, n_fft, 1, 0, spec, None) == "TFX_E_UNSUPPORTED"
+    assert _st("tfx_stft", x, 1, 1000, 1000, 256, 0, None, 256, 1, 0, spec, None) == "TFX_E_INVALID_ARG"
+    assert _st("tfx_stft", x, 1, 1000, 1000, 256, 64, None, 257, 1, 0, spec, None) == "TFX_E_INVALID_ARG"
+    # reflect padding needs more than n_fft/2 samples
+    assert _st("tfx_stft", x, 1, 128, 128, 256, 64, None, 256, 1, 0, spec, None) == "TFX_E_INVALID_ARG"
+    # spectrum overlapping the signal
+    assert _st("tfx_stft", x, 2, 1000, 1000, 256, 64, None, 256, 1, 0, x + 64, None) == "TFX_E_ALIAS"
+    # no frames: nothing to do
+    assert _st("tfx_stft", x, 1, 100, 100, 256, 64, None, 256, 0, 0, spec, None) == "TFX_OK"
+
+
+def test_istft_argument_validation_and_workspace():
+    n = ctypes.c_size_t()
+    assert _st("tfx_istft_workspace_size", 3, 10, 256, ctypes.byref(n)) == "TFX_OK" and n.value == 3 * 10 * 256 * 4
+    assert _st("tfx_istft_workspace_size", 3, 0, 256, ctypes.byref(n)) == "TFX_E_INVALID_ARG"
+    spec, y, ws = FAKE, FAKE + (1 << 30), FAKE + (1 << 31)
+    need = 2 * 10 * 256 * 4
+    assert _st("tfx_istft", spec, 2, 10, 256, 64, None, 256, 1, 0, y, -1, 1000, ws, need - 4, None) == "TFX_E_WORKSPACE"
+    assert _st("tfx_istft", spec, 2, 10, 256, 64, None, 256, 1, 0, y, -1, 100, ws, need, None) == "TFX_E_INVALID_ARG"
+    assert _st("tfx_istft", spec, 2, 0, 256, 64, None, 256, 1, 0, y, -1, 1000, ws, need, None) == "TFX_E_INVALID_ARG"
+    assert _st("tfx_istft", spec, 2, 10, 256, 64, None, 256, 1, 0, spec + 8, -1, 1000, ws, need,
+               None) == "TFX_E_ALIAS"
+    assert _st("tfx_istft", spec, 2, 10, 256, 64, None, 256, 1, 0, y, -1, 1000, y + 256, need, None) == "TFX_E_ALIAS"
+    assert _st("tfx_istft", spec, 2, 10, 300, 64, None, 256, 1, 0, y, -1, 1000, ws, need, None) == "TFX_E_UNSUPPORTED"
+    # zero-length output: nothing to do
+    assert _st("tfx_istft", spec, 2, 10, 256, 64, None, 256, 1, 0, y, 0, 0, None, 0, None) == "TFX_OK"

@@ -105,3 +105,12 @@ def test_frame_counts():
     assert S.num_frames(1000, 256, 64, True) == 1 + 1000 // 64
     assert S.num_frames(1000, 256, 64, False) == 1 + (1000 - 256) // 64
     assert S.num_frames(100, 256, 64, False) == 0
+
+
+def test_single_frame_helper_agrees_with_the_framed_transform():
+    g = np.random.default_rng(4)
+    x = g.standard_normal(3000)
+    for center in (True, False):
+        X = S.stft(x, 256, 77, S.hann(200), center=center, normalized=True)
+        for t in (0, 5, X.shape[0] - 1):
+            assert np.max(np.abs(S.frame(x, 256, 77, S.hann(200), center, t, True) - X[t])) < 1e-12
