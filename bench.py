@@ -21,8 +21,9 @@ sections).
 Unless --quick, the other workloads are measured once each (context, in
 "secondary"): the short chain, the 8191-tap FIR by FFT (fp32) and by the
 matrix-core Toeplitz product (bf16, fp16, split bf16), the ragged batch of
-256 clips (autotuned single launch, against one tfx_sos call per clip), and
-the differentiable workload's forward + backward.  Low-precision errors are
+256 clips (autotuned single launch, against one tfx_sos call per clip), the
+differentiable workload's forward + backward, the Wave pipe, streaming
+blocks, and the STFT / inverse STFT of the headline signal.  Low-precision errors are
 measured against the oracle on sampled outputs.
 
 The CPU baseline runs the FP64 oracle (test infrastructure: plain C, one
@@ -234,6 +235,49 @@ def secondary(torch, dev, stream):
                                  "rel_err_vs_oracle": rel_err(y, O.chain(w.x[:, :nb * blk], w.stages)),
                                  "tolerance": 1e-4}
     out["stream"] = res
+    del x
+
+    log("stft")
+    from oracle import stft as OS
+    from paper_2504_08624_amd import lib, spectral
+    w = workloads.chain_mid()
+    x = torch.from_numpy(w.x).to(dev)
+    C, N = x.shape
+    n_fft, hop = 2048, 512
+    T = spectral.num_frames(N, n_fft, hop, True)
+    F = n_fft // 2 + 1
+    win_np = OS.hann(n_fft).astype(np.float32)
+    win = torch.from_numpy(win_np).to(dev)
+    spec = torch.empty((C, T, F), dtype=torch.complex64, device=dev)
+    yi = torch.empty_like(x)
+    sp = stream.cuda_stream
+
+    def fwd():
+        lib.call("tfx_stft", x.data_ptr(), C, N, N, n_fft, hop, win.data_ptr(), n_fft, 1, 0, spec.data_ptr(), sp)
+
+    def inv():
+        lib.call("tfx_istft", spec.data_ptr(), C, T, n_fft, hop, win.data_ptr(), n_fft, 1, 0, yi.data_ptr(), N, N, sp)
+    s_f = timed(torch, fwd, 20, stream)
+    s_i = timed(torch, inv, 20, stream)
+    fwd()
+    inv()
+    g = np.random.default_rng(9)
+    picks = [(int(g.integers(C)), int(g.integers(T))) for _ in range(16)] + [(0, 0), (C - 1, T - 1)]
+    got = np.stack([spec[c, t].cpu().numpy() for c, t in picks])
+    ref = np.stack([OS.frame(w.x[c], n_fft, hop, win_np, True, t) for c, t in picks])
+    e_f = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+    e_i = rel_err(yi[:, :200000].cpu().numpy(), w.x[:, :200000])
+    b_f = C * N * 4 + C * T * F * 8
+    b_i = C * T * F * 8 + C * N * 4
+    out["stft"] = {"workload": "8 x 5,760,000 (chain_mid's signal), n_fft 2048, hop 512, periodic Hann, centred",
+                   "frames": T,
+                   "stft": {"ms": round(s_f * 1e3, 4), "Msamples_per_s": round(C * N / s_f / 1e6, 1),
+                            "alg_GBps": round(b_f / s_f / 1e9, 1), "hbm_frac": round(b_f / s_f / 1e9 / HBM_PEAK_GBS, 4),
+                            "rel_err_18_frames": e_f, "tolerance": 1e-5},
+                   "istft": {"ms": round(s_i * 1e3, 4), "Msamples_per_s": round(C * N / s_i / 1e6, 1),
+                             "alg_GBps": round(b_i / s_i / 1e9, 1),
+                             "hbm_frac": round(b_i / s_i / 1e9 / HBM_PEAK_GBS, 4),
+                             "round_trip_rel_err": e_i, "tolerance": 1e-5}}
     return out
 
 

@@ -319,12 +319,13 @@ tfx_status tfx_stft(const float *x, int64_t C, int64_t N, int64_t ldx, int32_t n
  * the covered range, and samples whose summed squared window is <= 1e-11,
  * are written as 0 (callers that need torch's error on a vanishing
  * envelope check the window themselves).  spec: [C][T][n_fft/2+1] complex,
- * T >= 1; y: [C][length], row stride ldy; workspace (the windowed frames)
- * from tfx_istft_workspace_size. */
-tfx_status tfx_istft_workspace_size(int64_t C, int64_t T, int32_t n_fft, size_t *bytes);
+ * T >= 1; y: [C][length], row stride ldy, not overlapping spec; length <
+ * 2^38.  Each workgroup owns a segment of output samples, inverts the frames
+ * that touch it and accumulates them in LDS, so nothing but y is written and
+ * no workspace is needed. */
 tfx_status tfx_istft(const float *spec, int64_t C, int64_t T, int32_t n_fft, int32_t hop, const float *window,
                      int32_t win_length, int32_t center, int32_t normalized, float *y, int64_t length, int64_t ldy,
-                     void *ws, size_t ws_bytes, void *stream);
+                     void *stream);
 
 #ifdef __cplusplus
 }

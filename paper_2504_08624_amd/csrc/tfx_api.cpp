@@ -705,17 +705,9 @@ tfx_status tfx_stft(const float *x, int64_t C, int64_t N, int64_t ldx, int32_t n
     return e == hipSuccess ? ok() : hip_fail(e, "stft kernel");
 }
 
-tfx_status tfx_istft_workspace_size(int64_t C, int64_t T, int32_t n_fft, size_t *bytes) {
-    if (!bytes) return fail(TFX_E_INVALID_ARG, "bytes is NULL");
-    if (C < 1 || T < 1) return fail(TFX_E_INVALID_ARG, "C and T must be >= 1");
-    if (stft_log2(n_fft) < 0) return fail(TFX_E_UNSUPPORTED, "n_fft must be a power of two in [16, 4096]");
-    *bytes = (size_t)C * (size_t)T * (size_t)n_fft * sizeof(float);
-    return ok();
-}
-
 tfx_status tfx_istft(const float *spec, int64_t C, int64_t T, int32_t n_fft, int32_t hop, const float *window,
                      int32_t win_length, int32_t center, int32_t normalized, float *y, int64_t length, int64_t ldy,
-                     void *ws, size_t ws_bytes, void *stream) {
+                     void *stream) {
     tfx::StftPlan sp{};
     tfx_status s = stft_params(n_fft, hop, win_length, &sp.log2n);
     if (s) return s;
@@ -727,12 +719,8 @@ tfx_status tfx_istft(const float *spec, int64_t C, int64_t T, int32_t n_fft, int
     if (ldy < length) return fail(TFX_E_INVALID_ARG, "ldy must be >= length");
     if (length == 0) return ok();
     if (!spec || !y) return fail(TFX_E_INVALID_ARG, "spec and y must be non-null");
-    const size_t need = (size_t)C * (size_t)T * (size_t)n_fft * sizeof(float);
-    if ((s = check_ws(ws, ws_bytes, need))) return s;
     const size_t sbytes = (size_t)C * (size_t)T * (size_t)(n_fft / 2 + 1) * 2 * sizeof(float);
     if (overlaps(y, span_bytes(C, length, ldy), spec, sbytes)) return fail(TFX_E_ALIAS, "y overlaps spec");
-    if (overlaps(y, span_bytes(C, length, ldy), ws, need) || overlaps(spec, sbytes, ws, need))
-        return fail(TFX_E_ALIAS, "the workspace overlaps spec or y");
     sp.hop = hop;
     sp.win_length = win_length;
     sp.center = center ? 1 : 0;
@@ -741,13 +729,12 @@ tfx_status tfx_istft(const float *spec, int64_t C, int64_t T, int32_t n_fft, int
     sp.C = C;
     sp.T = T;
     sp.spec_in = spec;
-    sp.frames = static_cast<float *>(ws);
     sp.y = y;
     sp.length = length;
     sp.ldy = ldy;
     sp.stream = static_cast<hipStream_t>(stream);
     hipError_t e = tfx::launch_istft(sp);
-    return e == hipSuccess ? ok() : hip_fail(e, "istft kernels");
+    return e == hipSuccess ? ok() : hip_fail(e, "istft kernel");
 }
 
 }  // extern "C"

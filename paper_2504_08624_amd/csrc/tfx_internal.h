@@ -234,7 +234,6 @@ struct StftPlan {
     float *spec;            // [C][T][n_fft/2+1] complex (re, im)
     // inverse
     const float *spec_in;
-    float *frames;          // workspace [C][T][n_fft]
     float *y;
     int64_t length, ldy;
     hipStream_t stream;

@@ -77,8 +77,7 @@ _SIGS = {
                                     ctypes.POINTER(ctypes.c_float)]),
     "tfx_stft_frames": (_i32, [_i64, _i32, _i32, _i32, ctypes.POINTER(_i64)]),
     "tfx_stft": (_i32, [_vp, _i64, _i64, _i64, _i32, _i32, _vp, _i32, _i32, _i32, _vp, _vp]),
-    "tfx_istft_workspace_size": (_i32, [_i64, _i64, _i32, ctypes.POINTER(_sz)]),
-    "tfx_istft": (_i32, [_vp, _i64, _i64, _i32, _i32, _vp, _i32, _i32, _i32, _vp, _i64, _i64, _vp, _sz, _vp]),
+    "tfx_istft": (_i32, [_vp, _i64, _i64, _i32, _i32, _vp, _i32, _i32, _i32, _vp, _i64, _i64, _vp]),
     "tfx_sos_backward_workspace_size": (_i32, [_i64, _i64, _i32, ctypes.POINTER(_sz)]),
     "tfx_sos_backward": (_i32, [_vp, _vp, _vp, _i64, _i64, _i64, _i64, _i64, _vp, _i32, _vp, _vp, _vp, _sz,
                                 _vp]),

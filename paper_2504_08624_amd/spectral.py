@@ -17,7 +17,7 @@ import numpy as np
 import torch
 
 from . import lib
-from .functional import _ptr, _signal, _stream, _workspace
+from .functional import _ptr, _signal, _stream
 
 
 def _window(window, win_length: int, device):
@@ -105,9 +105,6 @@ def istft(spec: torch.Tensor, n_fft: int, hop_length=None, win_length=None, wind
         raise ValueError("window overlap-add is zero somewhere (NOLA fails)")
     w = _window(window, wl, spec.device)
     y = torch.empty((C, L), dtype=torch.float32, device=spec.device)
-    nb = lib.size_out()
-    lib.call("tfx_istft_workspace_size", C, T, n_fft, ctypes.byref(nb))
-    ws, wsb = _workspace(nb.value, spec.device)
     lib.call("tfx_istft", fm.data_ptr(), C, T, n_fft, hop, _ptr(w), wl, int(bool(center)), int(bool(normalized)),
-             y.data_ptr() if L else None, L, max(L, 1), _ptr(ws), wsb, _stream(spec.device))
+             y.data_ptr() if L else None, L, max(L, 1), _stream(spec.device))
     return y[0] if squeeze else y
