@@ -85,6 +85,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--quick", action="store_true", help="headline workload only")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--stft-only", action="store_true", help="only the STFT leg (for kernel profiles)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also time a plain device copy of the headline input (counter calibration)")
     return ap.parse_args()
@@ -237,6 +238,14 @@ def secondary(torch, dev, stream):
     out["stream"] = res
     del x
 
+    out["stft"] = stft_leg(torch, dev, stream)
+    return out
+
+
+def stft_leg(torch, dev, stream):
+    """STFT and inverse STFT of the headline signal (n_fft 2048, hop 512,
+    periodic Hann, centred), timed through the C ABI on resident buffers."""
+    from paper_2504_08624_amd import workloads
     log("stft")
     from oracle import stft as OS
     from paper_2504_08624_amd import lib, spectral
@@ -269,16 +278,14 @@ def secondary(torch, dev, stream):
     e_i = rel_err(yi[:, :200000].cpu().numpy(), w.x[:, :200000])
     b_f = C * N * 4 + C * T * F * 8
     b_i = C * T * F * 8 + C * N * 4
-    out["stft"] = {"workload": "8 x 5,760,000 (chain_mid's signal), n_fft 2048, hop 512, periodic Hann, centred",
-                   "frames": T,
-                   "stft": {"ms": round(s_f * 1e3, 4), "Msamples_per_s": round(C * N / s_f / 1e6, 1),
-                            "alg_GBps": round(b_f / s_f / 1e9, 1), "hbm_frac": round(b_f / s_f / 1e9 / HBM_PEAK_GBS, 4),
-                            "rel_err_18_frames": e_f, "tolerance": 1e-5},
-                   "istft": {"ms": round(s_i * 1e3, 4), "Msamples_per_s": round(C * N / s_i / 1e6, 1),
-                             "alg_GBps": round(b_i / s_i / 1e9, 1),
-                             "hbm_frac": round(b_i / s_i / 1e9 / HBM_PEAK_GBS, 4),
-                             "round_trip_rel_err": e_i, "tolerance": 1e-5}}
-    return out
+    return {"workload": "8 x 5,760,000 (chain_mid's signal), n_fft 2048, hop 512, periodic Hann, centred",
+            "frames": T,
+            "stft": {"ms": round(s_f * 1e3, 4), "Msamples_per_s": round(C * N / s_f / 1e6, 1),
+                     "alg_GBps": round(b_f / s_f / 1e9, 1), "hbm_frac": round(b_f / s_f / 1e9 / HBM_PEAK_GBS, 4),
+                     "rel_err_18_frames": e_f, "tolerance": 1e-5},
+            "istft": {"ms": round(s_i * 1e3, 4), "Msamples_per_s": round(C * N / s_i / 1e6, 1),
+                      "alg_GBps": round(b_i / s_i / 1e9, 1), "hbm_frac": round(b_i / s_i / 1e9 / HBM_PEAK_GBS, 4),
+                      "round_trip_rel_err": e_i, "tolerance": 1e-5}}
 
 
 def main():
@@ -297,6 +304,9 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.stft_only:
+        print(json.dumps({"stft": stft_leg(torch, dev, torch.cuda.current_stream(dev))}))
+        return
     log("generating chain_mid inputs (8 x 5,760,000)")
     w = workloads.chain_mid()
     C, N = w.x.shape
