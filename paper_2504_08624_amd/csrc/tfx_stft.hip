@@ -369,14 +369,16 @@ __global__ __launch_bounds__(SWG, LOG2N == 4 ? 3 : 4) void stft_kernel(StftArgs 
     }
 }
 
-// Output samples per unit of the inverse: longer segments recompute fewer
-// boundary frames (a fraction (n_fft - hop) / SEG of the frames is computed
-// twice) at the price of LDS.
 constexpr int ENV_TAB = 512;  // hops up to this length use the periodic envelope table
 
+// Output samples per unit of the inverse and resident workgroups per CU:
+// longer segments recompute fewer boundary frames (a fraction
+// (n_fft - hop) / LEN of the frames is inverted twice) but take more LDS.
+// Chosen by measurement on the 8 x 5.76 M signal at hop = n_fft / 4.
 template <int LOG2N>
 struct Seg {
-    static constexpr int LEN = (1 << LOG2N) > 2048 ? 2 * (1 << LOG2N) : 4096;
+    static constexpr int LEN = LOG2N >= 11 ? 8192 : (LOG2N >= 9 ? 2048 : 4096);
+    static constexpr int PER_CU = LOG2N >= 11 ? 2 : 3;
 };
 
 // Inverse: each unit is a segment of one channel's output.  The frames that
@@ -385,7 +387,7 @@ struct Seg {
 // the other (fixed order); each sample is then divided by its summed squared
 // window.
 template <int LOG2N>
-__global__ __launch_bounds__(SWG, LOG2N >= 12 ? 2 : 3) void istft_kernel(StftArgs a) {
+__global__ __launch_bounds__(SWG, Seg<LOG2N>::PER_CU) void istft_kernel(StftArgs a) {
     using S = Shape<LOG2N>;
     constexpr int N = S::N, G = S::G, F = S::F, SEG = Seg<LOG2N>::LEN;
     constexpr int NW = N >= SWG ? N / SWG : 1;  // frame samples per lane in the overlap-add
@@ -534,7 +536,7 @@ StftArgs make_args(const StftPlan &sp) {
 }
 
 int batch_of(int log2n) { return (1 << log2n) >= TOTMIN ? 1 : TOTMIN >> log2n; }
-int seg_of(int log2n) { return (1 << log2n) > 2048 ? 2 << log2n : 4096; }
+int seg_of(int log2n) { return log2n >= 11 ? 8192 : (log2n >= 9 ? 2048 : 4096); }
 
 dim3 unit_grid(int64_t units, int per_cu) {
     // enough workgroups for per_cu resident per CU, in eight equal XCD shares
@@ -572,7 +574,7 @@ hipError_t launch_istft(const StftPlan &sp) {
     const int seg = seg_of(sp.log2n);
     a.nseg = (sp.length + seg - 1) / seg;
     a.units = sp.C * a.nseg;
-    TFX_STFT_SWITCH(istft_kernel, sp.log2n, unit_grid(a.units, 3), sp.stream, a);
+    TFX_STFT_SWITCH(istft_kernel, sp.log2n, unit_grid(a.units, sp.log2n >= 11 ? 2 : 3), sp.stream, a);
     return hipGetLastError();
 }
 

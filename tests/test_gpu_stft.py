@@ -146,3 +146,27 @@ def test_full_size_audio_signal_sampled_frames():
     got = np.stack([Xc[c, t].cpu().numpy() for c, t in picks])
     ref = np.stack([OS.frame(x[c], n_fft, hop, w, True, t) for c, t in picks])
     assert_close(_ri(got[None]), _ri(ref[None]), TOL, "sampled frames")
+
+
+def test_row_strides_through_the_c_abi():
+    """Input rows with a stride larger than their length (a column slice) and
+    an output with a padded row stride, called through the C ABI directly."""
+    from paper_2504_08624_amd import lib
+    C, N, n_fft, hop = 3, 7000, 512, 160
+    wide = _x(C, N + 333, (605,))
+    w = OS.hann(n_fft).astype(np.float32) + 0.05
+    xt = torch.from_numpy(wide).to(DEV)[:, :N]
+    assert xt.stride(0) == N + 333
+    X = tfx.stft(xt, n_fft, hop, window=torch.from_numpy(w))
+    ref = OS.stft(wide[:, :N], n_fft, hop, w, True)
+    assert_close(_ri(_cpu(X).transpose(0, 2, 1)), _ri(ref), TOL, "strided input")
+    T = ref.shape[1]
+    spec = torch.from_numpy(ref.astype(np.complex64)).to(DEV).contiguous()
+    wt = torch.from_numpy(w).to(DEV)
+    ldy = N + 100
+    y = torch.full((C, ldy), 7.0, dtype=torch.float32, device=DEV)
+    lib.call("tfx_istft", spec.data_ptr(), C, T, n_fft, hop, wt.data_ptr(), n_fft, 1, 0, y.data_ptr(), N, ldy,
+             torch.cuda.current_stream().cuda_stream)
+    yy = _cpu(y)
+    assert_close(yy[:, :N], OS.istft(ref.astype(np.complex64), n_fft, hop, w, True, length=N), TOL, "strided output")
+    assert np.all(yy[:, N:] == 7.0)   # the row padding is left alone
