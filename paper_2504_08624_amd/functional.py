@@ -13,9 +13,10 @@ from __future__ import annotations
 
 import ctypes
 
+import numpy as np
 import torch
 
-from . import lib
+from . import design, lib
 
 
 def _signal(x: torch.Tensor):
@@ -347,8 +348,6 @@ def lfilter(x: torch.Tensor, b, a, compute: str = "f32") -> torch.Tensor:
     (roots paired nearest-zero-to-pole) and run as one fused chain; a
     denominator of length 1 is a plain FIR.  An unstable denominator (a pole
     on or outside the unit circle) is an error.  Differentiable in x."""
-    import numpy as np
-    from . import design
     bb = np.atleast_1d(np.asarray(b, dtype=np.float64))
     aa = np.trim_zeros(np.atleast_1d(np.asarray(a, dtype=np.float64)), "b")
     if aa.size == 0 or aa[0] == 0.0:
