@@ -174,30 +174,29 @@ __global__ __launch_bounds__(WG, 3) void sos_bwd_kernel(BArgs a) {
     float gr[L];
     load_chunk(stg, mc, gr);
 
-    // 4. sections in reverse order
+    // 4. sections in reverse order.  xo holds the output of section s over
+    //    chunk mc: the input rebuilt for section s + 1 in the previous
+    //    iteration (for the last section it is computed once), so the state
+    //    s1 before sample r is xo[r] - b0 xs[r] (y = b0 x + s1) without a
+    //    further pass.
+    float xo[L];
     for (int s = S - 1; s >= 0; --s) {
         const SecLds &tb = s_tab[s];
         const float b0 = tb.coef[0], b1 = tb.coef[1], b2 = tb.coef[2], a1 = tb.coef[3], a2 = tb.coef[4];
         const float B0 = fmaf(-a1, b0, b1), B1 = fmaf(-a2, b0, b2);
-        // (a) input of section s over chunk mc, and s1 before every sample
-        float xs[L], sf[L];
+        // (a) input of section s over chunk mc
+        float xs[L];
 #pragma unroll
         for (int r = 0; r < L; ++r) xs[r] = fr[r];
         for (int j = 0; j < s; ++j) {
             const float2 st = sig[j * GL + mc];
             tdf2_chunk(xs, s_tab[j].coef, st.x, st.y);
         }
-        {
-            const float2 st = sig[s * GL + mc];
-            float s1 = st.x, s2 = st.y;
+        if (s == S - 1) {
 #pragma unroll
-            for (int r = 0; r < L; ++r) {
-                const float xv = xs[r];
-                sf[r] = s1;
-                const float yv = fmaf(b0, xv, s1);
-                s1 = fmaf(b1, xv, fmaf(-a1, yv, s2));
-                s2 = fmaf(b2, xv, -a2 * yv);
-            }
+            for (int r = 0; r < L; ++r) xo[r] = xs[r];
+            const float2 st = sig[s * GL + mc];
+            tdf2_chunk(xo, tb.coef, st.x, st.y);
         }
         // (b) adjoint zero-state response of the chunk, last sample first
         float m0 = 0.f, m1 = 0.f;
@@ -238,8 +237,9 @@ __global__ __launch_bounds__(WG, 3) void sos_bwd_kernel(BArgs a) {
         for (int r = L - 1; r >= 0; --r) {
             const float gv = gr[r];
             const float gx = fmaf(b0, gv, fmaf(B0, m0, B1 * m1));
-            dA00 = fmaf(m0, sf[r], dA00);
-            dA10 = fmaf(m1, sf[r], dA10);
+            const float sf = fmaf(-b0, xs[r], xo[r]);  // s1 before sample r
+            dA00 = fmaf(m0, sf, dA00);
+            dA10 = fmaf(m1, sf, dA10);
             dB0 = fmaf(m0, xs[r], dB0);
             dB1 = fmaf(m1, xs[r], dB1);
             dD = fmaf(gv, xs[r], dD);
@@ -248,6 +248,8 @@ __global__ __launch_bounds__(WG, 3) void sos_bwd_kernel(BArgs a) {
             m0 = n0v;
             gr[r] = gx;
         }
+#pragma unroll
+        for (int r = 0; r < L; ++r) xo[r] = xs[r];  // output of section s - 1
         // (e) group sums, in a fixed order
         double red[5] = {(double)dA00, (double)dA10, (double)dB0, (double)dB1, (double)dD};
 #pragma unroll
