@@ -13,7 +13,11 @@ build (tfx_chain_prepare) followed by the fused filter kernel
 synchronisations; `value` is channel-samples per second of the whole step.
 HIP events recorded on the launch stream around every tfx_chain_run give the
 fused kernel's average duration for the roofline (algorithmic bytes = 8 B
-per channel-sample: read x once, write y once).  The same loop is then timed
+per channel-sample: read x once, write y once; the bracket also holds the
+FP64-carry variant's launch, which exits at once); events around every step
+give its median and spread, ten more steps run "cold" (512 MB written before
+each, more than the last-level cache holds), and a plain device copy of the
+input gives the achievable bandwidth the HBM figure is also quoted against.  The same loop is then timed
 for forward + backward (forward with tile checkpoints, then the adjoint of
 the chain for a fixed upstream gradient: gradients of input, taps and
 sections).
@@ -87,7 +91,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--stft-only", action="store_true", help="only the STFT leg (for kernel profiles)")
     ap.add_argument("--copy-probe", action="store_true",
-                    help="also time a plain device copy of the headline input (counter calibration)")
+                    help="accepted for older profile commands; the device copy of the input is always timed")
     return ap.parse_args()
 
 
@@ -337,9 +341,11 @@ def main():
 
     K = args.steps
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(K)]
+    ev0 = [torch.cuda.Event(enable_timing=True) for _ in range(K)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(K):
+        ev0[i].record(stream)
         prepare()
         ev[i][0].record(stream)
         run()
@@ -348,7 +354,24 @@ def main():
     t1 = time.perf_counter()
     wall = t1 - t0
     kern_ms = np.array([a.elapsed_time(b) for a, b in ev])
+    step_ms = np.array([a.elapsed_time(b[1]) for a, b in zip(ev0, ev)])
     log("timed %d forward steps in %.3f s" % (K, wall))
+
+    # cold steps: 512 MB written between steps so no input is left in the
+    # 256 MB last-level cache (the headline input is 184 MB)
+    flush = torch.empty(128 * 1024 * 1024, dtype=torch.float32, device=dev)
+    cold = []
+    for i in range(10):
+        flush.fill_(float(i))
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        prepare()
+        run()
+        b.record(stream)
+        torch.cuda.synchronize()
+        cold.append(a.elapsed_time(b))
+    del flush
+    log("timed 10 cold steps")
 
     samples = C * N
     ms_step = wall / K * 1e3
@@ -362,20 +385,20 @@ def main():
     achieved_tfs = alg_flops / kern_s / 1e12
     out = y.cpu().numpy()
 
-    copy = None
-    if args.copy_probe:
-        z = torch.empty_like(x)
-        for _ in range(3):
-            z.copy_(x)
-        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        a.record(stream)
-        for _ in range(10):
-            z.copy_(x)
-        b.record(stream)
-        torch.cuda.synchronize()
-        cs = a.elapsed_time(b) / 10 / 1e3
-        copy = {"bytes": 2 * 4 * samples, "us": round(cs * 1e6, 2), "GB/s": round(2 * 4 * samples / cs / 1e9, 1)}
-        del z
+    # achievable copy bandwidth: a plain device copy of the input (also the
+    # calibration of the HBM counters)
+    z = torch.empty_like(x)
+    for _ in range(3):
+        z.copy_(x)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    for _ in range(10):
+        z.copy_(x)
+    b.record(stream)
+    torch.cuda.synchronize()
+    cs = a.elapsed_time(b) / 10 / 1e3
+    copy = {"bytes": 2 * 4 * samples, "us": round(cs * 1e6, 2), "GBps": round(2 * 4 * samples / cs / 1e9, 1)}
+    del z
 
     # forward + backward on the same workload
     st = [(k, t) for (k, _), t in zip(w.stages, kept)]
@@ -442,7 +465,12 @@ def main():
                      "kernel": "chain_kernel<FIR_FFT, true>", "kernel_us": round(kern_s * 1e6, 2),
                      "alg_flops_per_launch": alg_flops, "alg_flops_per_sample": round(fps, 2),
                      "alg_bytes_per_launch": alg_bytes, "hbm_achieved_GBps": round(achieved_gbs, 2),
-                     "hbm_peak_GBps": HBM_PEAK_GBS, "hbm_frac": round(achieved_gbs / HBM_PEAK_GBS, 4)},
+                     "hbm_peak_GBps": HBM_PEAK_GBS, "hbm_frac": round(achieved_gbs / HBM_PEAK_GBS, 4),
+                     "copy_GBps": copy["GBps"], "hbm_frac_of_copy": round(achieved_gbs / copy["GBps"], 4)},
+        "step_stats_ms": {"median": round(float(np.median(step_ms)), 4), "mean": round(float(step_ms.mean()), 4),
+                          "sd": round(float(step_ms.std(ddof=1)) if K > 1 else 0.0, 4),
+                          "cold_median": round(float(np.median(cold)), 4),
+                          "timing": "HIP events per step on the launch stream; cold = 512 MB written before each"},
         "fwd_bwd": fwd_bwd_rec,
         "cpu_baseline": cpu,
         "max_rel_err_vs_oracle": err,
@@ -450,8 +478,7 @@ def main():
     }
     if sec is not None:
         rec["secondary"] = sec
-    if copy is not None:
-        rec["copy_probe"] = copy
+    rec["copy"] = copy
     print(json.dumps(rec), flush=True)
 
 
