@@ -441,6 +441,11 @@ def main():
                "kind": "oracle",
                "sample": "the whole headline input (8 x 5,760,000), whole chain, FP64, %.1f s" % (c1 - c0)}
         err = rel_err(out[:, :Ns], ref)
+        c0 = time.perf_counter()
+        O.chain(w.x[:1, :Ns], w.stages)  # one channel: one thread
+        c1 = time.perf_counter()
+        cpu["single_thread"] = {"value": round(Ns / (c1 - c0) / 1e6, 3), "unit": "Msamples/s",
+                                "sample": "channel 0 (5,760,000 samples), whole chain, FP64, %.1f s" % (c1 - c0)}
 
     rec = {
         "metric": "Msamples/s (ch x samples) fwd and fwd+bwd, % HBM roofline, at stated error",
