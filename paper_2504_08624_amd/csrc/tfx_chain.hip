@@ -99,6 +99,7 @@ struct KArgs {
     const float2 *hspec;  // [nparts][4096] spectra of the tap partitions / 4096
     int32_t nparts;
     const CascTab *casc;  // cascade tile-transition powers (cascade-level look-back)
+    const CascZir *zir;   // zero-input response tables of the cascade
     const void *tzb;      // fused Toeplitz FIR: B operand table [2 Q][64][8]
     int32_t tzQ;          // its frame lags Q
     const float *hist;    // streaming: the M - 1 FIR inputs before the block, [C][M - 1] (null = zeros)
@@ -385,8 +386,50 @@ __device__ void run_section(const KArgs &a, const TB &tb, int s, float (&v)[L], 
 // section again from its now known tile-entering state, with no look-back.
 // This trades a second in-tile pass for S - 1 fewer cross-tile round trips,
 // which dominate the per-section form.
+// Completes a tile of a cascade-level cascade: v holds the response to a zero
+// tile-entering state (phase A), P (D = 2S floats, LDS) the state entering
+// the tile.  By linearity the output at sample r of chunk k gains
+// G[r] . (F^(L k) P): the entering state carried k chunks into the tile,
+// then through the cascade to its output, with no further pass per section.
+template <int D>
+__device__ __forceinline__ void casc_zir_add(float (&v)[L], const CascZir *zt, const float *P, int k) {
+    float p[D];
+#pragma unroll
+    for (int j = 0; j < D; ++j) p[j] = P[j];
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+        float zi = 0.f;  // component i of F^(L k) P; F is block lower triangular, and so are its powers
+#pragma unroll
+        for (int j = 0; j < (i | 1) + 1; ++j) zi = fmaf(zt->M[i][j][k], p[j], zi);
+#pragma unroll
+        for (int r = 0; r < L; ++r) v[r] = fmaf(zt->G[r][i], zi, v[r]);
+    }
+}
+
+// Cascades up to ZIR_MAX sections (larger ones would cost the kernel
+// registers, hence occupancy) use the zero-input response tables.
+constexpr int ZIR_MAX = 6;
+
+__device__ __forceinline__ void casc_zir(float (&v)[L], const CascZir *zt, const float *P, int k, int S) {
+    switch (S) {
+    case 1: casc_zir_add<2>(v, zt, P, k); break;
+    case 2: casc_zir_add<4>(v, zt, P, k); break;
+    case 3: casc_zir_add<6>(v, zt, P, k); break;
+    case 4: casc_zir_add<8>(v, zt, P, k); break;
+    case 5: casc_zir_add<10>(v, zt, P, k); break;
+    default: casc_zir_add<12>(v, zt, P, k); break;
+    }
+}
+
+// Workgroups per CU the variants with the table form are held to (four
+// waves per SIMD: at most 128 registers).
 template <int FIRM, bool HAS_SOS, bool HIQ, bool CASC, bool STOUT>
-__global__ __launch_bounds__(WG) void chain_kernel(KArgs a) {
+constexpr int chain_min_blocks() {
+    return (HAS_SOS && CASC && !HIQ && !STOUT && (FIRM == FIR_NONE || FIRM == FIR_FFT)) ? 4 : 1;
+}
+
+template <int FIRM, bool HAS_SOS, bool HIQ, bool CASC, bool STOUT>
+__global__ __launch_bounds__(WG, (chain_min_blocks<FIRM, HAS_SOS, HIQ, CASC, STOUT>())) void chain_kernel(KArgs a) {
     __shared__ __align__(16) float lds[lds_floats<FIRM>()];
     __shared__ double s_agg[2 * GROUPS][GWAVES][2];
     __shared__ double s_pre[2 * GROUPS][2];
@@ -531,16 +574,13 @@ __global__ __launch_bounds__(WG) void chain_kernel(KArgs a) {
             const int k = e / DD, i = (e % DD) / D, j = e % D;
             cT[e] = a.casc->T[k][i][j];
         }
-        // (A) zero tile-entering state: the cascade's tile aggregate; the
-        //     last section only needs its state
+        // (A) zero tile-entering state: the cascade's tile aggregate and its
+        //     response to the tile's input
         float eA0 = 0.f, eA1 = 0.f;
         for (int s = 0; s < a.S; ++s) {
             float e0, e1, E0, E1;
             const int buf = (s & 1) * GROUPS + c.grp;
-            if (s + 1 < a.S)
-                casc_section_a<L, true>(s_tabc[s], v, c.lane, c.gw, s_agg, buf, e0, e1, E0, E1);
-            else
-                casc_section_a<L, false>(s_tabc[s], v, c.lane, c.gw, s_agg, buf, e0, e1, E0, E1);
+            casc_section_a<L, true>(s_tabc[s], v, c.lane, c.gw, s_agg, buf, e0, e1, E0, E1);
             if (s == 0) {
                 eA0 = e0;
                 eA1 = e1;
@@ -565,8 +605,15 @@ __global__ __launch_bounds__(WG) void chain_kernel(KArgs a) {
             if (a.ckpt && c.valid && c.lane < D) a.ckpt[(c.ch * a.ntiles + c.tile) * a.S * 2 + c.lane] = cP[c.lane];
         }
         __syncthreads();
-        // (C) every section from its known tile-entering state; section 0
-        //     reuses phase A's carry (its input is unchanged)
+        // (the table form costs registers: kept to the variants where it
+        // does not lower occupancy)
+        constexpr bool ZIR = !STOUT && (FIRM == FIR_NONE || FIRM == FIR_FFT || FIRM == FIR_FFT_PARTS);
+        if (ZIR && a.S <= ZIR_MAX) {
+            // (C) the entering state's zero-input response added to phase A's output
+            casc_zir(v, a.zir, cP, c.gl, a.S);
+        } else {
+        // (C') otherwise: every section from its known tile-entering state;
+        //     section 0 reuses phase A's carry (its input is unchanged)
         load_chunk(stg, c.gl, v);
         const int r_cap = c.gl == c.owner ? c.r_last : -1;
         for (int s = 0; s < a.S; ++s) {
@@ -588,6 +635,7 @@ __global__ __launch_bounds__(WG) void chain_kernel(KArgs a) {
                 a.state_out[(c.ch * a.S + s) * 2 + 0] = c1;
                 a.state_out[(c.ch * a.S + s) * 2 + 1] = c2;
             }
+        }
         }
     } else if (HAS_SOS) {
         c.is_last = STOUT && (c.tile == a.ntiles - 1);
@@ -632,6 +680,8 @@ WsLayout ws_layout(int64_t C, int64_t N, int32_t S, int32_t M_merged, int32_t n_
     off += al256(nrec * REC_WORDS * sizeof(uint64_t));
     w.casc = off;
     if (S > 0 && S <= CASC_MAX) off += al256(sizeof(CascTab));
+    w.zir = off;
+    if (S > 0 && S <= CASC_MAX) off += al256(sizeof(CascZir));
     w.taps = w.merge = off;
     if (n_fir > 1) {
         off += al256((size_t)M_merged * sizeof(float));
@@ -774,6 +824,7 @@ hipError_t launch_run(const ChainPlan &p) {
     k.hspec = reinterpret_cast<const float2 *>(ws + lay.hspec);
     k.nparts = fft_parts(Mtot);
     k.casc = reinterpret_cast<const CascTab *>(ws + lay.casc);
+    k.zir = reinterpret_cast<const CascZir *>(ws + lay.zir);
     k.hist = Mtot > 1 ? p.hist_in : nullptr;
     k.ldh = Mtot > 1 ? Mtot - 1 : 0;
     const int64_t nblocks = (lay.cpad / 2) * k.ntiles;

@@ -107,6 +107,16 @@ struct alignas(16) CascTab {
     int32_t pad[3];
     float T[3][16][16];  // Phi_T, Phi_T^2, Phi_T^4
 };
+// Zero-input response of a cascade (chain path): with F the per-sample
+// transition of the cascade state (D = 2S components) and c the row that
+// maps the state to the cascade output under zero input, G[r] = c F^r and
+// M[i][j][k] = (F^(L k))[i][j].  The output of a tile is its zero-entering-
+// state response plus G[r] . (F^(L k) P) at sample r of chunk k, P being the
+// state entering the tile.
+struct alignas(16) CascZir {
+    float G[L][16];
+    float M[16][16][GL];
+};
 
 // Header words of a workspace: look-back error bit, look-back epoch, and
 // whether any section needs the FP64 carry (the filter kernels come in two
@@ -156,7 +166,7 @@ struct ChainPlan {
 
 // Workspace layout of a chain/SOS/FIR call.
 struct WsLayout {
-    size_t hdr, tab, recs, casc, taps, merge, twid, hspec, tw64, ttab, total;
+    size_t hdr, tab, recs, casc, zir, taps, merge, twid, hspec, tw64, ttab, total;
     int64_t ntiles, cpad;
 };
 WsLayout ws_layout(int64_t C, int64_t N, int32_t S, int32_t M_merged, int32_t n_fir, int32_t fir_mode);

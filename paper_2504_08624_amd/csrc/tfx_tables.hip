@@ -86,6 +86,23 @@ __device__ void build_section_block(SecTab *tb, const float *co, int Lc, int tid
     }
 }
 
+// Element (i, j) of the cascade's one-sample transition F under zero input
+// (D = 2S state components, section s at 2s, 2s + 1): block (s, s) is the
+// section's A; block (s, t), t < s, is B_s (prod_{t<l<s} b0_l) C, since
+// section s's input is section s-1's output.
+__device__ double cascade_f(const double (*co)[5], int D, int i, int j) {
+    if (i >= D || j >= D) return 0.0;
+    const int si = i >> 1, ri = i & 1, sj = j >> 1, cj = j & 1;
+    const double b0 = co[si][0], b1 = co[si][1], b2 = co[si][2], a1 = co[si][3], a2 = co[si][4];
+    if (si == sj) return ri == 0 ? (cj == 0 ? -a1 : 1.0) : (cj == 0 ? -a2 : 0.0);
+    if (sj < si && cj == 0) {
+        double pr = ri == 0 ? b1 - a1 * b0 : b2 - a2 * b0;
+        for (int l = sj + 1; l < si; ++l) pr *= co[l][0];
+        return pr;
+    }
+    return 0.0;
+}
+
 // Tile-transition powers of the whole cascade for the cascade-level
 // look-back, in FP64, by one block of 256 threads (one matrix element
 // each).  The cascade's one-sample transition F (zero input): block (i, i) =
@@ -120,20 +137,7 @@ __device__ void casc_table_block(Co co_at, int32_t S, int Lc, CascTab *out, int 
     const int i = tid >> 4, j = tid & 15;
     if (tid < S * 5) co[tid / 5][tid % 5] = co_at(tid / 5, tid % 5);
     __syncthreads();
-    const int D = 2 * S;
-    double f = 0.0;
-    if (i < D && j < D) {
-        const int si = i >> 1, ri = i & 1, sj = j >> 1, cj = j & 1;
-        const double b0 = co[si][0], b1 = co[si][1], b2 = co[si][2], a1 = co[si][3], a2 = co[si][4];
-        if (si == sj) {
-            f = ri == 0 ? (cj == 0 ? -a1 : 1.0) : (cj == 0 ? -a2 : 0.0);
-        } else if (sj < si && cj == 0) {
-            double pr = ri == 0 ? b1 - a1 * b0 : b2 - a2 * b0;
-            for (int l = sj + 1; l < si; ++l) pr *= co[l][0];
-            f = pr;
-        }
-    }
-    M1[i][j] = f;
+    M1[i][j] = cascade_f(co, 2 * S, i, j);
     Pw[0][i][j] = i == j ? 1.0 : 0.0;
     __syncthreads();
     for (int e = Lc; e > 0; e >>= 1) {  // Pw[0] = F^Lc by binary powering
@@ -171,6 +175,53 @@ __device__ void casc_table_block(Co co_at, int32_t S, int Lc, CascTab *out, int 
         dep = hi;
     }
     if (tid == 0) out->depth = dep;
+}
+
+// Zero-input response tables of the cascade (CascZir), in FP64 then
+// rounded, one block of 256 threads (one matrix element each) per entry:
+// k < GL gives F^(Lc k) by binary powering; k == GL gives the output rows
+// G[r] = c F^r, r < Lc, where c[2s] = prod_{t>s} b0_t (the s1 register of
+// section s reaches the output through the b0 of every later section) and
+// c[2s+1] = 0.
+template <class Co>
+__device__ void zir_block(Co co_at, int32_t S, int Lc, int k, CascZir *out, int tid) {
+    __shared__ double co[CASC_MAX][5];
+    __shared__ double Fm[16][16], P[16][16];
+    __shared__ double g[16];
+    const int i = tid >> 4, j = tid & 15;
+    if (tid < S * 5) co[tid / 5][tid % 5] = co_at(tid / 5, tid % 5);
+    __syncthreads();
+    const int D = 2 * S;
+    Fm[i][j] = cascade_f(co, D, i, j);
+    P[i][j] = i == j ? 1.0 : 0.0;
+    __syncthreads();
+    if (k < GL) {
+        for (int e = Lc * k; e > 0; e >>= 1) {
+            if (e & 1) mm16(P, Fm, P, i, j);
+            if (e > 1) mm16(Fm, Fm, Fm, i, j);
+        }
+        out->M[i][j][k] = (float)P[i][j];
+        return;
+    }
+    if (tid < 16) {
+        double c = 0.0;
+        if (tid < D && (tid & 1) == 0) {
+            c = 1.0;
+            for (int t = (tid >> 1) + 1; t < S; ++t) c *= co[t][0];
+        }
+        g[tid] = c;
+    }
+    __syncthreads();
+    for (int r = 0; r < Lc; ++r) {  // G[r] = g, then g <- g F
+        double acc = 0.0;
+        if (tid < 16) {
+            out->G[r][tid] = (float)g[tid];
+            for (int q = 0; q < 16; ++q) acc += g[q] * Fm[q][tid];
+        }
+        __syncthreads();
+        if (tid < 16) g[tid] = acc;
+        __syncthreads();
+    }
 }
 
 struct MergeArgs {
@@ -284,6 +335,7 @@ struct PrepareArgs {
     int32_t S, casc;
     StageList sos;
     CascTab *ctab;
+    CascZir *zir;  // zero-input response tables (null: not wanted)
     uint64_t *recs;
     int64_t nwords;
     uint32_t *hdr;
@@ -325,6 +377,18 @@ __global__ __launch_bounds__(256) void prepare_kernel(PrepareArgs a) {
                 return (double)sl.ptr[st][5 * s + k];
             },
             a.S, L, a.ctab, tid);
+    } else if (a.casc && a.zir && b > a.nspec + a.S && b <= a.nspec + a.S + 1 + GL) {
+        const StageList &sl = a.sos;
+        zir_block(
+            [&](int s, int k) {
+                int st = 0;
+                while (s >= sl.len[st]) {
+                    s -= sl.len[st];
+                    ++st;
+                }
+                return (double)sl.ptr[st][5 * s + k];
+            },
+            a.S, L, b - (a.nspec + a.S + 1), a.zir, tid);
     }
 }
 
@@ -432,10 +496,11 @@ hipError_t launch_tables(const ChainPlan &p, const WsLayout &lay, const float *h
     a.casc = (p.S > 0 && p.S <= CASC_MAX) ? 1 : 0;
     a.sos = p.sos;
     a.ctab = reinterpret_cast<CascTab *>(ws + lay.casc);
+    a.zir = a.casc ? reinterpret_cast<CascZir *>(ws + lay.zir) : nullptr;
     a.recs = reinterpret_cast<uint64_t *>(ws + lay.recs);
     a.nwords = p.S > 0 ? lay.cpad * lay.ntiles * p.S * REC_WORDS : 0;
     a.hdr = reinterpret_cast<uint32_t *>(ws + lay.hdr);
-    int64_t nb = a.nspec + a.S + a.casc;
+    int64_t nb = a.nspec + a.S + a.casc + (a.casc ? GL + 1 : 0);
     int64_t nclear = (a.nwords + 255) / 256;
     if (nclear > 1024) nclear = 1024;
     if (nb < nclear) nb = nclear;
