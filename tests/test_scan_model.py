@@ -208,3 +208,37 @@ def test_cascade_look_back_two_phase_equals_oracle():
         y[t * T:(t + 1) * T] = yt[0]
         P = FT @ P + E.reshape(-1)
     np.testing.assert_allclose(y, O.sos(x[None, :], sec)[0], rtol=1e-9, atol=1e-12)
+
+
+def test_cascade_zero_input_response_form_equals_oracle():
+    # phase C as the chain kernel's table form: the tile output is the response
+    # to a zero tile-entering state plus, at sample r of chunk k,
+    # G[r] . (F^(L k) P) with G[r] = c F^r and c[2s] = prod_{t>s} b0_t, c[2s+1] = 0
+    # (the s1 register of section s reaches the output through the b0 of every
+    # later section).  Only the lower block triangle of F^(L k) is used.
+    from paper_2504_08624_amd import design, signals
+    S, L, chunks, ntiles = 6, 8, 12, 5
+    T = L * chunks
+    sec = design.random_sections(signals.rng(75), S, 0.5, 0.995)
+    x = signals.rng(76).standard_normal(T * ntiles)
+    F = _cascade_transition(sec)
+    D = 2 * S
+    c = np.zeros(D)
+    for s in range(S):
+        c[2 * s] = np.prod([sec[t][0] for t in range(s + 1, S)]) if s + 1 < S else 1.0
+    G = np.array([c @ np.linalg.matrix_power(F, r) for r in range(L)])
+    Mk = [np.linalg.matrix_power(F, L * k) for k in range(chunks)]
+    lower = np.array([[j <= (i | 1) for j in range(D)] for i in range(D)])
+    for m in Mk:  # the powers are block lower triangular
+        assert np.all(m[~lower] == 0.0)
+    FT = np.linalg.matrix_power(F, T)
+    P = np.zeros(D)
+    y = np.empty_like(x)
+    for t in range(ntiles):
+        seg = x[t * T:(t + 1) * T][None, :]
+        yA, E = O.sos(seg, sec, state_in=np.zeros((1, S, 2)), return_state=True)
+        n = np.arange(T)
+        corr = np.array([G[i % L] @ ((Mk[i // L] * lower) @ P) for i in n])
+        y[t * T:(t + 1) * T] = yA[0] + corr
+        P = FT @ P + E.reshape(-1)
+    np.testing.assert_allclose(y, O.sos(x[None, :], sec)[0], rtol=1e-9, atol=1e-11)
