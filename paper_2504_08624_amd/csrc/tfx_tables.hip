@@ -345,14 +345,24 @@ __global__ __launch_bounds__(256) void prepare_kernel(PrepareArgs a) {
     const int tid = threadIdx.x;
     const int b = blockIdx.x;
     for (int64_t i = (int64_t)b * 256 + tid; i < a.nwords; i += (int64_t)gridDim.x * 256) a.recs[i] = 0ull;
-    if (b == 0 && tid == 0 && a.S > 0) {
-        a.hdr[HDR_ERROR] = 0u;
-        a.hdr[HDR_EPOCH] = 1u;
-        uint32_t any = 0u;
-        for (int st = 0; st < a.sos.n; ++st)
-            for (int j = 0; j < a.sos.len[st]; ++j)
-                any |= section_hiq(a.sos.ptr[st][5 * j + 3], a.sos.ptr[st][5 * j + 4]) ? 1u : 0u;
-        a.hdr[HDR_HIQ] = any;
+    if (b == 0 && a.S > 0) {  // the cascade's high-Q word: one section per thread, loads in parallel
+        __shared__ uint32_t s_any;
+        if (tid == 0) s_any = 0u;
+        __syncthreads();
+        for (int q = tid; q < a.S; q += 256) {
+            int sec = q, st = 0;
+            while (sec >= a.sos.len[st]) {
+                sec -= a.sos.len[st];
+                ++st;
+            }
+            if (section_hiq(a.sos.ptr[st][5 * sec + 3], a.sos.ptr[st][5 * sec + 4])) atomicOr(&s_any, 1u);
+        }
+        __syncthreads();
+        if (tid == 0) {
+            a.hdr[HDR_ERROR] = 0u;
+            a.hdr[HDR_EPOCH] = 1u;
+            a.hdr[HDR_HIQ] = s_any;
+        }
     }
     if (b < a.nspec) {
         const int blk = b % (NFFT / 16), part = b / (NFFT / 16);
