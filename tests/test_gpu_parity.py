@@ -353,3 +353,35 @@ def test_chain_run_replays_on_prepared_workspace():
         assert_close(_cpu(y), refs[i % 2], TOL_IIR_F32, "replay %d" % i)
     hdr = _cpu(ws[:16].view(torch.int32))
     assert hdr[1] == 0 and hdr[2] == 8  # epoch advanced once per run, no spin timeouts
+
+
+# ------------------------------------------- cascade lengths of the table form
+
+@pytest.mark.parametrize("S", [1, 2, 3, 4, 5, 6, 7, 8])
+def test_chain_fft_every_cascade_length(S):
+    """FFT FIR then S sections: up to six sections the cascade's second phase
+    is the zero-input-response table form, seven and eight take the
+    per-section form; both against the oracle, over several tiles and a
+    ragged tail, with poles up to radius 0.994."""
+    x = _x(3, 4 * T + 17, (90, S))
+    h = design.fir_lowpass(255, 5000.0, 48000.0).astype(np.float32)
+    # peaking sections across the band (gains near one: a well-conditioned
+    # cascade, so fp32 rounding stays at its own size in the output)
+    g = signals.rng(91, S)
+    sec = np.concatenate([design.peaking(f, q, gd, 48000.0) for f, q, gd in
+                          zip(np.geomspace(300.0, 12000.0, S), g.uniform(0.7, 4.0, S), g.uniform(-9.0, 9.0, S))])
+    sec = sec.astype(np.float32)
+    assert 0.975 < design.max_pole_radius(sec) < 0.999  # below the FP64-carry threshold
+    y = _cpu(tfx.chain(_gpu(x), [("fir", _gpu(h)), ("sos", _gpu(sec))]))
+    assert_close(y, O.chain(x, [("fir", h), ("sos", sec)]), TOL_IIR_F32, "FFT FIR + %d sections" % S)
+
+
+@pytest.mark.parametrize("S", [3, 5])
+def test_sos_state_in_through_the_table_form(S):
+    """A nonzero state entering the first tile reaches every later sample
+    through the zero-input response; no final state is asked for."""
+    x = _x(2, 3 * T + 5, (92, S))
+    sec = _sections(S, (93, S), r_hi=0.995)
+    st = signals.rng(94, S).standard_normal((2, S, 2)).astype(np.float32)
+    y = _cpu(tfx.sos(_gpu(x), _gpu(sec), state_in=_gpu(st)))
+    assert_close(y, O.sos(x, sec, state_in=st), TOL_IIR_F32, "state_in, %d sections" % S)
