@@ -215,6 +215,20 @@ def secondary(torch, dev, stream):
                         "rel_err_2ch": rel_err(yp[:2].cpu().numpy(), ref), "tolerance": 1e-4}
     del x, yp
 
+    log("chain_mid, matrix-core FIR")
+    w = workloads.chain_mid()
+    x = torch.from_numpy(w.x).to(dev)
+    st = [(k, torch.from_numpy(c).to(dev)) for k, c in w.stages]
+    ref = O.chain(w.x[:2], w.stages)
+    res = {"workload": "chain_mid (8 x 5,760,000, 1023-tap FIR | 6 SOS), one tfx_chain call (prepare + run)"}
+    for comp in ("f32", "bf16", "f16"):
+        s_c = timed(torch, lambda: tfx.chain(x, st, compute=comp), 10, stream)
+        yc = tfx.chain(x, st, compute=comp)[:2].cpu().numpy()
+        res[comp] = {"ms": round(s_c * 1e3, 4), "Msamples_per_s": round(x.numel() / s_c / 1e6, 1),
+                     "rel_err_2ch": rel_err(yc, ref), "tolerance": 1e-4 if comp == "f32" else 1e-2}
+    out["chain_mid_compute"] = res
+    del x, st
+
     log("stream")
     w = workloads.chain_mid(C=8, N=48000)
     x = torch.from_numpy(w.x).to(dev)
