@@ -251,11 +251,19 @@ __global__ __launch_bounds__(WG, 3) void sos_bwd_kernel(BArgs a) {
 #pragma unroll
         for (int r = 0; r < L; ++r) xo[r] = xs[r];  // output of section s - 1
         // (e) group sums, in a fixed order
-        double red[5] = {(double)dA00, (double)dA10, (double)dB0, (double)dB1, (double)dD};
+        // within rows of 16 lanes in fp32 (16 chunk sums), across rows in FP64
+        float rf[5] = {dA00, dA10, dB0, dB1, dD};
 #pragma unroll
         for (int k = 0; k < 5; ++k) {
 #pragma unroll
-            for (int d = 32; d >= 1; d >>= 1) red[k] += __shfl_xor(red[k], d);
+            for (int d = 1; d <= 8; d <<= 1) rf[k] += __shfl_xor(rf[k], d);
+        }
+        double red[5];
+#pragma unroll
+        for (int k = 0; k < 5; ++k) {
+            red[k] = (double)rf[k];
+            red[k] += __shfl_xor(red[k], 16);
+            red[k] += __shfl_xor(red[k], 32);
         }
         const int rb = (S - 1 - s) & 1;
         if (lane == 0) {
