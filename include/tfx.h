@@ -254,7 +254,8 @@ tfx_status tfx_sos_batched_tune(const tfx_clip *clips, int32_t nclips, int32_t r
  * tile by tile from the forward's checkpoints `ckpt` (the tile-entering
  * states written by the forward call with the same x, coefficients and
  * state_in), so nothing is stored per sample.  Coefficient gradients are
- * reduced in FP64 in a fixed order (bit-identical from run to run); gradient
+ * summed in fp32 within a chunk and over 16 neighbouring chunks, then in FP64,
+ * always in a fixed order (bit-identical from run to run); gradient
  * buffers are overwritten, not accumulated into.  The gradient with respect
  * to state_in is not produced.
  * Limits: at most 16 sections in the cascade (TFX_E_UNSUPPORTED beyond). */
