@@ -64,7 +64,9 @@ typedef enum tfx_status {
     TFX_E_UNSTABLE = 4,    /* host-checked filter with a pole on/outside |z|=1 */
     TFX_E_ALIAS = 5,       /* output overlaps an input                        */
     TFX_E_CAPTURE = 6,     /* call not allowed while the stream is captured   */
-    TFX_E_HIP = 7          /* a HIP runtime call failed                       */
+    TFX_E_HIP = 7,         /* a HIP runtime call failed                       */
+    TFX_E_DEVICE = 8       /* a kernel flagged its result in a workspace's
+                              status word (see tfx_workspace_status)          */
 } tfx_status;
 
 /* Arithmetic of the FIR contraction.  Signals stay fp32 in memory for every
@@ -110,6 +112,29 @@ int64_t tfx_sos_tile_length(void);
  * TFX_E_UNSTABLE semantics check here first.  Returns TFX_E_UNSTABLE when not
  * stable. */
 tfx_status tfx_sos_check_stable(const float *sos_host, int32_t S, int32_t *stable);
+
+/* Device-side status of a workspace.  The IIR scan carries the state
+ * entering each tile from its predecessors (Sec. 3's recursive filters run
+ * as a chunked linear-recurrence scan): a workgroup waits, with a bounded
+ * number of polls, for the tiles before it.  Workgroups are dispatched in
+ * tile order, so the wait always ends; should the bound ever be reached the
+ * kernel finishes with a wrong prefix and sets TFX_DEV_LOOKBACK_TIMEOUT in the
+ * workspace's status word instead of hanging.  Every call that uses a
+ * workspace of at least 256 bytes (forward, stream, adjoint, batched) clears
+ * the word when it prepares the workspace; tfx_chain_run and
+ * tfx_sos_batched_run only ever set bits, so the word covers every run since
+ * the last prepare.
+ *
+ * tfx_workspace_status enqueues on `stream` one single-thread kernel that ORs
+ * the status word of ws into *flags and, when `clear` is non-zero, zeroes the
+ * word.  flags is a DEVICE pointer (or mapped pinned host memory, e.g. from
+ * hipHostMalloc); its value is valid once the stream is synchronised.  The
+ * call neither allocates nor synchronises, so it may be captured.  A NULL ws
+ * or ws_bytes < 256 (a call that needed no workspace) leaves *flags
+ * unchanged.  The caller reads *flags after synchronising and treats any set
+ * bit as TFX_E_DEVICE for the calls that used ws. */
+#define TFX_DEV_LOOKBACK_TIMEOUT 1u
+tfx_status tfx_workspace_status(const void *ws, size_t ws_bytes, uint32_t *flags, int32_t clear, void *stream);
 
 /* ------------------------------------------------------ workspace queries */
 
@@ -236,7 +261,8 @@ tfx_status tfx_sos_batched(const tfx_clip *clips, int32_t nclips, const tfx_batc
  * this batch with HIP events, `reps` timed runs each after one warm-up, and
  * returns the fastest in *best (its mean time in *best_ms if not NULL).
  * Synchronises `stream`; overwrites the clips' outputs; leaves ws prepared
- * for *best. */
+ * for *best.  Returns TFX_E_CAPTURE (nothing enqueued) when `stream` is
+ * being captured into a graph. */
 tfx_status tfx_sos_batched_tune(const tfx_clip *clips, int32_t nclips, int32_t reps, void *ws,
                                 size_t ws_bytes, void *stream, tfx_batch_config *best, float *best_ms);
 

@@ -16,6 +16,7 @@ import shutil
 import subprocess
 import sys
 import tempfile
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
@@ -49,7 +50,7 @@ def build(verbose: bool = False) -> str:
     hip, cpp = sources()
     cc = hipcc()
     with tempfile.TemporaryDirectory(prefix="tfx_build_") as tmp:
-        objs = []
+        cmds, objs = [], []
         for src in hip + cpp:
             obj = os.path.join(tmp, os.path.basename(src) + ".o")
             if src.endswith(".hip"):
@@ -58,8 +59,14 @@ def build(verbose: bool = False) -> str:
                 cmd = [cc, *CXX_FLAGS, "-D__HIP_PLATFORM_AMD__", "-I", INCLUDE, "-I", CSRC, "-c", src, "-o", obj]
             if verbose:
                 print(" ".join(cmd), flush=True)
-            subprocess.run(cmd, check=True)
+            cmds.append(cmd)
             objs.append(obj)
+        # one compiler process per source, at most as many as the CPUs this
+        # process may use (and never more than 16)
+        jobs = max(1, min(16, len(os.sched_getaffinity(0)), len(cmds)))
+        with ThreadPoolExecutor(jobs) as pool:
+            for r in list(pool.map(lambda c: subprocess.run(c, check=True), cmds)):
+                pass
         tmp_lib = LIB + ".tmp%d" % os.getpid()
         cmd = [cc, "-shared", f"--offload-arch={ARCH}", "-o", tmp_lib, *objs]
         if verbose:

@@ -250,8 +250,9 @@ tfx_status batch_do(const tfx_clip *clips, int32_t n, const tfx_batch_config *cf
     if ((s = check_ws(ws, ws_bytes, lay.total))) return s;
     hipStream_t st = static_cast<hipStream_t>(stream);
     hipError_t e = hipSuccess;
-    if (prep && n > 0) {
-        if ((e = tfx::upload_descriptors(desc.data(), n, lay, ws, st)) != hipSuccess) return hip_fail(e, "descriptor upload");
+    if (prep) {  // an empty batch still gets its header words written
+        if (n > 0 && (e = tfx::upload_descriptors(desc.data(), n, lay, ws, st)) != hipSuccess)
+            return hip_fail(e, "descriptor upload");
         if ((e = tfx::launch_batch_prepare(lay, lc, n, ws, st)) != hipSuccess) return hip_fail(e, "batch prepare");
     }
     if (run && n > 0 && (e = tfx::launch_batch_run(lay, lc, n, ws, st)) != hipSuccess)
@@ -263,6 +264,16 @@ tfx_status backward(const tfx::BwdPlan &bp) {
     const hipError_t e = tfx::launch_backward(bp);
     if (e != hipSuccess) return hip_fail(e, "adjoint kernel launch");
     return ok();
+}
+
+// Calls that synchronise (the tuners) are refused on a capturing stream.
+tfx_status not_capturing(hipStream_t st, const char *what) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    const hipError_t e = hipStreamIsCapturing(st, &cs);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamIsCapturing");
+    if (cs != hipStreamCaptureStatusNone)
+        return fail(TFX_E_CAPTURE, "%s synchronises the stream and cannot run while it is being captured", what);
+    return TFX_OK;
 }
 
 // STFT argument checks
@@ -300,6 +311,7 @@ const char *tfx_status_string(tfx_status s) {
         case TFX_E_ALIAS: return "TFX_E_ALIAS";
         case TFX_E_CAPTURE: return "TFX_E_CAPTURE";
         case TFX_E_HIP: return "TFX_E_HIP";
+        case TFX_E_DEVICE: return "TFX_E_DEVICE";
     }
     return "TFX_E_UNKNOWN";
 }
@@ -329,6 +341,15 @@ tfx_status tfx_sos_check_stable(const float *sos_host, int32_t S, int32_t *stabl
         }
     }
     return ok();
+}
+
+tfx_status tfx_workspace_status(const void *ws, size_t ws_bytes, uint32_t *flags, int32_t clear, void *stream) {
+    if (!flags) return fail(TFX_E_INVALID_ARG, "flags is NULL");
+    if (!ws || ws_bytes < 256) return ok();
+    if (reinterpret_cast<uintptr_t>(ws) % 256) return fail(TFX_E_WORKSPACE, "workspace must be 256-byte aligned");
+    const hipError_t e = tfx::launch_ws_status(const_cast<void *>(ws), flags, clear ? 1 : 0,
+                                               static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? ok() : hip_fail(e, "status kernel launch");
 }
 
 tfx_status tfx_fir_workspace_size(int64_t C, int64_t N, int32_t M, tfx_compute cmp, tfx_fir_algo algo,
@@ -620,6 +641,8 @@ tfx_status tfx_sos_batched_tune(const tfx_clip *clips, int32_t nclips, int32_t r
     if (!best) return fail(TFX_E_INVALID_ARG, "best is NULL");
     if (reps < 1 || reps > 1000) return fail(TFX_E_INVALID_ARG, "reps must be in [1, 1000]");
     hipStream_t st = static_cast<hipStream_t>(stream);
+    tfx_status cs = not_capturing(st, "tfx_sos_batched_tune");
+    if (cs) return cs;
     hipEvent_t e0, e1;
     hipError_t he;
     if ((he = hipEventCreate(&e0)) != hipSuccess) return hip_fail(he, "hipEventCreate");

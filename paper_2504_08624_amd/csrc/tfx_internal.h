@@ -171,6 +171,9 @@ struct WsLayout {
 };
 WsLayout ws_layout(int64_t C, int64_t N, int32_t S, int32_t M_merged, int32_t n_fir, int32_t fir_mode);
 
+// Status word of a workspace into *flags (tfx_workspace_status).
+hipError_t launch_ws_status(void *ws, uint32_t *flags, int32_t clear, hipStream_t st);
+
 // Tables + workspace initialisation (once per workspace and coefficients).
 hipError_t launch_prepare(const ChainPlan &p);
 // The filtering itself; may be repeated on a prepared workspace.

@@ -345,7 +345,7 @@ __global__ __launch_bounds__(256) void prepare_kernel(PrepareArgs a) {
     const int tid = threadIdx.x;
     const int b = blockIdx.x;
     for (int64_t i = (int64_t)b * 256 + tid; i < a.nwords; i += (int64_t)gridDim.x * 256) a.recs[i] = 0ull;
-    if (b == 0 && a.S > 0) {  // the cascade's high-Q word: one section per thread, loads in parallel
+    if (b == 0) {  // header words; the cascade's high-Q word: one section per thread, loads in parallel
         __shared__ uint32_t s_any;
         if (tid == 0) s_any = 0u;
         __syncthreads();
@@ -514,8 +514,25 @@ hipError_t launch_tables(const ChainPlan &p, const WsLayout &lay, const float *h
     int64_t nclear = (a.nwords + 255) / 256;
     if (nclear > 1024) nclear = 1024;
     if (nb < nclear) nb = nclear;
+    // a workspace with room for the header gets its header words written
+    // even when there is nothing else to build
+    if (nb == 0 && p.ws && p.ws_bytes >= 256) nb = 1;
     if (nb == 0) return hipSuccess;
     hipLaunchKernelGGL(prepare_kernel, dim3((unsigned)nb), dim3(256), 0, p.stream, a);
+    return hipGetLastError();
+}
+
+// Status word of a workspace: OR it into *flags (written only when a bit is
+// set), then optionally clear it.  One thread; stream-ordered after the
+// calls that used the workspace.
+__global__ void ws_status_kernel(uint32_t *hdr, uint32_t *flags, int32_t clear) {
+    const uint32_t v = __hip_atomic_load(hdr + HDR_ERROR, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (v) *flags |= v;
+    if (clear) __hip_atomic_store(hdr + HDR_ERROR, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+hipError_t launch_ws_status(void *ws, uint32_t *flags, int32_t clear, hipStream_t st) {
+    hipLaunchKernelGGL(ws_status_kernel, dim3(1), dim3(1), 0, st, static_cast<uint32_t *>(ws), flags, clear);
     return hipGetLastError();
 }
 

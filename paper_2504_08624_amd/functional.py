@@ -57,6 +57,52 @@ def _workspace(nbytes: int, device):
     return ws, int(nbytes)
 
 
+# One device-side status word per device.  After every call that used a
+# workspace, the workspace's status word (set by a kernel whose look-back wait
+# gave up) is folded into it by tfx_workspace_status on the same stream, so
+# nothing synchronises; device_status() reads it.
+_status_words = {}
+
+
+def _status_word(device) -> torch.Tensor:
+    device = torch.device(device)
+    key = device.index if device.index is not None else torch.cuda.current_device()
+    w = _status_words.get(key)
+    if w is None:
+        w = torch.zeros(1, dtype=torch.int32, device=torch.device("cuda", key))
+        _status_words[key] = w
+    return w
+
+
+def _track(ws, wsb: int, device):
+    if ws is None or wsb < 256:
+        return
+    lib.call("tfx_workspace_status", _ptr(ws), wsb, _status_word(device).data_ptr(), 1, _stream(device))
+
+
+def device_status(device=None, clear: bool = True) -> int:
+    """Synchronises the device and returns the OR of the status words of
+    every workspace used by the calls of this module since the last clear
+    (0 = clean; lib.DEV_LOOKBACK_TIMEOUT = a look-back wait gave up, so the
+    output of some call is wrong)."""
+    device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+    w = _status_word(device)
+    torch.cuda.synchronize(device)
+    v = int(w.item())
+    if clear and v:
+        w.zero_()
+    return v
+
+
+def check_device_status(device=None):
+    """Raises lib.TfxError(TFX_E_DEVICE) if a kernel flagged a workspace
+    since the last check (clears the flag)."""
+    v = device_status(device, clear=True)
+    if v:
+        raise lib.TfxError(lib.TFX_E_DEVICE, "device status",
+                           "workspace status word 0x%x (look-back wait gave up: some output is wrong)" % v)
+
+
 def _ptr(t):
     return t.data_ptr() if t is not None else None
 
@@ -75,6 +121,7 @@ def _fir_raw(x: torch.Tensor, h, compute: str = "f32", algo: str = "auto") -> to
     ws, wsb = _workspace(nb.value, x.device)
     lib.call("tfx_fir", _ptr(x2), _ptr(y), C, N, ld, max(N, 1), _ptr(h), h.numel(),
              lib.COMPUTE[compute], lib.FIR_ALGO[algo], _ptr(ws), wsb, _stream(x.device))
+    _track(ws, wsb, x.device)
     return y[0] if squeeze else y
 
 
@@ -98,6 +145,7 @@ def _sos_raw(x: torch.Tensor, sections, state_in=None, return_state: bool = Fals
     ws, wsb = _workspace(nb.value, x.device)
     lib.call("tfx_sos", _ptr(x2), _ptr(y), C, N, ld, max(N, 1), _ptr(co), S, _ptr(si), _ptr(so),
              _ptr(ck), _ptr(ws), wsb, _stream(x.device))
+    _track(ws, wsb, x.device)
     y = y[0] if squeeze else y
     out = [y]
     if return_state:
@@ -138,6 +186,7 @@ def _chain_raw(x: torch.Tensor, stages, compute: str = "f32", return_ckpt: bool 
     ws, wsb = _workspace(nb.value, x.device)
     lib.call("tfx_chain", _ptr(x2), _ptr(y), C, N, ld, max(N, 1), arr, len(desc),
              lib.COMPUTE[compute], _ptr(ck), _ptr(ws), wsb, _stream(x.device))
+    _track(ws, wsb, x.device)
     del kept
     y = y[0] if squeeze else y
     return (y, ck) if return_ckpt else y
@@ -161,6 +210,7 @@ def fir_backward(x: torch.Tensor, gy: torch.Tensor, h, compute: str = "f32", alg
     ws, wsb = _workspace(nb.value, x.device)
     lib.call("tfx_fir_backward", _ptr(x2), _ptr(g2), _ptr(gx), C, N, ld, ldg, max(N, 1), _ptr(h), h.numel(),
              _ptr(gh), lib.COMPUTE[compute], lib.FIR_ALGO[algo], _ptr(ws), wsb, _stream(x.device))
+    _track(ws, wsb, x.device)
     return (gx[0] if squeeze else gx), gh
 
 
@@ -182,6 +232,7 @@ def sos_backward(x: torch.Tensor, gy: torch.Tensor, sections, ckpt: torch.Tensor
     ws, wsb = _workspace(nb.value, x.device)
     lib.call("tfx_sos_backward", _ptr(x2), _ptr(g2), _ptr(gx), C, N, ld, ldg, max(N, 1), _ptr(co), S, _ptr(ck),
              _ptr(gs), _ptr(ws), wsb, _stream(x.device))
+    _track(ws, wsb, x.device)
     return (gx[0] if squeeze else gx), gs
 
 
@@ -206,6 +257,7 @@ def chain_backward(x: torch.Tensor, gy: torch.Tensor, stages, ckpt, compute: str
     ws, wsb = _workspace(nb.value, x.device)
     lib.call("tfx_chain_backward", _ptr(x2), _ptr(g2), _ptr(gx), C, N, ld, ldg, max(N, 1), arr, len(desc),
              lib.COMPUTE[compute], _ptr(ck), parr, _ptr(ws), wsb, _stream(x.device))
+    _track(ws, wsb, x.device)
     del kept
     return (gx[0] if squeeze else gx), grads
 
@@ -251,6 +303,7 @@ class ChainStream:
         lib.call("tfx_chain_stream", _ptr(x2), _ptr(y), C, N, ld, max(N, 1), self._arr, self._ns,
                  lib.COMPUTE[self.compute], self.n_max, _ptr(self._hist[i]), _ptr(self._hist[o]),
                  _ptr(self._state[i]), _ptr(self._state[o]), _ptr(self._ws), self._wsb, _stream(x.device))
+        _track(self._ws, self._wsb, x.device)
         self._cur = o
         return y[0] if squeeze else y
 
@@ -408,12 +461,14 @@ class SosBatch:
     def run(self):
         lib.call("tfx_sos_batched_run", self.clips, self.n, self.config, _ptr(self.ws), self.wsb,
                  _stream(self.device))
+        _track(self.ws, self.wsb, self.device)
         return self.ys
 
     def tune(self, reps: int = 3):
         best, ms = lib.BatchConfig(0, 0), ctypes.c_float(0.0)
         lib.call("tfx_sos_batched_tune", self.clips, self.n, reps, _ptr(self.ws), self.wsb, _stream(self.device),
                  best, ms)
+        _track(self.ws, self.wsb, self.device)
         self.config = best
         return {"chunk": best.chunk, "order": best.order}, float(ms.value)
 

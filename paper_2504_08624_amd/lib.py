@@ -17,7 +17,9 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "tfx.h")
 
 TFX_OK = 0
 STATUS_NAMES = {0: "TFX_OK", 1: "TFX_E_INVALID_ARG", 2: "TFX_E_UNSUPPORTED", 3: "TFX_E_WORKSPACE",
-                4: "TFX_E_UNSTABLE", 5: "TFX_E_ALIAS", 6: "TFX_E_CAPTURE", 7: "TFX_E_HIP"}
+                4: "TFX_E_UNSTABLE", 5: "TFX_E_ALIAS", 6: "TFX_E_CAPTURE", 7: "TFX_E_HIP", 8: "TFX_E_DEVICE"}
+TFX_E_DEVICE = 8
+DEV_LOOKBACK_TIMEOUT = 1
 COMPUTE = {"f32": 0, "bf16": 1, "f16": 2, "bf16x3": 3}
 FIR_ALGO = {"auto": 0, "direct": 1, "toeplitz": 2, "fft": 3}
 STAGE_FIR, STAGE_SOS = 0, 1
@@ -50,6 +52,7 @@ _SIGS = {
     "tfx_version": (_i32, []),
     "tfx_sos_tile_length": (_i64, []),
     "tfx_sos_check_stable": (_i32, [_vp, _i32, ctypes.POINTER(_i32)]),
+    "tfx_workspace_status": (_i32, [_vp, _sz, _vp, _i32, _vp]),
     "tfx_fir_workspace_size": (_i32, [_i64, _i64, _i32, _i32, _i32, ctypes.POINTER(_sz)]),
     "tfx_sos_workspace_size": (_i32, [_i64, _i64, _i32, ctypes.POINTER(_sz)]),
     "tfx_chain_workspace_size": (_i32, [_i64, _i64, ctypes.POINTER(Stage), _i32, _i32, ctypes.POINTER(_sz)]),

@@ -196,3 +196,13 @@ def test_istft_argument_validation():
     assert _st("tfx_istft", spec, 2, 10, 256, 64, None, 256, 1, 0, y, 1 << 38, 1 << 38, None) == "TFX_E_UNSUPPORTED"
     # zero-length output: nothing to do
     assert _st("tfx_istft", spec, 2, 10, 256, 64, None, 256, 1, 0, y, 0, 0, None) == "TFX_OK"
+
+
+def test_workspace_status_arguments():
+    # flags NULL is an argument error; a call that needed no workspace (NULL
+    # ws or fewer than 256 bytes) has no status word and enqueues nothing
+    assert _st("tfx_workspace_status", FAKE, 4096, None, 0, None) == "TFX_E_INVALID_ARG"
+    assert _st("tfx_workspace_status", None, 0, FAKE, 0, None) == "TFX_OK"
+    assert _st("tfx_workspace_status", FAKE, 128, FAKE, 1, None) == "TFX_OK"
+    assert _st("tfx_workspace_status", FAKE + 8, 4096, FAKE, 1, None) == "TFX_E_WORKSPACE"
+    assert lib.STATUS_NAMES[lib.TFX_E_DEVICE] == "TFX_E_DEVICE"
