@@ -360,6 +360,10 @@ def chain(x: torch.Tensor, stages, compute: str = "f32", return_ckpt: bool = Fal
     if _wants_grad(x, coefs):
         if return_ckpt:
             raise ValueError("return_ckpt is for explicit adjoint calls, not autograd")
+        if compute != "f32" and any(k == "fir" for k, _ in stages):
+            # refused before the forward runs, not at loss.backward()
+            raise ValueError("the adjoint computes in fp32 only: a differentiable chain with a FIR stage needs "
+                             "compute='f32' (got %r)" % (compute,))
         kinds = tuple(k for k, _ in stages)
         for k in kinds:
             if k not in ("fir", "sos"):

@@ -6,8 +6,7 @@ with the filters' sample rate bound from the wave.  Here the pipe is lazy:
 piping a filter (or a ``Sequential`` of filters) into a wave only records the
 stage, and the recorded stages run as one fused chain (one kernel launch for
 the whole cascade, FIR stages merged in front) when the samples are read
-(``.y``).  Any other module is applied to the samples at once.  WAV files
-are read and written on the host (``from_file``, ``save``).
+(``.y``).  Any other module is applied to the samples at once.
 """
 from __future__ import annotations
 
@@ -61,30 +60,6 @@ class Wave:
 
     def to(self, device) -> "Wave":
         return Wave(self.y.to(device), self.fs)
-
-    @classmethod
-    def from_file(cls, path, device=None) -> "Wave":
-        """Reads a WAV file (PCM 8/16/32-bit or float) as float32 samples in
-        [-1, 1), channels first, with the file's sample rate."""
-        import numpy as np
-        from scipy.io import wavfile
-        fs, data = wavfile.read(path)
-        data = np.asarray(data)
-        if data.dtype == np.uint8:
-            y = (data.astype(np.float32) - 128.0) / 128.0
-        elif data.dtype.kind == "i":
-            y = data.astype(np.float32) / float(2 ** (8 * data.dtype.itemsize - 1))
-        else:
-            y = data.astype(np.float32)
-        y = y.T if y.ndim == 2 else y[None, :]
-        t = torch.from_numpy(np.ascontiguousarray(y))
-        return cls(t.to(device) if device is not None else t, float(fs))
-
-    def save(self, path) -> None:
-        """Writes the samples (after any pending stages) as a 32-bit float WAV."""
-        import numpy as np
-        from scipy.io import wavfile
-        wavfile.write(path, int(round(self.fs)), np.ascontiguousarray(self.y.detach().cpu().numpy().T))
 
     def __or__(self, module) -> "Wave":
         stages = stages_of(module, self.fs)
