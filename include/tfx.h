@@ -82,7 +82,10 @@ typedef enum tfx_fir_algo {
     TFX_FIR_AUTO = 0,      /* pick by tap count and compute mode             */
     TFX_FIR_DIRECT = 1,    /* LDS-tiled direct convolution (fp32 only)       */
     TFX_FIR_TOEPLITZ = 2,  /* MFMA block-Toeplitz product (bf16/fp16/bf16x3) */
-    TFX_FIR_FFT = 3        /* overlap-save FFT (fp32 only)                   */
+    TFX_FIR_FFT = 3,       /* overlap-save, 4096-point FFT per 3072 outputs;
+                              taps beyond 1025 in partitions of 1025 (fp32) */
+    TFX_FIR_FFT16K = 4     /* overlap-save, 16384-point FFT per 8192 outputs;
+                              at most 8193 taps (fp32)                      */
 } tfx_fir_algo;
 
 typedef enum tfx_stage_kind { TFX_STAGE_FIR = 0, TFX_STAGE_SOS = 1 } tfx_stage_kind;
@@ -216,6 +219,41 @@ tfx_status tfx_chain_stream(const float *x, float *y, int64_t C, int64_t N, int6
                             const tfx_stage *stages, int32_t nstages, tfx_compute cmp, int64_t n_max,
                             const float *hist_in, float *hist_out, const float *state_in, float *state_out,
                             void *ws, size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------------- tuning */
+
+/* FIR algorithm tuner.  The FIR forms above compute the same convolution:
+ * direct, overlap-save with 4096- or 16384-point FFTs (fp32), and the
+ * matrix-core Toeplitz product in split bf16, fp16 or bf16 operands.  Each
+ * has a stated accuracy, the per-channel relative RMS error it is held to:
+ * fp32 forms 1e-5, split bf16 1e-4, fp16 and bf16 1e-2.  tfx_fir_autotune
+ * times every form whose stated accuracy is within `tol` on the caller's
+ * buffers (one untimed call each, then `reps` timed calls of tfx_fir with
+ * HIP events; a form more than 4x slower than the best so far on its untimed
+ * call is not timed further) and returns the fastest in *best_algo /
+ * *best_cmp (its mean time per call in *best_ms if not NULL).  It records
+ * the result in the process-wide tuning cache, keyed by (device architecture
+ * and compute-unit count, M, C, floor(log2 N), tolerance class); from then on
+ * an fp32 TFX_FIR_AUTO request of that key by tfx_fir, tfx_fir_backward and
+ * FIR-only chains takes the recorded form (chains with sections keep the
+ * fixed rule, under which the FIR fuses with the cascade).
+ * Synchronises `stream` (TFX_E_CAPTURE, nothing enqueued, when the stream is
+ * being captured); overwrites y.  ws: at least
+ * tfx_fir_autotune_workspace_size bytes.  tol < 1e-5: TFX_E_UNSUPPORTED. */
+tfx_status tfx_fir_autotune_workspace_size(int64_t C, int64_t N, int32_t M, double tol, size_t *bytes);
+tfx_status tfx_fir_autotune(const float *x, float *y, int64_t C, int64_t N, int64_t ldx, int64_t ldy,
+                            const float *h, int32_t M, double tol, int32_t reps, void *ws, size_t ws_bytes,
+                            void *stream, tfx_fir_algo *best_algo, tfx_compute *best_cmp, float *best_ms);
+/* The cached form for (C, N, M, tol) on the current device, or
+ * TFX_FIR_AUTO / TFX_COMPUTE_F32 when nothing is cached (host only). */
+tfx_status tfx_fir_tuned(int64_t C, int64_t N, int32_t M, double tol, tfx_fir_algo *algo, tfx_compute *cmp);
+/* Makes the tuning cache persistent in the text file `path` (host string):
+ * entries already in the file are loaded now (lines of the form
+ * "fir <arch> <M> <C> <log2 N> <class> <algo> <compute> <ms>"; arch "*"
+ * matches any device), and the whole cache is rewritten there after every
+ * tuning run.  NULL or "" keeps the cache in memory only.  Malformed lines
+ * are skipped and reported as TFX_E_INVALID_ARG after the rest is loaded. */
+tfx_status tfx_set_tuning_cache(const char *path);
 
 /* ------------------------------------------------------- batched clips */
 

@@ -67,21 +67,40 @@ tfx_status check_ws(void *ws, size_t ws_bytes, size_t need) {
     return TFX_OK;
 }
 
-// Validates the FIR request and picks the kernel path (*mode).
-tfx_status check_fir_mode(int32_t M, tfx_compute cmp, tfx_fir_algo algo, int32_t *mode) {
+// Default fp32 FIR path by tap count: direct up to 48 taps, one 4096-point
+// FFT per 3072-sample block up to 1025, one 16384-point FFT per 8192-sample
+// block up to 8193, partitioned 4096-point FFTs beyond.
+int32_t auto_fir_mode(int32_t M) {
+    if (M <= 48) return tfx::FIR_DIRECT;
+    if (M > tfx::FFT_PART && M <= tfx::FFT16_MAX_TAPS) return tfx::FIR_FFT16;
+    return tfx::FIR_FFT;
+}
+
+// Validates the FIR request and picks the kernel path (*mode).  With
+// `tuned` (FIR-only calls of shape C x N), an automatic fp32 choice takes the
+// form tfx_fir_autotune recorded for this shape, if any.
+tfx_status check_fir_mode(int32_t M, tfx_compute cmp, tfx_fir_algo algo, int32_t *mode, int64_t C = 0,
+                          int64_t N = 0, bool tuned = false) {
+    if (tuned && algo == TFX_FIR_AUTO && cmp == TFX_COMPUTE_F32 && M >= 1 && M <= tfx::MAX_TAPS) {
+        int32_t ta = 0, tc = 0;
+        if (tfx::tuned_fir_algo(M, C, N, &ta, &tc) && tc == TFX_COMPUTE_F32) algo = (tfx_fir_algo)ta;
+    }
     if (M < 1 || M > tfx::MAX_TAPS) return fail(TFX_E_INVALID_ARG, "tap count M must be in [1, %d] (got %d)", tfx::MAX_TAPS, M);
     if (cmp < TFX_COMPUTE_F32 || cmp > TFX_COMPUTE_BF16X3) return fail(TFX_E_INVALID_ARG, "unknown compute mode %d", (int)cmp);
-    if (algo < TFX_FIR_AUTO || algo > TFX_FIR_FFT) return fail(TFX_E_INVALID_ARG, "unknown FIR algorithm %d", (int)algo);
+    if (algo < TFX_FIR_AUTO || algo > TFX_FIR_FFT16K) return fail(TFX_E_INVALID_ARG, "unknown FIR algorithm %d", (int)algo);
     if (cmp != TFX_COMPUTE_F32) {  // low-precision operands: only the matrix-core path
-        if (algo == TFX_FIR_DIRECT || algo == TFX_FIR_FFT)
+        if (algo == TFX_FIR_DIRECT || algo == TFX_FIR_FFT || algo == TFX_FIR_FFT16K)
             return fail(TFX_E_UNSUPPORTED, "the direct and FFT paths compute in fp32 only");
         *mode = tfx::FIR_TOEPLITZ;
         return TFX_OK;
     }
     if (algo == TFX_FIR_TOEPLITZ) return fail(TFX_E_UNSUPPORTED, "the Toeplitz path needs a bf16/fp16 compute mode");
+    if (algo == TFX_FIR_FFT16K && M > tfx::FFT16_MAX_TAPS)
+        return fail(TFX_E_UNSUPPORTED, "the 16384-point FFT path takes at most %d taps (got %d)", tfx::FFT16_MAX_TAPS, M);
     if (algo == TFX_FIR_DIRECT) *mode = tfx::FIR_DIRECT;
     else if (algo == TFX_FIR_FFT) *mode = tfx::FIR_FFT;
-    else *mode = M > 48 ? tfx::FIR_FFT : tfx::FIR_DIRECT;
+    else if (algo == TFX_FIR_FFT16K) *mode = tfx::FIR_FFT16;
+    else *mode = auto_fir_mode(M);
     return TFX_OK;
 }
 
@@ -144,7 +163,7 @@ tfx_status chain_plan(int64_t C, int64_t N, const tfx_stage *stages, int32_t nst
     tfx_status s = gather(stages, nstages, g);
     if (s) return s;
     int32_t mode = tfx::FIR_NONE;
-    if (g.firs.n > 0 && (s = check_fir_mode(g.Mtot, cmp, TFX_FIR_AUTO, &mode))) return s;
+    if (g.firs.n > 0 && (s = check_fir_mode(g.Mtot, cmp, TFX_FIR_AUTO, &mode, C, N, g.S == 0))) return s;
     const tfx::WsLayout lay = tfx::ws_layout(C, N, g.S, g.Mtot, g.firs.n, mode);
     if ((s = check_ws(ws, ws_bytes, lay.total))) return s;
     p.fir_mode = mode;
@@ -299,6 +318,13 @@ tfx_status stft_params(int32_t n_fft, int32_t hop, int32_t win_length, int *log2
 
 }  // namespace
 
+namespace tfx {
+tfx_status set_error(tfx_status s, const char *msg) {
+    g_last_error = msg;
+    return s;
+}
+}  // namespace tfx
+
 extern "C" {
 
 const char *tfx_status_string(tfx_status s) {
@@ -356,7 +382,7 @@ tfx_status tfx_fir_workspace_size(int64_t C, int64_t N, int32_t M, tfx_compute c
                                   size_t *bytes) {
     if (!bytes) return fail(TFX_E_INVALID_ARG, "bytes is NULL");
     int32_t mode = 0;
-    tfx_status s = check_fir_mode(M, cmp, algo, &mode);
+    tfx_status s = check_fir_mode(M, cmp, algo, &mode, C, N, true);
     if (s) return s;
     if (C < 1 || N < 0) return fail(TFX_E_INVALID_ARG, "bad shape");
     *bytes = tfx::ws_layout(C, N, 0, M, 1, mode).total;
@@ -378,7 +404,7 @@ tfx_status tfx_chain_workspace_size(int64_t C, int64_t N, const tfx_stage *stage
     tfx_status s = gather(stages, nstages, g);
     if (s) return s;
     int32_t mode = tfx::FIR_NONE;
-    if (g.firs.n > 0 && (s = check_fir_mode(g.Mtot, cmp, TFX_FIR_AUTO, &mode))) return s;
+    if (g.firs.n > 0 && (s = check_fir_mode(g.Mtot, cmp, TFX_FIR_AUTO, &mode, C, N, g.S == 0))) return s;
     *bytes = tfx::ws_layout(C, N, g.S, g.Mtot, g.firs.n, mode).total;
     return ok();
 }
@@ -388,7 +414,7 @@ tfx_status tfx_fir(const float *x, float *y, int64_t C, int64_t N, int64_t ldx, 
     tfx_status s = check_signal(x, y, C, N, ldx, ldy);
     if (s) return s;
     int32_t mode = 0;
-    if ((s = check_fir_mode(M, cmp, algo, &mode))) return s;
+    if ((s = check_fir_mode(M, cmp, algo, &mode, C, N, true))) return s;
     if (!h) return fail(TFX_E_INVALID_ARG, "taps h is NULL");
     if ((s = check_ws(ws, ws_bytes, tfx::ws_layout(C, N, 0, M, 1, mode).total))) return s;
     tfx::ChainPlan p{};
@@ -512,7 +538,7 @@ tfx_status tfx_chain_backward_workspace_size(int64_t C, int64_t N, const tfx_sta
     tfx_status s = gather(stages, nstages, g);
     if (s) return s;
     int32_t mode = tfx::FIR_NONE;
-    if (g.firs.n > 0 && (s = check_fir_mode(g.Mtot, cmp, TFX_FIR_AUTO, &mode))) return s;
+    if (g.firs.n > 0 && (s = check_fir_mode(g.Mtot, cmp, TFX_FIR_AUTO, &mode, C, N, g.S == 0))) return s;
     *bytes = tfx::bwd_layout(C, N, g.S, g.Mtot, g.firs.n, mode).total;
     return ok();
 }
@@ -524,7 +550,7 @@ tfx_status tfx_chain_backward(const float *x, const float *gy, float *gx, int64_
     tfx_status s = gather(stages, nstages, g);
     if (s) return s;
     int32_t mode = tfx::FIR_NONE;
-    if (g.firs.n > 0 && (s = check_fir_mode(g.Mtot, cmp, TFX_FIR_AUTO, &mode))) return s;
+    if (g.firs.n > 0 && (s = check_fir_mode(g.Mtot, cmp, TFX_FIR_AUTO, &mode, C, N, g.S == 0))) return s;
     tfx::BwdPlan bp{};
     if ((s = bwd_plan(x, gy, gx, C, N, ldx, ldg, ldgx, g, mode, ckpt, ws, ws_bytes, stream, bp))) return s;
     // gradient pointers in the order of the gathered stage lists
@@ -548,7 +574,7 @@ tfx_status tfx_fir_backward_workspace_size(int64_t C, int64_t N, int32_t M, tfx_
                                            size_t *bytes) {
     if (!bytes) return fail(TFX_E_INVALID_ARG, "bytes is NULL");
     int32_t mode = 0;
-    tfx_status s = check_fir_mode(M, cmp, algo, &mode);
+    tfx_status s = check_fir_mode(M, cmp, algo, &mode, C, N, true);
     if (s) return s;
     if (C < 1 || N < 0) return fail(TFX_E_INVALID_ARG, "bad shape");
     *bytes = tfx::bwd_layout(C, N, 0, M, 1, mode).total;
@@ -559,7 +585,7 @@ tfx_status tfx_fir_backward(const float *x, const float *gy, float *gx, int64_t 
                             int64_t ldg, int64_t ldgx, const float *h, int32_t M, float *gh, tfx_compute cmp,
                             tfx_fir_algo algo, void *ws, size_t ws_bytes, void *stream) {
     int32_t mode = 0;
-    tfx_status s = check_fir_mode(M, cmp, algo, &mode);
+    tfx_status s = check_fir_mode(M, cmp, algo, &mode, C, N, true);
     if (s) return s;
     if (!h) return fail(TFX_E_INVALID_ARG, "taps h is NULL");
     Gathered g;

@@ -676,6 +676,9 @@ hipError_t launch_backward(const BwdPlan &bp) {
                              : nullptr;
     // tables, merged taps, spectrum; clears the look-back records
     if ((e = launch_tables(p, lay.fwd, h, M)) != hipSuccess) return e;
+    if (has_fir && p.fir_mode == FIR_FFT16 &&
+        (e = launch_fft16k_prepare(h, M, ws + lay.fwd.f16, st)) != hipSuccess)
+        return e;
     // the cascade input f and the gradient of the cascade input gf
     const float *f = p.x;
     int64_t ldf = p.ldx;

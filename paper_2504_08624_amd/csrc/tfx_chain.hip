@@ -698,7 +698,9 @@ WsLayout ws_layout(int64_t C, int64_t N, int32_t S, int32_t M_merged, int32_t n_
     }
     w.ttab = off;
     if (fir_mode == FIR_TOEPLITZ) off += al256(toeplitz_table_bytes(M_merged, 3));  // largest (split) table
-    w.total = (S > 0 || n_fir > 1 || fir_mode == FIR_FFT || fir_mode == FIR_TOEPLITZ) ? off : 0;
+    w.f16 = off;
+    if (fir_mode == FIR_FFT16) off += al256(fft16k_table_bytes());
+    w.total = (S > 0 || n_fir > 1 || fir_mode == FIR_FFT || fir_mode == FIR_TOEPLITZ || fir_mode == FIR_FFT16) ? off : 0;
     return w;
 }
 
@@ -751,7 +753,10 @@ hipError_t launch_prepare(const ChainPlan &p) {
     const int32_t Mtot = merged_taps(p.firs);
     const WsLayout lay = ws_layout(p.C, p.N, p.S, Mtot, p.firs.n, p.fir_mode);
     hipError_t e = launch_tables(p, lay, taps_ptr(p, lay), Mtot);
-    if (e != hipSuccess || p.fir_mode != FIR_TOEPLITZ) return e;
+    if (e != hipSuccess) return e;
+    if (Mtot > 0 && p.fir_mode == FIR_FFT16)
+        return launch_fft16k_prepare(taps_ptr(p, lay), Mtot, static_cast<char *>(p.ws) + lay.f16, p.stream);
+    if (p.fir_mode != FIR_TOEPLITZ) return e;
     return launch_toeplitz_prepare(taps_ptr(p, lay), Mtot, p.cmp, static_cast<char *>(p.ws) + lay.ttab, p.stream);
 }
 
@@ -792,6 +797,15 @@ hipError_t launch_run(const ChainPlan &p) {
     // into the chain kernel (the split-bf16 form and a FIR alone run the
     // stand-alone Toeplitz kernel)
     const bool tz_fused = Mtot > 0 && p.fir_mode == FIR_TOEPLITZ && p.S > 0 && (p.cmp == TZ_BF16 || p.cmp == TZ_F16);
+    if (Mtot > 0 && p.fir_mode == FIR_FFT16) {
+        // 16384-point FFT FIR into y, then the cascade in place over y (each
+        // tile of the cascade kernel reads only the samples it writes)
+        hipError_t e = launch_fft16k(p.x, p.y, p.C, p.N, p.ldx, p.ldy, Mtot, ws + lay.f16, false, p.hist_in, p.stream);
+        if (e != hipSuccess || p.S == 0) return e;
+        k.x = p.y;
+        k.ldx = p.ldy;
+        Mtot = 0;
+    }
     if (Mtot > 0 && p.fir_mode == FIR_TOEPLITZ && !tz_fused) {
         // matrix-core FIR into y, then the cascade in place over y (each
         // tile reads only the samples it writes)
@@ -854,6 +868,8 @@ hipError_t launch_fir_pass(const ChainPlan &p, const WsLayout &lay, const float 
     const int32_t Mtot = merged_taps(p.firs);
     if (p.N == 0 || Mtot == 0) return hipSuccess;
     char *ws = static_cast<char *>(p.ws);
+    if (p.fir_mode == FIR_FFT16)
+        return launch_fft16k(in, out, p.C, p.N, ldin, ldout, Mtot, ws + lay.f16, correlate, nullptr, p.stream);
     KArgs k{};
     k.x = in;
     k.y = out;

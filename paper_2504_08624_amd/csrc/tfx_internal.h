@@ -5,6 +5,8 @@
 #include <stdint.h>
 #include <math.h>
 
+#include "tfx.h"
+
 namespace tfx {
 
 // ---- tiling ------------------------------------------------------------------
@@ -32,13 +34,18 @@ constexpr int FFT_PART = FFT_DISCARD + 1;  // taps per partition of a long filte
 // TW3 [16][16][16] (float2 entries)
 constexpr int TW1_OFF = 0, TW2_OFF = NFFT, TW3_OFF = NFFT + 256, TWID_ENTRIES = 2 * NFFT + 256;
 __host__ __device__ constexpr int fft_parts(int M) { return (M + FFT_PART - 1) / FFT_PART; }
+// One 16384-point FFT per block of 8192 outputs (tfx_fft16k.hip): filters of
+// up to 8193 taps.
+constexpr int FFT16_POINTS = 16384;
+constexpr int FFT16_HOP = 8192;
+constexpr int FFT16_MAX_TAPS = FFT16_HOP + 1;
 
 constexpr int MAX_STAGES = 64;
 constexpr int MAX_SECTIONS = 256;
 constexpr int MAX_TAPS = 65536;
 constexpr int BWD_MAX_SECTIONS = 16;  // adjoint: chunk states of every section stay in LDS
 
-enum FirMode { FIR_NONE = 0, FIR_DIRECT = 1, FIR_FFT = 2, FIR_TOEPLITZ = 3 };
+enum FirMode { FIR_NONE = 0, FIR_DIRECT = 1, FIR_FFT = 2, FIR_TOEPLITZ = 3, FIR_FFT16 = 4 };
 
 // Per-section tables built on the device from the fp32 coefficients (in FP64,
 // then rounded).  2x2 matrices are row-major {m00, m01, m10, m11}.
@@ -166,10 +173,18 @@ struct ChainPlan {
 
 // Workspace layout of a chain/SOS/FIR call.
 struct WsLayout {
-    size_t hdr, tab, recs, casc, zir, taps, merge, twid, hspec, tw64, ttab, total;
+    size_t hdr, tab, recs, casc, zir, taps, merge, twid, hspec, tw64, ttab, f16, total;
     int64_t ntiles, cpad;
 };
 WsLayout ws_layout(int64_t C, int64_t N, int32_t S, int32_t M_merged, int32_t n_fir, int32_t fir_mode);
+
+// Sets the calling thread's tfx_last_error message and returns s (for entry
+// points defined outside tfx_api.cpp).
+tfx_status set_error(tfx_status s, const char *msg);
+
+// The FIR form tfx_fir_autotune recorded for an fp32 call of this shape
+// (false when there is none).
+bool tuned_fir_algo(int32_t M, int64_t C, int64_t N, int32_t *algo, int32_t *cmp);
 
 // Status word of a workspace into *flags (tfx_workspace_status).
 hipError_t launch_ws_status(void *ws, uint32_t *flags, int32_t clear, hipStream_t st);
@@ -194,6 +209,15 @@ size_t toeplitz_table_bytes(int32_t M, int32_t cmp);
 hipError_t launch_toeplitz_prepare(const float *h, int32_t M, int32_t cmp, void *tab, hipStream_t st);
 hipError_t launch_toeplitz(const float *x, float *y, int64_t C, int64_t N, int64_t ldx, int64_t ldy, int32_t M,
                            int32_t cmp, const void *tab, hipStream_t st, const float *hist = nullptr);
+
+// ---- overlap-save FIR with 16384-point FFTs (tfx_fft16k.hip) --------------------
+// Twiddle tables and tap spectrum of the 16384-point path.
+size_t fft16k_table_bytes();
+hipError_t launch_fft16k_prepare(const float *h, int32_t M, void *tab, hipStream_t st);
+// FIR (or, with correlate, its adjoint correlation) x -> y; hist: streaming
+// history [C][M - 1] before the block (convolution only), or null.
+hipError_t launch_fft16k(const float *x, float *y, int64_t C, int64_t N, int64_t ldx, int64_t ldy, int32_t M,
+                         const void *tab, bool correlate, const float *hist, hipStream_t st);
 
 // ---- batched ragged clips (tfx_batched.hip) -------------------------------------
 // Device descriptor of one clip, in processing order.  Blocks of the single

@@ -125,6 +125,41 @@ def _fir_raw(x: torch.Tensor, h, compute: str = "f32", algo: str = "auto") -> to
     return y[0] if squeeze else y
 
 
+_ALGO_NAMES = {v: k for k, v in lib.FIR_ALGO.items()}
+_COMPUTE_NAMES = {v: k for k, v in lib.COMPUTE.items()}
+
+
+def fir_autotune(x: torch.Tensor, h, tol: float = 1e-5, reps: int = 3):
+    """Times every FIR form whose stated accuracy is within ``tol`` on this
+    signal and these taps (tfx_fir_autotune) and returns (algo, compute, ms)
+    of the fastest; an fp32 ``fir(x, h)`` of this shape then uses it.
+    Synchronises the device."""
+    x2, squeeze, ld = _signal(x)
+    C, N = x2.shape
+    h = _coef(h, x.device).reshape(-1)
+    y = torch.empty((C, N), dtype=torch.float32, device=x.device)
+    nb = lib.size_out()
+    lib.call("tfx_fir_autotune_workspace_size", C, N, h.numel(), float(tol), nb)
+    ws, wsb = _workspace(nb.value, x.device)
+    a, c, ms = ctypes.c_int32(0), ctypes.c_int32(0), ctypes.c_float(0.0)
+    lib.call("tfx_fir_autotune", _ptr(x2), _ptr(y), C, N, ld, max(N, 1), _ptr(h), h.numel(), float(tol), int(reps),
+             _ptr(ws), wsb, _stream(x.device), a, c, ms)
+    _track(ws, wsb, x.device)
+    return _ALGO_NAMES[a.value], _COMPUTE_NAMES[c.value], float(ms.value)
+
+
+def set_tuning_cache(path):
+    """Makes the FIR tuning cache persistent in a text file (None: memory only)."""
+    lib.call("tfx_set_tuning_cache", None if path is None else str(path).encode())
+
+
+def fir_tuned(C: int, N: int, M: int, tol: float = 1e-5):
+    """(algo, compute) recorded by fir_autotune for this shape, or ("auto", "f32")."""
+    a, c = ctypes.c_int32(0), ctypes.c_int32(0)
+    lib.call("tfx_fir_tuned", int(C), int(N), int(M), float(tol), a, c)
+    return _ALGO_NAMES[a.value], _COMPUTE_NAMES[c.value]
+
+
 def _sos_raw(x: torch.Tensor, sections, state_in=None, return_state: bool = False,
              return_ckpt: bool = False):
     x2, squeeze, ld = _signal(x)

@@ -21,7 +21,7 @@ STATUS_NAMES = {0: "TFX_OK", 1: "TFX_E_INVALID_ARG", 2: "TFX_E_UNSUPPORTED", 3: 
 TFX_E_DEVICE = 8
 DEV_LOOKBACK_TIMEOUT = 1
 COMPUTE = {"f32": 0, "bf16": 1, "f16": 2, "bf16x3": 3}
-FIR_ALGO = {"auto": 0, "direct": 1, "toeplitz": 2, "fft": 3}
+FIR_ALGO = {"auto": 0, "direct": 1, "toeplitz": 2, "fft": 3, "fft16k": 4}
 STAGE_FIR, STAGE_SOS = 0, 1
 
 
@@ -53,6 +53,11 @@ _SIGS = {
     "tfx_sos_tile_length": (_i64, []),
     "tfx_sos_check_stable": (_i32, [_vp, _i32, ctypes.POINTER(_i32)]),
     "tfx_workspace_status": (_i32, [_vp, _sz, _vp, _i32, _vp]),
+    "tfx_fir_autotune_workspace_size": (_i32, [_i64, _i64, _i32, ctypes.c_double, ctypes.POINTER(_sz)]),
+    "tfx_fir_autotune": (_i32, [_vp, _vp, _i64, _i64, _i64, _i64, _vp, _i32, ctypes.c_double, _i32, _vp, _sz, _vp,
+                                ctypes.POINTER(_i32), ctypes.POINTER(_i32), ctypes.POINTER(ctypes.c_float)]),
+    "tfx_fir_tuned": (_i32, [_i64, _i64, _i32, ctypes.c_double, ctypes.POINTER(_i32), ctypes.POINTER(_i32)]),
+    "tfx_set_tuning_cache": (_i32, [ctypes.c_char_p]),
     "tfx_fir_workspace_size": (_i32, [_i64, _i64, _i32, _i32, _i32, ctypes.POINTER(_sz)]),
     "tfx_sos_workspace_size": (_i32, [_i64, _i64, _i32, ctypes.POINTER(_sz)]),
     "tfx_chain_workspace_size": (_i32, [_i64, _i64, ctypes.POINTER(Stage), _i32, _i32, ctypes.POINTER(_sz)]),

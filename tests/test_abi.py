@@ -206,3 +206,46 @@ def test_workspace_status_arguments():
     assert _st("tfx_workspace_status", FAKE, 128, FAKE, 1, None) == "TFX_OK"
     assert _st("tfx_workspace_status", FAKE + 8, 4096, FAKE, 1, None) == "TFX_E_WORKSPACE"
     assert lib.STATUS_NAMES[lib.TFX_E_DEVICE] == "TFX_E_DEVICE"
+
+
+def test_tuning_cache_file_drives_the_automatic_choice(tmp_path):
+    """An entry of the persistent tuning cache (arch "*": any device) decides
+    TFX_FIR_AUTO for its (M, C, log2 N) key: the 777-tap, 5-channel, 2^9..2^10
+    sample shape is sent to the direct form (no workspace) instead of the FFT
+    (a workspace); the neighbouring tap count keeps the fixed rule.  Lines
+    that are malformed or name a form the key does not admit are skipped and
+    reported."""
+    import paper_2504_08624_amd as tfx
+    n = ctypes.c_size_t(0)
+    assert _st("tfx_fir_workspace_size", 5, 1000, 777, 0, 0, ctypes.byref(n)) == "TFX_OK" and n.value > 0
+    path = tmp_path / "tune.txt"
+    path.write_text("# comment\n"
+                    "fir * 777 5 9 0 1 0 0.25\n"          # direct, fp32, class 1e-5
+                    "fir * 777 5 9 2 2 1 0.10\n"          # Toeplitz bf16 for the 1e-2 class
+                    "fir * 9000 5 9 0 4 0 0.5\n"          # the 16384-point form cannot take 9000 taps
+                    "fir * 777 5 9 0 2 1 0.1\n"           # bf16 is not admitted at 1e-5
+                    "garbage\n")
+    L = lib.load()
+    assert lib.STATUS_NAMES[L.tfx_set_tuning_cache(str(path).encode())] == "TFX_E_INVALID_ARG"
+    assert b"3 malformed" in L.tfx_last_error()
+    assert tfx.fir_tuned(5, 1000, 777) == ("direct", "f32")
+    assert tfx.fir_tuned(5, 1000, 777, tol=1e-2) == ("toeplitz", "bf16")
+    assert tfx.fir_tuned(5, 1000, 778) == ("auto", "f32")
+    assert tfx.fir_tuned(5, 5000, 777) == ("auto", "f32")        # another log2 N bucket
+    assert _st("tfx_fir_workspace_size", 5, 1000, 777, 0, 0, ctypes.byref(n)) == "TFX_OK" and n.value == 0
+    assert _st("tfx_fir_workspace_size", 5, 1000, 778, 0, 0, ctypes.byref(n)) == "TFX_OK" and n.value > 0
+    tfx.set_tuning_cache(None)  # memory only from here on; the entries stay
+
+
+def test_autotune_arguments():
+    n16 = ctypes.c_size_t(0)
+    n2 = ctypes.c_size_t(0)
+    assert _st("tfx_fir_autotune_workspace_size", 8, 100_000, 1023, 1e-5, ctypes.byref(n16)) == "TFX_OK"
+    assert _st("tfx_fir_autotune_workspace_size", 8, 100_000, 1023, 1e-2, ctypes.byref(n2)) == "TFX_OK"
+    assert n2.value >= n16.value > 0
+    assert _st("tfx_fir_autotune_workspace_size", 8, 100_000, 1023, 1e-6, ctypes.byref(n2)) == "TFX_E_UNSUPPORTED"
+    a, c, ms = ctypes.c_int32(0), ctypes.c_int32(0), ctypes.c_float(0)
+    assert _st("tfx_fir_autotune", FAKE, FAKE + (1 << 30), 2, 10, 10, 10, FAKE, 5, 1e-6, 1, None, 0, None,
+               ctypes.byref(a), ctypes.byref(c), ctypes.byref(ms)) == "TFX_E_UNSUPPORTED"
+    assert _st("tfx_fir_autotune", FAKE, FAKE + (1 << 30), 2, 10, 10, 10, FAKE, 5, 1e-5, 0, None, 0, None,
+               ctypes.byref(a), ctypes.byref(c), ctypes.byref(ms)) == "TFX_E_INVALID_ARG"   # reps = 0
