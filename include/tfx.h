@@ -392,6 +392,25 @@ tfx_status tfx_istft(const float *spec, int64_t C, int64_t T, int32_t n_fft, int
                      int32_t win_length, int32_t center, int32_t normalized, float *y, int64_t length, int64_t ldy,
                      void *stream);
 
+/* ------------------------------------------------------------------- FFT */
+
+/* Batched real FFT, the other transform on the roadmap of Sec. 5 (textbook
+ * definition, numpy.fft.rfft / irfft conventions):
+ *
+ *   X[b,k] = sum_{m<n} x[b,m] exp(-2 pi i k m / n),  k = 0 .. n/2,
+ *   y[b,m] = (1/n) (X[b,0] + X[b,n/2] (-1)^m
+ *                   + 2 Re sum_{k=1}^{n/2-1} X[b,k] exp(+2 pi i k m / n)),
+ *
+ * the imaginary parts of bins 0 and n/2 ignored by the inverse.  n: a power
+ * of two in [16, 4096] (TFX_E_UNSUPPORTED otherwise).  x / y: B rows of n
+ * fp32 samples, row stride ldx / ldy >= n.  spec: [B][n/2+1] complex as
+ * interleaved (re, im) fp32, contiguous, not overlapping x or y.  Both run
+ * the STFT kernels with one rectangular frame per row (two rows share one
+ * complex FFT when the rows are contiguous, ld == n); no workspace.  B == 0 is
+ * a no-op. */
+tfx_status tfx_rfft(const float *x, int64_t B, int32_t n, int64_t ldx, float *spec, void *stream);
+tfx_status tfx_irfft(const float *spec, int64_t B, int32_t n, float *y, int64_t ldy, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

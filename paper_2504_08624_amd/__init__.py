@@ -10,10 +10,10 @@ from .functional import (ChainStream, SosBatch, chain, chain_backward, check_dev
                          sos_backward, sos_batched, tile_length)
 from .filters import (FIR, SOS, AllPass, BandPass, Butterworth, ButterworthBand, Chebyshev1, Chebyshev2,  # noqa: F401
                       DirectForm, Filter, HiShelving, LoShelving, Notch, Peaking, WindowedSincFIR)
-from .spectral import istft, stft  # noqa: F401
+from .spectral import irfft, istft, rfft, stft  # noqa: F401
 from .wave import Wave  # noqa: F401
 
-__all__ = ["fir", "sos", "chain", "lfilter", "stft", "istft", "ChainStream", "fir_backward", "sos_backward", "chain_backward", "sos_batched", "SosBatch",
+__all__ = ["fir", "sos", "chain", "lfilter", "stft", "istft", "rfft", "irfft", "ChainStream", "fir_backward", "sos_backward", "chain_backward", "sos_batched", "SosBatch",
            "tile_length", "device_status", "check_device_status", "fir_autotune", "fir_tuned",
            "set_tuning_cache", "Wave", "Filter", "Butterworth", "Chebyshev1", "Peaking", "HiShelving", "LoShelving",
            "WindowedSincFIR", "FIR", "SOS", "Chebyshev2", "ButterworthBand", "Notch", "AllPass", "BandPass",

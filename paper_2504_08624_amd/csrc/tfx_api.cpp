@@ -786,4 +786,64 @@ tfx_status tfx_istft(const float *spec, int64_t C, int64_t T, int32_t n_fft, int
     return e == hipSuccess ? ok() : hip_fail(e, "istft kernel");
 }
 
+// ---- batched real FFT ------------------------------------------------------------
+// Both run the STFT kernels: every row is one rectangular, uncentred frame
+// (hop = n).  Rows that follow each other in memory (ld == n) form a single
+// signal of B frames, so the kernels pair frames two to a complex FFT across
+// rows; other strides give B channels of one frame each.
+
+tfx_status tfx_rfft(const float *x, int64_t B, int32_t n, int64_t ldx, float *spec, void *stream) {
+    tfx::StftPlan sp{};
+    tfx_status s = stft_params(n, n, n, &sp.log2n);
+    if (s) return s;
+    if (B < 0 || B >= (int64_t(1) << 40) / n) return fail(TFX_E_INVALID_ARG, "B out of range (got %lld)", (long long)B);
+    if (ldx < n) return fail(TFX_E_INVALID_ARG, "ldx must be >= n");
+    if (B == 0) return ok();
+    if (!x || !spec) return fail(TFX_E_INVALID_ARG, "x and spec must be non-null");
+    const size_t sbytes = (size_t)B * (size_t)(n / 2 + 1) * 2 * sizeof(float);
+    if (overlaps(x, span_bytes(B, n, ldx), spec, sbytes)) return fail(TFX_E_ALIAS, "spec overlaps x");
+    const bool packed = ldx == n;
+    sp.hop = n;
+    sp.win_length = n;
+    sp.center = 0;
+    sp.normalized = 0;
+    sp.win = nullptr;
+    sp.C = packed ? 1 : B;
+    sp.T = packed ? B : 1;
+    sp.x = x;
+    sp.nx = packed ? B * (int64_t)n : n;
+    sp.ldx = packed ? sp.nx : ldx;
+    sp.spec = spec;
+    sp.stream = static_cast<hipStream_t>(stream);
+    hipError_t e = tfx::launch_stft(sp);
+    return e == hipSuccess ? ok() : hip_fail(e, "rfft kernel");
+}
+
+tfx_status tfx_irfft(const float *spec, int64_t B, int32_t n, float *y, int64_t ldy, void *stream) {
+    tfx::StftPlan sp{};
+    tfx_status s = stft_params(n, n, n, &sp.log2n);
+    if (s) return s;
+    if (B < 0 || B >= (int64_t(1) << 38) / n) return fail(TFX_E_INVALID_ARG, "B out of range (got %lld)", (long long)B);
+    if (ldy < n) return fail(TFX_E_INVALID_ARG, "ldy must be >= n");
+    if (B == 0) return ok();
+    if (!spec || !y) return fail(TFX_E_INVALID_ARG, "spec and y must be non-null");
+    const size_t sbytes = (size_t)B * (size_t)(n / 2 + 1) * 2 * sizeof(float);
+    if (overlaps(y, span_bytes(B, n, ldy), spec, sbytes)) return fail(TFX_E_ALIAS, "y overlaps spec");
+    const bool packed = ldy == n;
+    sp.hop = n;
+    sp.win_length = n;
+    sp.center = 0;
+    sp.normalized = 0;
+    sp.win = nullptr;
+    sp.C = packed ? 1 : B;
+    sp.T = packed ? B : 1;
+    sp.spec_in = spec;
+    sp.y = y;
+    sp.length = packed ? B * (int64_t)n : n;
+    sp.ldy = packed ? sp.length : ldy;
+    sp.stream = static_cast<hipStream_t>(stream);
+    hipError_t e = tfx::launch_istft(sp);
+    return e == hipSuccess ? ok() : hip_fail(e, "irfft kernel");
+}
+
 }  // extern "C"

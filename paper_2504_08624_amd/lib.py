@@ -83,6 +83,8 @@ _SIGS = {
     "tfx_sos_batched": (_i32, [ctypes.POINTER(Clip), _i32, ctypes.POINTER(BatchConfig), _vp, _sz, _vp]),
     "tfx_sos_batched_tune": (_i32, [ctypes.POINTER(Clip), _i32, _i32, _vp, _sz, _vp, ctypes.POINTER(BatchConfig),
                                     ctypes.POINTER(ctypes.c_float)]),
+    "tfx_rfft": (_i32, [_vp, _i64, _i32, _i64, _vp, _vp]),
+    "tfx_irfft": (_i32, [_vp, _i64, _i32, _vp, _i64, _vp]),
     "tfx_stft_frames": (_i32, [_i64, _i32, _i32, _i32, ctypes.POINTER(_i64)]),
     "tfx_stft": (_i32, [_vp, _i64, _i64, _i64, _i32, _i32, _vp, _i32, _i32, _i32, _vp, _vp]),
     "tfx_istft": (_i32, [_vp, _i64, _i64, _i32, _i32, _vp, _i32, _i32, _i32, _vp, _i64, _i64, _vp]),

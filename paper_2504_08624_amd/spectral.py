@@ -108,3 +108,38 @@ def istft(spec: torch.Tensor, n_fft: int, hop_length=None, win_length=None, wind
     lib.call("tfx_istft", fm.data_ptr(), C, T, n_fft, hop, _ptr(w), wl, int(bool(center)), int(bool(normalized)),
              y.data_ptr() if L else None, L, max(L, 1), _stream(spec.device))
     return y[0] if squeeze else y
+
+
+def rfft(x: torch.Tensor) -> torch.Tensor:
+    """One-sided DFT of every row of a float32 tensor [..., n] (n a power of
+    two from 16 to 4096): complex64 [..., n/2 + 1], numpy.fft.rfft's
+    convention (no scaling)."""
+    if not isinstance(x, torch.Tensor) or x.device.type != "cuda":
+        raise TypeError("tfx runs on the GPU only")
+    if x.dtype != torch.float32:
+        raise TypeError("rfft takes float32 rows")
+    n = x.shape[-1]
+    rows = x.reshape(-1, n)
+    if rows.stride(1) != 1:
+        rows = rows.contiguous()
+    B = rows.shape[0]
+    ld = rows.stride(0) if B > 1 else n
+    spec = torch.empty((B, n // 2 + 1), dtype=torch.complex64, device=x.device)
+    lib.call("tfx_rfft", _ptr(rows) if B else None, B, n, ld, spec.data_ptr() if B else None, _stream(x.device))
+    return spec.reshape(*x.shape[:-1], n // 2 + 1)
+
+
+def irfft(spec: torch.Tensor, n: int) -> torch.Tensor:
+    """Inverse of ``rfft`` for rows of n samples: float32 [..., n] from
+    complex [..., n/2 + 1] (the imaginary parts of bins 0 and n/2 are
+    ignored), numpy.fft.irfft's convention (1/n scaling)."""
+    if not isinstance(spec, torch.Tensor) or spec.device.type != "cuda":
+        raise TypeError("tfx runs on the GPU only")
+    n = int(n)
+    if spec.shape[-1] != n // 2 + 1:
+        raise ValueError("spectrum has %d bins, n = %d needs %d" % (spec.shape[-1], n, n // 2 + 1))
+    s2 = spec.reshape(-1, n // 2 + 1).to(torch.complex64).contiguous()
+    B = s2.shape[0]
+    y = torch.empty((B, n), dtype=torch.float32, device=spec.device)
+    lib.call("tfx_irfft", s2.data_ptr() if B else None, B, n, y.data_ptr() if B else None, n, _stream(spec.device))
+    return y.reshape(*spec.shape[:-1], n)
