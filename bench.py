@@ -49,21 +49,28 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0        # MI355X published HBM3E bandwidth
 MFMA_BF16_PEAK_TFS = 2500.0  # dense bf16 / fp16 matrix peak
+MFMA_F32_PEAK_TFS = 157.3    # dense fp32 matrix peak
 # fp32 vector peak without packed-FP32 instructions (disabled at build time):
 # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz
 VALU_F32_PEAK_TFS = 78.6
 
 
-def chain_flops_per_sample(M, S):
-    """Algorithmic flops per channel-sample of the fused FFT-FIR + SOS kernel:
-    per 6144 channel-samples (one channel pair, one 3072-sample tile) one
+def fft_flops_per_sample(M):
+    """Vector-unit flops per channel-sample of the fused kernel's FFT FIR: per
+    6144 channel-samples (one channel pair, one 3072-sample tile) one
     4096-point complex FFT per tap partition of 1025 plus one inverse
     (5 N log2 N each) and the spectrum products (6 flops per bin and
-    partition); per section 9 (TDF-II) + 4 (zero-input correction) + 2 (scan
-    and fold)."""
+    partition)."""
     parts = (M + 1024) // 1025
     fft = (parts + 1) * 5 * 4096 * 12 + parts * 6 * 4096
-    return fft / 6144.0 + 15.0 * S
+    return fft / 6144.0
+
+
+def cascade_mfma_flops_per_sample():
+    """Matrix-core flops per channel-sample of the cascade (16 x 16 x 4 fp32
+    steps as issued): per 32-sample chunk [Tc; H] (48 x 32) times the chunk and
+    G (32 x 16) times its entering state."""
+    return (2 * 48 * 32 + 2 * 32 * 16) / 32.0
 
 
 def measured_traffic():
@@ -80,6 +87,16 @@ def measured_traffic():
     except (OSError, ValueError, KeyError):
         return None
     return rec["traffic_bytes_per_launch"] if h.hexdigest() == rec["sources_sha256"] else None
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def parse():
@@ -142,8 +159,13 @@ def secondary(torch, dev, stream):
     pos = np.linspace(0, w.x.shape[1] - 1, 257).astype(np.int64)
     chans = [0, 21, 63]
     ref = O.fir_at(w.x[chans], w.stages[0][1], pos)
-    res = {"workload": "64 x 5,760,000, 8191-tap low-pass", "error": "rel RMS on 3 ch x 257 sampled outputs"}
-    for name, kw, tol in [("fft_f32", {}, 1e-5), ("toeplitz_bf16", {"compute": "bf16"}, 1e-2),
+    o_sec = O.last_seconds()
+    res = {"workload": "64 x 5,760,000, 8191-tap low-pass", "error": "rel RMS on 3 ch x 257 sampled outputs",
+           "oracle": {"Msamples_per_s": round(len(chans) * pos.size / o_sec / 1e6, 4),
+                      "cores": min(len(chans), O.threads()),
+                      "sample": "3 ch x 257 outputs by direct convolution, steady clock around the C loop"}}
+    for name, kw, tol in [("fft_f32", {}, 1e-5), ("fft4096_parts_f32", {"algo": "fft"}, 1e-5),
+                          ("toeplitz_bf16", {"compute": "bf16"}, 1e-2),
                           ("toeplitz_f16", {"compute": "f16"}, 1e-2), ("toeplitz_bf16x3", {"compute": "bf16x3"}, None)]:
         s = timed(torch, lambda: tfx.fir(x, h, **kw), 3, stream)
         yy = tfx.fir(x, h, **kw)[chans][:, pos].cpu().numpy()
@@ -166,15 +188,70 @@ def secondary(torch, dev, stream):
     b = tfx.SosBatch(xs, ss)
     cfg, _ = b.tune(reps=2)
     s_b = timed(torch, b.run, 5, stream)
+    # the batch as one captured graph (one hipGraphLaunch per replay)
+    gs = torch.cuda.Stream()
+    gs.wait_stream(stream)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(gs):
+        with torch.cuda.graph(graph, stream=gs):
+            b.run()
+    stream.wait_stream(gs)
+    s_g = timed(torch, graph.replay, 10, stream)
     s_l = timed(torch, lambda: [tfx.sos(a, c) for a, c in zip(xs, ss)], 3, stream)
-    ys = b.run()
+    graph.replay()
+    ys = b.ys
     errs = [rel_err(ys[i].cpu().numpy(), O.sos(clips[i][0], clips[i][1])) for i in (0, 97, 201)]
+    c0 = time.perf_counter()
+    c_sec = 0.0
+    c_n = 0
+    for i in (0, 97, 201):
+        O.sos(clips[i][0], clips[i][1])
+        c_sec += O.last_seconds()
+        c_n += clips[i][0].size
     out["ragged_batch"] = {"workload": "256 clips @44.1 kHz, 1-30 s, 1-16 ch, 1-6 SOS each",
-                           "samples": n, "tuned": cfg, "Msamples_per_s": round(n / s_b / 1e6, 1),
-                           "ms": round(s_b * 1e3, 3), "per_clip_calls_ms": round(s_l * 1e3, 3),
-                           "speedup_vs_per_clip": round(s_l / s_b, 2), "rel_err_3_clips": max(errs),
-                           "tolerance": 1e-4}
-    del xs, ss, b, ys
+                           "samples": n, "tuned": cfg, "Msamples_per_s": round(n / s_g / 1e6, 1),
+                           "ms": round(s_g * 1e3, 3), "timing": "one hipGraph replay of the batched run",
+                           "eager_run_ms": round(s_b * 1e3, 3),
+                           "hbm_frac": round(8.0 * n / s_g / 1e9 / HBM_PEAK_GBS, 4),
+                           "per_clip_calls_ms": round(s_l * 1e3, 3),
+                           "speedup_vs_per_clip": round(s_l / s_g, 2), "rel_err_3_clips": max(errs),
+                           "tolerance": 1e-4,
+                           "oracle": {"Msamples_per_s": round(c_n / c_sec / 1e6, 3), "cores": O.threads(),
+                                      "sample": "clips 0, 97 and 201 (%d samples), steady clock around the C loops"
+                                                % c_n}}
+    del xs, ss, b, ys, graph
+
+    log("chain_short_large (C1-L)")
+    w = workloads.chain_mid_short_fir()
+    x = torch.from_numpy(w.x).to(dev)
+    st = [(k, torch.from_numpy(c).to(dev)) for k, c in w.stages]
+    s = timed(torch, lambda: tfx.chain(x, st), 20, stream)
+    y = tfx.chain(x, st)[:2].cpu().numpy()
+    out["chain_short_large"] = {"workload": "8 x 5,760,000, chain_short's filters (101-tap FIR | Butterworth HP, "
+                                            "2 SOS), one tfx_chain call",
+                                "Msamples_per_s": round(x.numel() / s / 1e6, 1), "ms": round(s * 1e3, 4),
+                                "hbm_frac": round(8.0 * x.numel() / s / 1e9 / HBM_PEAK_GBS, 4),
+                                "rel_err_2ch": rel_err(y, O.chain(w.x[:2], w.stages)), "tolerance": 1e-4}
+    del x, st
+
+    log("learnable: forward, forward + backward")
+    x_np, params, target = workloads.learnable()
+    x = torch.from_numpy(x_np).to(dev)
+    st = [(k, torch.from_numpy(c).to(dev)) for k, c in target]
+    gup = torch.from_numpy(np.random.default_rng(12).standard_normal(x_np.shape).astype(np.float32)).to(dev)
+    s_f = timed(torch, lambda: tfx.chain(x, st), 20, stream)
+
+    def fb():
+        yv, ck = tfx.chain(x, st, return_ckpt=True)
+        return tfx.chain_backward(x, gup, st, ck)
+    s_fb = timed(torch, fb, 20, stream)
+    out["learnable_fwd_bwd"] = {"workload": "64 x 192,000 (32 x 2 ch), 255-tap FIR | 8 SOS",
+                                "fwd_Msamples_per_s": round(x.numel() / s_f / 1e6, 1), "fwd_ms": round(s_f * 1e3, 4),
+                                "fwd_bwd_Msamples_per_s": round(x.numel() / s_fb / 1e6, 1),
+                                "fwd_bwd_ms": round(s_fb * 1e3, 4), "ratio_to_fwd": round(s_f / s_fb, 4),
+                                "step": "tfx_chain (+ checkpoints) and tfx_chain_backward for a fixed upstream "
+                                        "gradient (input, taps and section gradients)"}
+    del x, st, gup
 
     log("learnable fwd+bwd")
     x_np, params, target = workloads.learnable()
@@ -347,6 +424,13 @@ def main():
         lib.check(L.tfx_chain_run(x.data_ptr(), y.data_ptr(), C, N, N, N, arr, nst, 0, None,
                                   ws.data_ptr(), ws.numel(), sp), "tfx_chain_run")
 
+    # device status word of the workspace, folded after every run (before the
+    # next prepare clears it): a look-back that gave up would flag it
+    flags = torch.zeros(1, dtype=torch.int32, device=dev)
+
+    def fold():
+        lib.check(L.tfx_workspace_status(ws.data_ptr(), ws.numel(), flags.data_ptr(), 1, sp), "tfx_workspace_status")
+
     log("warmup %d" % args.warmup)
     for _ in range(args.warmup):
         prepare()
@@ -364,7 +448,10 @@ def main():
         ev[i][0].record(stream)
         run()
         ev[i][1].record(stream)
+        fold()
     torch.cuda.synchronize()
+    if int(flags.item()) != 0:
+        raise RuntimeError("a timed step flagged its workspace (status word 0x%x)" % int(flags.item()))
     t1 = time.perf_counter()
     wall = t1 - t0
     kern_ms = np.array([a.elapsed_time(b) for a, b in ev])
@@ -382,6 +469,7 @@ def main():
         prepare()
         run()
         b.record(stream)
+        fold()
         torch.cuda.synchronize()
         cold.append(a.elapsed_time(b))
     del flush
@@ -392,11 +480,12 @@ def main():
     value = samples / (wall / K) / 1e6
     alg_bytes = 8.0 * samples
     S_tot = int(sum(s[1].shape[0] for s in w.stages if s[0] == "sos"))
-    fps = chain_flops_per_sample(int(w.stages[0][1].size), S_tot)
-    alg_flops = fps * samples
+    fps = fft_flops_per_sample(int(w.stages[0][1].size))
+    mps = cascade_mfma_flops_per_sample()
     kern_s = float(kern_ms.mean()) / 1e3
     achieved_gbs = alg_bytes / kern_s / 1e9
-    achieved_tfs = alg_flops / kern_s / 1e12
+    achieved_tfs = fps * samples / kern_s / 1e12
+    mfma_tfs = mps * samples / kern_s / 1e12
     out = y.cpu().numpy()
 
     # achievable copy bandwidth: a plain device copy of the input (also the
@@ -445,21 +534,27 @@ def main():
     if not args.no_cpu_baseline:
         from oracle import oracle as O
         O.build()
-        threads = min(C, len(os.sched_getaffinity(0)), int(os.environ.get("OMP_NUM_THREADS", "1024")))
+        threads = min(C, O.threads())
         Ns = N  # the whole input: a few seconds of CPU work
         log("oracle on 8 x %d samples (%d threads)" % (Ns, threads))
-        c0 = time.perf_counter()
-        ref = O.chain(w.x[:, :Ns], w.stages)
-        c1 = time.perf_counter()
-        cpu = {"value": round(C * Ns / (c1 - c0) / 1e6, 3), "unit": "Msamples/s", "cores": threads,
-               "kind": "oracle",
-               "sample": "the whole headline input (8 x 5,760,000), whole chain, FP64, %.1f s" % (c1 - c0)}
+
+        def oracle_chain(xs):
+            """The oracle's chain, stage by stage; returns (y, seconds of the
+            C filtering loops, steady clock)."""
+            yv, sec = xs, 0.0
+            for kind, coef in w.stages:
+                yv = O.chain(yv, [(kind, coef)])
+                sec += O.last_seconds()
+            return yv, sec
+        ref, c_sec = oracle_chain(w.x[:, :Ns])
+        cpu = {"value": round(C * Ns / c_sec / 1e6, 3), "unit": "Msamples/s", "cores": threads,
+               "kind": "oracle", "cpu_model": cpu_model(),
+               "sample": "the whole headline input (8 x 5,760,000), whole chain, FP64, one thread per channel; "
+                         "steady clock around the C loops, %.2f s" % c_sec}
         err = rel_err(out[:, :Ns], ref)
-        c0 = time.perf_counter()
-        O.chain(w.x[:1, :Ns], w.stages)  # one channel: one thread
-        c1 = time.perf_counter()
-        cpu["single_thread"] = {"value": round(Ns / (c1 - c0) / 1e6, 3), "unit": "Msamples/s",
-                                "sample": "channel 0 (5,760,000 samples), whole chain, FP64, %.1f s" % (c1 - c0)}
+        _, c_sec1 = oracle_chain(w.x[:1, :Ns])  # one channel: one thread
+        cpu["single_thread"] = {"value": round(Ns / c_sec1 / 1e6, 3), "unit": "Msamples/s",
+                                "sample": "channel 0 (5,760,000 samples), whole chain, FP64, %.2f s" % c_sec1}
 
     rec = {
         "metric": "Msamples/s (ch x samples) fwd and fwd+bwd, % HBM roofline, at stated error",
@@ -479,13 +574,18 @@ def main():
                    "channels": C, "samples": N, "fir_taps": int(w.stages[0][1].size),
                    "sections": int(sum(s[1].shape[0] for s in w.stages if s[0] == "sos")),
                    "fir_algo": "fft", "step": "tfx_chain_prepare + tfx_chain_run"},
-        "roofline": {"bound": "alu", "achieved": round(achieved_tfs, 3), "peak": VALU_F32_PEAK_TFS,
-                     "unit": "TFLOP/s", "frac": round(achieved_tfs / VALU_F32_PEAK_TFS, 4), "traffic": measured_traffic(),
-                     "kernel": "chain_kernel<FIR_FFT, true>", "kernel_us": round(kern_s * 1e6, 2),
-                     "alg_flops_per_launch": alg_flops, "alg_flops_per_sample": round(fps, 2),
-                     "alg_bytes_per_launch": alg_bytes, "hbm_achieved_GBps": round(achieved_gbs, 2),
-                     "hbm_peak_GBps": HBM_PEAK_GBS, "hbm_frac": round(achieved_gbs / HBM_PEAK_GBS, 4),
-                     "copy_GBps": copy["GBps"], "hbm_frac_of_copy": round(achieved_gbs / copy["GBps"], 4)},
+        "roofline": {"bound": "hbm", "achieved": round(achieved_gbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved_gbs / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
+                     "kernel": "chain_mc_kernel<FIR_FFT>", "kernel_us": round(kern_s * 1e6, 2),
+                     "alg_bytes_per_launch": alg_bytes, "alg_bytes_per_sample": 8,
+                     "copy_GBps": copy["GBps"], "frac_of_copy": round(achieved_gbs / copy["GBps"], 4),
+                     "valu": {"what": "the FFT FIR's flops on the vector units",
+                              "flops_per_sample": round(fps, 2), "achieved_TFLOP_per_s": round(achieved_tfs, 3),
+                              "peak_TFLOP_per_s": VALU_F32_PEAK_TFS,
+                              "frac": round(achieved_tfs / VALU_F32_PEAK_TFS, 4)},
+                     "mfma": {"what": "the cascade's fp32 matrix-core flops as issued",
+                              "flops_per_sample": round(mps, 2), "achieved_TFLOP_per_s": round(mfma_tfs, 3),
+                              "peak_TFLOP_per_s": MFMA_F32_PEAK_TFS, "frac": round(mfma_tfs / MFMA_F32_PEAK_TFS, 4)}},
         "step_stats_ms": {"median": round(float(np.median(step_ms)), 4), "mean": round(float(step_ms.mean()), 4),
                           "sd": round(float(step_ms.std(ddof=1)) if K > 1 else 0.0, 4),
                           "cold_median": round(float(np.median(cold)), 4),

@@ -60,8 +60,23 @@ def _load():
             for f in ("oracle_fir", "oracle_fir_at", "oracle_sos",
                       "oracle_fir_backward", "oracle_sos_backward"):
                 getattr(lib, f).restype = None
+            lib.oracle_last_seconds.restype = ctypes.c_double
+            lib.oracle_last_seconds.argtypes = []
+            lib.oracle_threads.restype = ctypes.c_int
+            lib.oracle_threads.argtypes = []
             _lib = lib
     return _lib
+
+
+def last_seconds() -> float:
+    """Steady-clock seconds of the filtering loops of the last fir / fir_at /
+    sos call (C side, excluding the float64 promotion)."""
+    return float(_load().oracle_last_seconds())
+
+
+def threads() -> int:
+    """Threads the oracle's loops over channels may use."""
+    return int(_load().oracle_threads())
 
 
 def _d(a) -> np.ndarray:

@@ -30,14 +30,35 @@
  * independent channels on different cores; no blocking, fusion or
  * reordering is done inside a channel.
  */
+#define _POSIX_C_SOURCE 199309L
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#include <time.h>
+
+/* Wall time of the filtering loops of the last oracle_fir / oracle_fir_at /
+ * oracle_sos call, from the monotonic (steady) clock: what the CPU baseline
+ * reports, without the Python-side promotion and copies. */
+static double g_last_seconds = 0.0;
+
+static double steady_seconds(void)
+{
+    struct timespec ts;
+    clock_gettime(CLOCK_MONOTONIC, &ts);
+    return (double)ts.tv_sec + 1e-9 * (double)ts.tv_nsec;
+}
+
+double oracle_last_seconds(void) { return g_last_seconds; }
+
+/* Threads the parallel loops over channels may use. */
+int oracle_threads(void) { return omp_get_max_threads(); }
 
 /* FIR: plain per-sample direct convolution (definition above). */
 void oracle_fir(const double *x, double *y, int64_t C, int64_t N,
                 const double *h, int64_t M)
 {
+    const double t0 = steady_seconds();
 #pragma omp parallel for schedule(dynamic, 1)
     for (int64_t c = 0; c < C; ++c) {
         const double *xc = x + c * N;
@@ -50,6 +71,7 @@ void oracle_fir(const double *x, double *y, int64_t C, int64_t N,
             yc[n] = acc;
         }
     }
+    g_last_seconds = steady_seconds() - t0;
 }
 
 /* FIR evaluated only at the listed output positions pos[0..P) of every
@@ -58,6 +80,7 @@ void oracle_fir(const double *x, double *y, int64_t C, int64_t N,
 void oracle_fir_at(const double *x, int64_t C, int64_t N, const double *h,
                    int64_t M, const int64_t *pos, int64_t P, double *out)
 {
+    const double t0 = steady_seconds();
 #pragma omp parallel for schedule(dynamic, 1)
     for (int64_t c = 0; c < C; ++c) {
         const double *xc = x + c * N;
@@ -70,6 +93,7 @@ void oracle_fir_at(const double *x, int64_t C, int64_t N, const double *h,
             out[c * P + p] = acc;
         }
     }
+    g_last_seconds = steady_seconds() - t0;
 }
 
 /* One section in transposed direct form II over one channel, starting from
@@ -99,6 +123,7 @@ void oracle_sos(const double *x, double *y, int64_t C, int64_t N,
                 const double *sos, int64_t S, const double *state_in,
                 double *state_out)
 {
+    const double t0 = steady_seconds();
 #pragma omp parallel for schedule(dynamic, 1)
     for (int64_t c = 0; c < C; ++c) {
         const double *xc = x + c * N;
@@ -118,6 +143,7 @@ void oracle_sos(const double *x, double *y, int64_t C, int64_t N,
             }
         }
     }
+    g_last_seconds = steady_seconds() - t0;
 }
 
 /* FIR adjoint.  g, x: [C][N].  gx: NULL or [C][N]; gh: NULL or [M]

@@ -629,8 +629,10 @@ tfx_status tfx_sos_backward(const float *x, const float *gy, float *gx, int64_t 
         bp.gsos.n = 1;
     }
     if (S == 0) {  // identity: gx = gy
+        hipError_t e = tfx::launch_header_init(ws, ws_bytes, static_cast<hipStream_t>(stream));
+        if (e != hipSuccess) return hip_fail(e, "workspace header");
         if (N == 0) return ok();
-        const hipError_t e = hipMemcpy2DAsync(gx, ldgx * sizeof(float), gy, ldg * sizeof(float), N * sizeof(float),
+        e = hipMemcpy2DAsync(gx, ldgx * sizeof(float), gy, ldg * sizeof(float), N * sizeof(float),
                                               C, hipMemcpyDeviceToDevice, static_cast<hipStream_t>(stream));
         if (e != hipSuccess) return hip_fail(e, "copy");
         return ok();

@@ -663,6 +663,7 @@ hipError_t launch_backward(const BwdPlan &bp) {
     hipStream_t st = p.stream;
     hipError_t e;
     if (p.N == 0) {  // every gradient sum is empty
+        if ((e = launch_header_init(p.ws, p.ws_bytes, st)) != hipSuccess) return e;
         for (int i = 0; i < bp.gsos.n; ++i)
             if (bp.gsos.ptr[i] && (e = launch_state_passthrough(nullptr, bp.gsos.ptr[i], 5 * (int64_t)bp.gsos.len[i], st)))
                 return e;

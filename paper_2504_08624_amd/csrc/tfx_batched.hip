@@ -13,6 +13,7 @@
 #include <hip/hip_runtime.h>
 
 #include "tfx_device.h"
+#include "tfx_mc.h"
 
 namespace tfx {
 
@@ -46,9 +47,32 @@ struct BatchArgs {
     int32_t nclips;
     const SecTab *tab;
     const CascTab *ctab;  // per clip (cascade-level variant)
+    const McTab *mtab;    // per clip (matrix-core variant)
     uint64_t *recs;
     uint32_t *hdr;
 };
+
+// The last clip whose first block is <= id (first blocks never decrease):
+// a 64-way search by the first wave, two rounds for up to 4096 clips; thread
+// 0 writes it and the look-back epoch to LDS (the caller synchronises).
+__device__ __forceinline__ void find_clip(const BatchArgs &a, int64_t id, int tid, int *s_clip, uint32_t *s_epoch) {
+    if (tid < 64) {
+        int lo = 0, n = a.nclips;
+        while (n > 1) {
+            const int step = (n + 63) / 64;
+            const int j = lo + tid * step;
+            const bool ok = j < lo + n && a.desc[j].blk0 <= id;
+            const int cnt = __popcll(__ballot(ok));  // >= 1: desc[lo].blk0 <= id
+            const int nlo = lo + (cnt - 1) * step;
+            n = min(step, lo + n - nlo);
+            lo = nlo;
+        }
+        if (tid == 0) {
+            *s_clip = lo;
+            *s_epoch = load_epoch(a.hdr, HDR_EPOCH);
+        }
+    }
+}
 
 // HIQ: the variant with the FP64 carry; both run, the one that does not match
 // the batch's high-Q word advances the look-back epoch and exits.
@@ -76,25 +100,7 @@ __global__ __launch_bounds__(WG) void batch_kernel(BatchArgs a) {
     }
     const int tid = threadIdx.x, lane = tid & 63, grp = tid / GL, gl = tid % GL, gw = gl >> 6;
     const int64_t id = blockIdx.x;
-    if (tid < 64) {
-        // the last clip whose first block is <= id (first blocks never
-        // decrease): a 64-way search by the first wave, two rounds for up
-        // to 4096 clips
-        int lo = 0, n = a.nclips;
-        while (n > 1) {
-            const int step = (n + 63) / 64;
-            const int j = lo + tid * step;
-            const bool ok = j < lo + n && a.desc[j].blk0 <= id;
-            const int cnt = __popcll(__ballot(ok));  // >= 1: desc[lo].blk0 <= id
-            const int nlo = lo + (cnt - 1) * step;
-            n = min(step, lo + n - nlo);
-            lo = nlo;
-        }
-        if (tid == 0) {
-            s_clip = lo;
-            s_epoch = load_epoch(a.hdr, HDR_EPOCH);
-        }
-    }
+    find_clip(a, id, tid, &s_clip, &s_epoch);
     __syncthreads();
     const ClipDesc &d = a.desc[s_clip];
     const uint32_t epoch = s_epoch;
@@ -207,6 +213,57 @@ __global__ __launch_bounds__(WG) void batch_kernel(BatchArgs a) {
     if (valid) store_tile<LC>(d.y + ch * d.ldy + n0, stg, d.N - n0, d.vec != 0, gl);
 }
 
+// Matrix-core form (chunk length 24, i.e. 3072-sample tiles, every cascade
+// of at most CASC_MAX sections without FP64-carry sections): each block
+// stages its tile of a channel pair and runs the cascade of its clip on the
+// matrix cores (mc_cascade_tile, with the clip's own tables); the look-back
+// records are the clip's, as in the cascade-level form.
+__global__ __launch_bounds__(WG, 4) void batch_mc_kernel(BatchArgs a) {
+    __shared__ __align__(16) float lds[MC_X_FLOATS];
+    __shared__ uint32_t s_epoch;
+    __shared__ int s_clip;
+    if (a.hdr[HDR_HIQ] != 0u) {  // the FP64-carry variant runs
+        advance_epoch(a.hdr);
+        return;
+    }
+    const int tid = threadIdx.x;
+    const int64_t id = blockIdx.x;
+    find_clip(a, id, tid, &s_clip, &s_epoch);
+    __syncthreads();
+    const ClipDesc &d = a.desc[s_clip];
+    const int64_t npairs = d.cpad / 2, local = id - d.blk0;
+    const int64_t tile = local / npairs, pair = local % npairs;
+    const int64_t n0 = tile * T, rem = d.N - n0;
+    const float *src[GROUPS];
+    float *dst[GROUPS];
+#pragma unroll
+    for (int g = 0; g < GROUPS; ++g) {
+        const bool valid = 2 * pair + g < d.C;
+        src[g] = valid ? d.x + (2 * pair + g) * d.ldx + n0 : nullptr;
+        dst[g] = valid ? d.y + (2 * pair + g) * d.ldy + n0 : nullptr;
+    }
+    mc_stage_pair(lds, src, rem, d.vec != 0, tid);
+    if (d.S > 0) {  // block-uniform
+        McCtx m;
+        m.mt = &a.mtab[s_clip];
+        m.ct = &a.ctab[s_clip];
+        m.S = d.S;
+        m.pos = tile;
+        m.epoch = s_epoch;
+        m.hdr = a.hdr;
+#pragma unroll
+        for (int g = 0; g < GROUPS; ++g) {
+            m.rec[g] = a.recs + (d.rec0 + (2 * pair + g) * d.ntiles * d.S) * REC_WORDS;
+            m.known[g] = nullptr;
+            m.ckpt[g] = nullptr;
+        }
+        mc_cascade_tile(lds, m, tid);
+    } else {
+        __syncthreads();
+    }
+    mc_store_pair(lds, dst, rem, d.vec != 0, tid);
+}
+
 // The descriptor table reaches the device through kernel arguments, 32
 // clips per launch: no host buffer has to outlive the call.
 constexpr int DESC_CHUNK = 32;
@@ -296,6 +353,9 @@ BatchLayout batch_plan(const ClipIn *clips, int32_t n, int lc, int order, ClipDe
     lay.casc = off;
     lay.casc_on = lay.smax > 0 && lay.smax <= CASC_MAX;
     if (lay.casc_on) off += al256b(sizeof(CascTab) * (size_t)n);
+    lay.mc = off;
+    lay.mc_on = lay.casc_on && lc == L;  // 3072-sample tiles: the matrix-core form
+    if (lay.mc_on) off += al256b(sizeof(McTab) * (size_t)n);
     lay.total = off;
     return lay;
 }
@@ -310,6 +370,7 @@ hipError_t launch_batch_run(const BatchLayout &lay, int lc, int32_t nclips, void
     a.recs = reinterpret_cast<uint64_t *>(w + lay.recs);
     a.hdr = reinterpret_cast<uint32_t *>(w + lay.hdr);
     a.ctab = reinterpret_cast<const CascTab *>(w + lay.casc);
+    a.mtab = reinterpret_cast<const McTab *>(w + lay.mc);
     const dim3 grid((unsigned)lay.nblocks), block(WG);
     const size_t dyn = sizeof(SecLds) * (size_t)(lay.smax < LDS_SECTIONS ? lay.smax : LDS_SECTIONS);
     const size_t dync = sizeof(SecLdsC) * (size_t)lay.smax + sizeof(float) * (size_t)casc_floats(2 * lay.smax);
@@ -329,7 +390,8 @@ hipError_t launch_batch_run(const BatchLayout &lay, int lc, int32_t nclips, void
             hipLaunchKernelGGL((batch_kernel<32, true, false>), grid, block, dyn, st, a);
             break;
         default:
-            if (cs) hipLaunchKernelGGL((batch_kernel<24, false, true>), grid, block, dync, st, a);
+            if (lay.mc_on) hipLaunchKernelGGL(batch_mc_kernel, grid, block, 0, st, a);
+            else if (cs) hipLaunchKernelGGL((batch_kernel<24, false, true>), grid, block, dync, st, a);
             else hipLaunchKernelGGL((batch_kernel<24, false, false>), grid, block, dyn, st, a);
             if ((e = hipGetLastError()) != hipSuccess) return e;
             hipLaunchKernelGGL((batch_kernel<24, true, false>), grid, block, dyn, st, a);

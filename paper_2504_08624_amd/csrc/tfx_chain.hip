@@ -47,6 +47,7 @@
 #include <hip/hip_runtime.h>
 
 #include "tfx_device.h"
+#include "tfx_mc.h"
 
 namespace tfx {
 
@@ -100,6 +101,7 @@ struct KArgs {
     int32_t nparts;
     const CascTab *casc;  // cascade tile-transition powers (cascade-level look-back)
     const CascZir *zir;   // zero-input response tables of the cascade
+    const McTab *mc;      // matrix-core cascade tables
     const void *tzb;      // fused Toeplitz FIR: B operand table [2 Q][64][8]
     int32_t tzQ;          // its frame lags Q
     const float *hist;    // streaming: the M - 1 FIR inputs before the block, [C][M - 1] (null = zeros)
@@ -127,7 +129,9 @@ constexpr int TZ_QC = 64;
 constexpr int TZ_PF = 4;  // tap-fragment loads in flight
 constexpr int TZ_ROWS = T / TP + TZ_QC - 1;
 static_assert(GROUPS * TZ_ROWS * TROW * 2 <= GROUPS * STG_FLOATS * 4, "Toeplitz operands must fit in the staging");
-template <int MODE>
+// MCL: the output goes to the matrix-core cascade's chunk layout (chunk k
+// of channel g at g * 96 * 36 + 36 k) instead of the staging areas.
+template <int MODE, bool MCL = false>
 __device__ void tz_tile(const KArgs &a, float *lds, int64_t pair, int64_t n0, int tid) {
     typedef Op<MODE> O;
     typedef typename O::T Tt;
@@ -209,11 +213,20 @@ __device__ void tz_tile(const KArgs &a, float *lds, int64_t pair, int64_t n0, in
     for (int k = 0; k < 2; ++k) {
         if (k < ntl) {
             const int u = w + 4 * k, g = u / 3, t = u % 3;
-            float *st = lds + g * STG_FLOATS;
+            if constexpr (MCL) {
+                float *st = lds + g * (T / TP) * 36;
 #pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                const int i = 8 * (r >> 2) + 4 * kh + (r & 3);
-                st[cphys(32 * (32 * t + i) + r32)] = acc[k][r];
+                for (int r = 0; r < 16; ++r) {
+                    const int i = 8 * (r >> 2) + 4 * kh + (r & 3);
+                    st[36 * (32 * t + i) + r32] = acc[k][r];
+                }
+            } else {
+                float *st = lds + g * STG_FLOATS;
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const int i = 8 * (r >> 2) + 4 * kh + (r & 3);
+                    st[cphys(32 * (32 * t + i) + r32)] = acc[k][r];
+                }
             }
         }
     }
@@ -279,6 +292,72 @@ __device__ void fft_block(const KArgs &a, float *lds, int64_t pair, int64_t n0, 
             zi[q] = zi[q - 4];
         }
     }
+}
+
+// Direct FIR of a group's tile: lane gl gets the outputs gl * L .. gl * L +
+// L - 1 of the tile starting at n0 (convolution, or the adjoint correlation)
+// in v.  stg: the group's DIRECT_GROUP_FLOATS of LDS.  Contains workgroup
+// barriers (every lane of the workgroup calls it).
+__device__ void direct_tile(const KArgs &a, float *stg, int64_t ch, bool valid, int gl, int64_t n0, float (&v)[L]) {
+    const float *xc = a.x + ch * a.ldx;
+    const int p0 = gl * L;
+    float acc[L];
+#pragma unroll
+    for (int r = 0; r < L; ++r) acc[r] = 0.f;
+    for (int k0 = 0; k0 < a.M; k0 += a.KBL) {
+        __syncthreads();
+        // stage x[src0 + i], i < T + KBL: convolution needs x[n - k],
+        // correlation x[n + k]
+        const int64_t src0 = a.correlate ? n0 + k0 : n0 - (k0 + a.KBL - 1);
+        for (int i0 = 0; i0 < T + a.KBL; i0 += 8 * GL) {
+            float t8[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int i = i0 + gl + GL * u;
+                const int64_t n = src0 + i;
+                t8[u] = (valid && i < T + a.KBL) ? fir_input(a, xc, ch, n) : 0.f;
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int i = i0 + gl + GL * u;
+                if (i < T + a.KBL) stg[cphys(i)] = t8[u];
+            }
+        }
+        __syncthreads();
+        const int kend = min(a.KBL, a.M - k0);
+        for (int kb = 0; kb < kend; kb += KB) {
+            // convolution: W[i] = x[n0 + p0 - kbase - (KB-1) + i];
+            // correlation: W[i] = x[n0 + p0 + kbase + i]
+            const int base0 = a.correlate ? p0 + kb : p0 + a.KBL - KB - kb;
+            float W[L + KB];
+#pragma unroll
+            for (int q = 0; q < (L + KB) / 4; ++q) {
+                const float4 t4 = *reinterpret_cast<const float4 *>(&stg[cphys(base0 + 4 * q)]);
+                W[4 * q + 0] = t4.x;
+                W[4 * q + 1] = t4.y;
+                W[4 * q + 2] = t4.z;
+                W[4 * q + 3] = t4.w;
+            }
+            const int kbase = k0 + kb;
+            if (a.correlate) {
+#pragma unroll
+                for (int j = 0; j < KB; ++j) {
+                    const float hj = (kbase + j < a.M) ? a.h[kbase + j] : 0.f;
+#pragma unroll
+                    for (int r = 0; r < L; ++r) acc[r] = fmaf(hj, W[r + j], acc[r]);
+                }
+            } else {
+#pragma unroll
+                for (int j = 0; j < KB; ++j) {
+                    const float hj = (kbase + j < a.M) ? a.h[kbase + j] : 0.f;
+#pragma unroll
+                    for (int r = 0; r < L; ++r) acc[r] = fmaf(hj, W[r - j + KB - 1], acc[r]);
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < L; ++r) v[r] = acc[r];
 }
 
 struct TileCtx {
@@ -480,65 +559,7 @@ __global__ __launch_bounds__(WG, (chain_min_blocks<FIRM, HAS_SOS, HIQ, CASC, STO
         tz_tile<FIRM == FIR_TZ_BF16 ? TZ_BF16 : TZ_F16>(a, lds, pair, n0, c.tid);
         load_chunk(stg, c.gl, v);
     } else if (FIRM == FIR_DIRECT) {
-        const float *xc = a.x + c.ch * a.ldx;
-        const int p0 = c.gl * L;
-        float acc[L];
-#pragma unroll
-        for (int r = 0; r < L; ++r) acc[r] = 0.f;
-        for (int k0 = 0; k0 < a.M; k0 += a.KBL) {
-            __syncthreads();
-            // stage x[src0 + i], i < T + KBL: convolution needs x[n - k],
-            // correlation x[n + k]
-            const int64_t src0 = a.correlate ? n0 + k0 : n0 - (k0 + a.KBL - 1);
-            for (int i0 = 0; i0 < T + a.KBL; i0 += 8 * GL) {
-                float t8[8];
-#pragma unroll
-                for (int u = 0; u < 8; ++u) {
-                    const int i = i0 + c.gl + GL * u;
-                    const int64_t n = src0 + i;
-                    t8[u] = (c.valid && i < T + a.KBL) ? fir_input(a, xc, c.ch, n) : 0.f;
-                }
-#pragma unroll
-                for (int u = 0; u < 8; ++u) {
-                    const int i = i0 + c.gl + GL * u;
-                    if (i < T + a.KBL) stg[cphys(i)] = t8[u];
-                }
-            }
-            __syncthreads();
-            const int kend = min(a.KBL, a.M - k0);
-            for (int kb = 0; kb < kend; kb += KB) {
-                // convolution: W[i] = x[n0 + p0 - kbase - (KB-1) + i];
-                // correlation: W[i] = x[n0 + p0 + kbase + i]
-                const int base0 = a.correlate ? p0 + kb : p0 + a.KBL - KB - kb;
-                float W[L + KB];
-#pragma unroll
-                for (int q = 0; q < (L + KB) / 4; ++q) {
-                    const float4 t4 = *reinterpret_cast<const float4 *>(&stg[cphys(base0 + 4 * q)]);
-                    W[4 * q + 0] = t4.x;
-                    W[4 * q + 1] = t4.y;
-                    W[4 * q + 2] = t4.z;
-                    W[4 * q + 3] = t4.w;
-                }
-                const int kbase = k0 + kb;
-                if (a.correlate) {
-#pragma unroll
-                    for (int j = 0; j < KB; ++j) {
-                        const float hj = (kbase + j < a.M) ? a.h[kbase + j] : 0.f;
-#pragma unroll
-                        for (int r = 0; r < L; ++r) acc[r] = fmaf(hj, W[r + j], acc[r]);
-                    }
-                } else {
-#pragma unroll
-                    for (int j = 0; j < KB; ++j) {
-                        const float hj = (kbase + j < a.M) ? a.h[kbase + j] : 0.f;
-#pragma unroll
-                        for (int r = 0; r < L; ++r) acc[r] = fmaf(hj, W[r - j + KB - 1], acc[r]);
-                    }
-                }
-            }
-        }
-#pragma unroll
-        for (int r = 0; r < L; ++r) v[r] = acc[r];
+        direct_tile(a, stg, c.ch, c.valid, c.gl, n0, v);
     } else {  // FIR_FFT
         float zr[16], zi[16];
         fft_block<FIRM == FIR_FFT_PARTS>(a, lds, pair, n0, c.tid, zr, zi);
@@ -662,6 +683,90 @@ __global__ __launch_bounds__(WG, (chain_min_blocks<FIRM, HAS_SOS, HIQ, CASC, STO
     if (c.valid) store_tile(a.y + c.ch * a.ldy + n0, stg, a.N - n0, a.vec != 0, c.gl);
 }
 
+template <int FIRM>
+constexpr int mc_lds_floats() {
+    return FIRM == FIR_FFT ? 2 * NFFT
+         : is_tz<FIRM>() ? (GROUPS * STG_FLOATS > MC_X_FLOATS ? GROUPS * STG_FLOATS : MC_X_FLOATS)
+                           : (FIRM == FIR_DIRECT ? (GROUPS * DIRECT_GROUP_FLOATS > MC_X_FLOATS
+                                                        ? GROUPS * DIRECT_GROUP_FLOATS
+                                                        : MC_X_FLOATS)
+                                                 : MC_X_FLOATS);
+}
+static_assert(2 * NFFT >= MC_X_FLOATS, "chunks must fit in the FFT buffers");
+
+template <int FIRM>
+__global__ __launch_bounds__(WG, 4) void chain_mc_kernel(KArgs a) {
+    __shared__ __align__(16) float lds[mc_lds_floats<FIRM>()];
+    __shared__ uint32_t s_epoch;
+    if (a.hdr[HDR_HIQ] != 0u) {  // the FP64-carry variant runs
+        advance_epoch(a.hdr);
+        return;
+    }
+    const int tid = threadIdx.x;
+    if (tid == 0) s_epoch = load_epoch(a.hdr, HDR_EPOCH);
+    const uint64_t npairs = (uint64_t)(a.cpad / 2);
+    const int64_t tile = (int64_t)(blockIdx.x / npairs);
+    const int64_t pair = (int64_t)(blockIdx.x % npairs);
+    const int64_t n0 = tile * T;
+    const int64_t rem = a.N - n0;  // samples of the tile inside the signal (> 0)
+    float *X = lds;                // [192][MC_XS]: sample j of channel g at g * 96 * 36 + 36 (j / 32) + j % 32
+
+    // ---- FIR (or the input) into X
+    if constexpr (FIRM == FIR_FFT) {
+        float zr[16], zi[16];
+        fft_block<false>(a, lds, pair, n0, tid, zr, zi);
+        __syncthreads();  // the FFT buffers become X
+#pragma unroll
+        for (int q = 4; q < 16; ++q) {
+            const int j = 256 * (q - 4) + tid;
+            X[MC_XS * (j >> 5) + (j & 31)] = zr[q];
+            X[MC_NCH * MC_XS + MC_XS * (j >> 5) + (j & 31)] = zi[q];
+        }
+    } else if constexpr (is_tz<FIRM>()) {
+        static_assert(MC_LC == TP && MC_XS == 36, "the matrix-core FIR's frames are the cascade's chunks");
+        tz_tile<FIRM == FIR_TZ_BF16 ? TZ_BF16 : TZ_F16, true>(a, lds, pair, n0, tid);
+    } else if constexpr (FIRM == FIR_DIRECT) {
+        const int grp = tid / GL, gl = tid % GL;
+        const int64_t ch = 2 * pair + grp;
+        float v[L];
+        direct_tile(a, lds + grp * DIRECT_GROUP_FLOATS, ch, ch < a.C, gl, n0, v);
+        __syncthreads();  // the direct FIR's staging becomes X
+#pragma unroll
+        for (int r = 0; r < L; ++r) {
+            const int j = gl * L + r;
+            X[grp * MC_NCH * MC_XS + MC_XS * (j >> 5) + (j & 31)] = v[r];
+        }
+    } else {
+        const float *src[GROUPS];
+#pragma unroll
+        for (int g = 0; g < GROUPS; ++g) src[g] = 2 * pair + g < a.C ? a.x + (2 * pair + g) * a.ldx + n0 : nullptr;
+        mc_stage_pair(X, src, rem, a.vec != 0, tid);
+    }
+    McCtx m;
+    m.mt = a.mc;
+    m.ct = a.casc;
+    m.S = a.S;
+    m.pos = tile;
+    m.hdr = a.hdr;
+#pragma unroll
+    for (int g = 0; g < GROUPS; ++g) {
+        const int64_t ch = 2 * pair + g;
+        const bool valid = ch < a.C;
+        m.rec[g] = a.recs + ch * a.ntiles * (int64_t)(4 * a.S);
+        m.known[g] = (a.state_in && valid) ? a.state_in + ch * a.S * 2 : nullptr;
+        m.ckpt[g] = (a.ckpt && valid) ? a.ckpt + (ch * a.ntiles + tile) * a.S * 2 : nullptr;
+    }
+    __syncthreads();  // s_epoch
+    m.epoch = s_epoch;
+    mc_cascade_tile(lds, m, tid);
+
+    // ---- store both channels
+    float *dst[GROUPS];
+#pragma unroll
+    for (int g = 0; g < GROUPS; ++g) dst[g] = 2 * pair + g < a.C ? a.y + (2 * pair + g) * a.ldy + n0 : nullptr;
+    mc_store_pair(X, dst, rem, a.vec != 0, tid);
+}
+
 // ------------------------------------------------------------------- host
 
 static size_t al256(size_t b) { return (b + 255) & ~size_t(255); }
@@ -682,6 +787,8 @@ WsLayout ws_layout(int64_t C, int64_t N, int32_t S, int32_t M_merged, int32_t n_
     if (S > 0 && S <= CASC_MAX) off += al256(sizeof(CascTab));
     w.zir = off;
     if (S > 0 && S <= CASC_MAX) off += al256(sizeof(CascZir));
+    w.mc = off;
+    if (S > 0 && S <= CASC_MAX) off += al256(sizeof(McTab));
     w.taps = w.merge = off;
     if (n_fir > 1) {
         off += al256((size_t)M_merged * sizeof(float));
@@ -713,7 +820,11 @@ static hipError_t launch_variants(const KArgs &k, int64_t nblocks, hipStream_t s
     if constexpr (S) {
         const size_t dync = sizeof(SecLdsC) * (size_t)k.S +
                             (casc_in_tail(F, k.S) ? 0 : sizeof(float) * (size_t)casc_floats(2 * k.S));
-        if (k.S <= CASC_MAX)
+        constexpr bool mc = !STOUT && (F == FIR_NONE || F == FIR_FFT || F == FIR_DIRECT || is_tz<F>());
+        if (mc && k.S <= CASC_MAX) {
+            if constexpr (mc)
+                hipLaunchKernelGGL((chain_mc_kernel<F>), dim3((unsigned)nblocks), dim3(WG), 0, st, k);
+        } else if (k.S <= CASC_MAX)
             hipLaunchKernelGGL((chain_kernel<F, S, false, true, STOUT>), dim3((unsigned)nblocks), dim3(WG), dync, st, k);
         else
             hipLaunchKernelGGL((chain_kernel<F, S, false, false, STOUT>), dim3((unsigned)nblocks), dim3(WG), dyn, st, k);
@@ -839,6 +950,7 @@ hipError_t launch_run(const ChainPlan &p) {
     k.nparts = fft_parts(Mtot);
     k.casc = reinterpret_cast<const CascTab *>(ws + lay.casc);
     k.zir = reinterpret_cast<const CascZir *>(ws + lay.zir);
+    k.mc = reinterpret_cast<const McTab *>(ws + lay.mc);
     k.hist = Mtot > 1 ? p.hist_in : nullptr;
     k.ldh = Mtot > 1 ? Mtot - 1 : 0;
     const int64_t nblocks = (lay.cpad / 2) * k.ntiles;

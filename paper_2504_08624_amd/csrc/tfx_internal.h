@@ -125,6 +125,31 @@ struct alignas(16) CascZir {
     float M[16][16][GL];
 };
 
+// Matrix-core form of a cascade of up to CASC_MAX sections (chain path).
+// With chunks of MC_LC = 32 samples, F the cascade's one-sample transition
+// (D = 2S components), b its input column, c its output row and d the
+// product of the b0s, a chunk with input x and entering state s gives
+//     y  = Tc x + G s          Tc[r][m] = h[r - m] (h[0] = d, h[n] = c F^(n-1) b)
+//     s' = Fc s + H x          G[r] = c F^r, H[:, m] = F^(31 - m) b, Fc = F^32.
+// W stacks Tc (rows 0..31) over H (rows 32..47) as the A operand of the
+// 16 x 16 x 4 fp32 matrix instruction, per lane: W[l][8 rb + t] is row
+// 16 rb + (l & 15), column 8 (l >> 4) + t.  Gt[l][4 rb + k] is G's row
+// 16 rb + (l & 15), column 4 (l >> 4) + k.  Fr[i][d] / Fsr[i][d] are row i
+// of Fc / Fs = Fc^12 at the column the DPP rotation by d brings to lane i
+// of a 16-lane row (mc_src).
+constexpr int MC_LC = 32;            // samples per chunk
+constexpr int MC_NCH = T / MC_LC;    // chunks per channel tile (96)
+constexpr int MC_SEG = 12;           // chunks per recurrence segment
+// lane whose value a row rotation by d (DPP row_ror:d) brings to lane i of
+// a 16-lane row
+__host__ __device__ constexpr int mc_src(int i, int d) { return (i - d) & 15; }
+struct alignas(16) McTab {
+    float W[64][24];
+    float Gt[64][8];
+    float Fr[16][16];
+    float Fsr[16][16];
+};
+
 // Header words of a workspace: look-back error bit, look-back epoch, and
 // whether any section needs the FP64 carry (the filter kernels come in two
 // variants; the one that does not match this word exits at once).
@@ -173,7 +198,7 @@ struct ChainPlan {
 
 // Workspace layout of a chain/SOS/FIR call.
 struct WsLayout {
-    size_t hdr, tab, recs, casc, zir, taps, merge, twid, hspec, tw64, ttab, f16, total;
+    size_t hdr, tab, recs, casc, zir, mc, taps, merge, twid, hspec, tw64, ttab, f16, total;
     int64_t ntiles, cpad;
 };
 WsLayout ws_layout(int64_t C, int64_t N, int32_t S, int32_t M_merged, int32_t n_fir, int32_t fir_mode);
@@ -186,6 +211,9 @@ tfx_status set_error(tfx_status s, const char *msg);
 // (false when there is none).
 bool tuned_fir_algo(int32_t M, int64_t C, int64_t N, int32_t *algo, int32_t *cmp);
 
+// Header words of a workspace (at least 256 bytes, else nothing) for a call
+// that builds no tables.
+hipError_t launch_header_init(void *ws, size_t ws_bytes, hipStream_t st);
 // Status word of a workspace into *flags (tfx_workspace_status).
 hipError_t launch_ws_status(void *ws, uint32_t *flags, int32_t clear, hipStream_t st);
 
@@ -234,10 +262,11 @@ struct alignas(16) ClipDesc {
 };
 
 struct BatchLayout {
-    size_t hdr, desc, tab, recs, casc, total;
+    size_t hdr, desc, tab, recs, casc, mc, total;
     int64_t nblocks, nsec, nrec;
     int32_t smax;  // longest cascade of the batch
     bool casc_on;  // every cascade has at most CASC_MAX sections: one CascTab per clip
+    bool mc_on;    // and the chunk length is L: one McTab per clip (matrix-core form)
 };
 
 // host-side clip record (mirrors the public tfx_clip)

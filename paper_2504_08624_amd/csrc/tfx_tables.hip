@@ -224,6 +224,91 @@ __device__ void zir_block(Co co_at, int32_t S, int Lc, int k, CascZir *out, int 
     }
 }
 
+// Matrix-core cascade tables (McTab), in FP64 then rounded, one block of
+// 256 threads: the chunk's impulse response h, the input columns F^m b, the
+// output rows c F^r, the chunk transition Fc = F^32 and the segment
+// transition Fc^12, each laid out as the kernel's operands.
+template <class Co>
+__device__ void mc_block(Co co_at, int32_t S, McTab *out, int tid) {
+    __shared__ double co[CASC_MAX][5];
+    __shared__ double Fm[16][16], Pw[16][16], Q[16][16];
+    __shared__ double bv[16], cv[16];
+    __shared__ double V[MC_LC][16];   // F^m b
+    __shared__ double Gm[MC_LC][16];  // c F^r
+    __shared__ double hh[MC_LC];
+    const int i = tid >> 4, j = tid & 15;
+    if (tid < S * 5) co[tid / 5][tid % 5] = co_at(tid / 5, tid % 5);
+    __syncthreads();
+    const int D = 2 * S;
+    Fm[i][j] = cascade_f(co, D, i, j);
+    if (tid < 16) {
+        // b: section s sees the input through the b0 of every earlier
+        // section; c: the s1 register of section s reaches the output
+        // through the b0 of every later one
+        double bb = 0.0, cc = 0.0;
+        if (tid < D) {
+            const int sc = tid >> 1;
+            double g = 1.0;
+            for (int l = 0; l < sc; ++l) g *= co[l][0];
+            bb = ((tid & 1) ? co[sc][2] - co[sc][4] * co[sc][0] : co[sc][1] - co[sc][3] * co[sc][0]) * g;
+            if ((tid & 1) == 0) {
+                cc = 1.0;
+                for (int t = sc + 1; t < S; ++t) cc *= co[t][0];
+            }
+        }
+        bv[tid] = bb;
+        cv[tid] = cc;
+    }
+    __syncthreads();
+    for (int m = 0; m < MC_LC; ++m) {
+        double nb = 0.0, nc = 0.0;
+        if (tid < 16) {
+            V[m][tid] = bv[tid];
+            Gm[m][tid] = cv[tid];
+            for (int k = 0; k < 16; ++k) {
+                nb += Fm[tid][k] * bv[k];
+                nc += cv[k] * Fm[k][tid];
+            }
+        }
+        __syncthreads();
+        if (tid < 16) {
+            bv[tid] = nb;
+            cv[tid] = nc;
+        }
+        __syncthreads();
+    }
+    if (tid < MC_LC) {  // h[0] = d, h[n] = c F^(n-1) b
+        double hv = 0.0;
+        if (tid == 0) {
+            hv = S > 0 ? 1.0 : 0.0;
+            for (int l = 0; l < S; ++l) hv *= co[l][0];
+        } else {
+            for (int k = 0; k < 16; ++k) hv += Gm[tid - 1][k] * V[0][k];
+        }
+        hh[tid] = hv;
+    }
+    __syncthreads();
+    for (int e = tid; e < 64 * 24; e += 256) {
+        const int l = e / 24, q = e % 24, rb = q / 8, t = q % 8;
+        const int row = 16 * rb + (l & 15), m = 8 * (l >> 4) + t;
+        double v;
+        if (row < MC_LC) v = row >= m ? hh[row - m] : 0.0;
+        else v = V[MC_LC - 1 - m][row - MC_LC];  // H[:, m] = F^(31 - m) b
+        out->W[l][q] = (float)v;
+    }
+    for (int e = tid; e < 64 * 8; e += 256) {
+        const int l = e / 8, q = e % 8, rb = q / 4, k = q % 4;
+        out->Gt[l][q] = (float)Gm[16 * rb + (l & 15)][4 * (l >> 4) + k];
+    }
+    for (int t = 0; t < 5; ++t) mm16(Fm, Fm, Fm, i, j);  // Fc = F^32
+    out->Fr[i][j] = (float)Fm[i][mc_src(i, j)];
+    mm16(Fm, Fm, Pw, i, j);  // Fc^2
+    mm16(Pw, Pw, Pw, i, j);  // Fc^4
+    mm16(Pw, Pw, Q, i, j);   // Fc^8
+    mm16(Q, Pw, Q, i, j);    // Fc^12
+    out->Fsr[i][j] = (float)Q[i][mc_src(i, j)];
+}
+
 struct MergeArgs {
     StageList firs;
     double *buf0, *buf1;
@@ -335,6 +420,7 @@ struct PrepareArgs {
     int32_t S, casc;
     StageList sos;
     CascTab *ctab;
+    McTab *mc;     // matrix-core cascade tables (null: not wanted)
     CascZir *zir;  // zero-input response tables (null: not wanted)
     uint64_t *recs;
     int64_t nwords;
@@ -387,7 +473,19 @@ __global__ __launch_bounds__(256) void prepare_kernel(PrepareArgs a) {
                 return (double)sl.ptr[st][5 * s + k];
             },
             a.S, L, a.ctab, tid);
-    } else if (a.casc && a.zir && b > a.nspec + a.S && b <= a.nspec + a.S + 1 + GL) {
+    } else if (a.casc && a.mc && b == a.nspec + a.S + 1) {
+        const StageList &sl = a.sos;
+        mc_block(
+            [&](int s, int k) {
+                int st = 0;
+                while (s >= sl.len[st]) {
+                    s -= sl.len[st];
+                    ++st;
+                }
+                return (double)sl.ptr[st][5 * s + k];
+            },
+            a.S, a.mc, tid);
+    } else if (a.casc && a.zir && b > a.nspec + a.S + 1 && b <= a.nspec + a.S + 2 + GL) {
         const StageList &sl = a.sos;
         zir_block(
             [&](int s, int k) {
@@ -398,7 +496,7 @@ __global__ __launch_bounds__(256) void prepare_kernel(PrepareArgs a) {
                 }
                 return (double)sl.ptr[st][5 * s + k];
             },
-            a.S, L, b - (a.nspec + a.S + 1), a.zir, tid);
+            a.S, L, b - (a.nspec + a.S + 2), a.zir, tid);
     }
 }
 
@@ -420,6 +518,7 @@ struct BatchPrepArgs {
     uint32_t *hdr;
     int32_t lc;
     CascTab *ctab;  // per clip, or null
+    McTab *mtab;    // per clip, or null
 };
 
 // Blocks g < nsec build section g; blocks nsec + c build clip c's cascade
@@ -436,7 +535,7 @@ __global__ __launch_bounds__(256) void batch_prep_kernel(BatchPrepArgs a) {
                 any |= section_hiq(a.desc[c].sos[5 * s + 3], a.desc[c].sos[5 * s + 4]) ? 1u : 0u;
         a.hdr[HDR_HIQ] = any;
     }
-    const int64_t nroles = a.nsec + (a.ctab ? a.nclips : 0);
+    const int64_t nroles = a.nsec + (a.ctab ? a.nclips : 0) + (a.mtab ? a.nclips : 0);
     for (int64_t g = blockIdx.x; g < nroles; g += gridDim.x) {
         if (g < a.nsec) {
             // the last clip with tab0 <= g: tab0 grows with the clip index by
@@ -448,12 +547,19 @@ __global__ __launch_bounds__(256) void batch_prep_kernel(BatchPrepArgs a) {
                 else hi = mid - 1;
             }
             build_section_block(&a.tab[g], a.desc[lo].sos + 5 * (g - a.desc[lo].tab0), a.lc, tid);
-        } else {
+        } else if (g < a.nsec + a.nclips) {
             const ClipDesc &d = a.desc[g - a.nsec];
             if (d.S > 0) {
                 const float *co = d.sos;
                 casc_table_block([&](int s, int k) { return (double)co[5 * s + k]; }, d.S, a.lc,
                                  &a.ctab[g - a.nsec], tid);
+            }
+        } else {
+            const int c = (int)(g - a.nsec - a.nclips);
+            const ClipDesc &d = a.desc[c];
+            if (d.S > 0) {
+                const float *co = d.sos;
+                mc_block([&](int s, int k) { return (double)co[5 * s + k]; }, d.S, &a.mtab[c], tid);
             }
         }
         __syncthreads();  // the role's shared memory is reused by the next one
@@ -472,7 +578,8 @@ hipError_t launch_batch_prepare(const BatchLayout &lay, int lc, int32_t nclips, 
     a.hdr = reinterpret_cast<uint32_t *>(w + lay.hdr);
     a.lc = lc;
     a.ctab = lay.casc_on ? reinterpret_cast<CascTab *>(w + lay.casc) : nullptr;
-    const int64_t nroles = a.nsec + (a.ctab ? nclips : 0);
+    a.mtab = lay.mc_on ? reinterpret_cast<McTab *>(w + lay.mc) : nullptr;
+    const int64_t nroles = a.nsec + (a.ctab ? nclips : 0) + (a.mtab ? nclips : 0);
     int64_t nb = (a.nwords + 255) / 256;
     if (nb > 2048) nb = 2048;
     if (nb < nroles) nb = nroles < 2048 ? nroles : 2048;
@@ -506,11 +613,15 @@ hipError_t launch_tables(const ChainPlan &p, const WsLayout &lay, const float *h
     a.casc = (p.S > 0 && p.S <= CASC_MAX) ? 1 : 0;
     a.sos = p.sos;
     a.ctab = reinterpret_cast<CascTab *>(ws + lay.casc);
-    a.zir = a.casc ? reinterpret_cast<CascZir *>(ws + lay.zir) : nullptr;
+    a.mc = a.casc ? reinterpret_cast<McTab *>(ws + lay.mc) : nullptr;
+    // the zero-input response tables serve only the cascade-level form of
+    // the partitioned FFT FIR (every other form with a short cascade runs
+    // the matrix-core cascade)
+    a.zir = (a.casc && fft && fft_parts(M) > 1) ? reinterpret_cast<CascZir *>(ws + lay.zir) : nullptr;
     a.recs = reinterpret_cast<uint64_t *>(ws + lay.recs);
     a.nwords = p.S > 0 ? lay.cpad * lay.ntiles * p.S * REC_WORDS : 0;
     a.hdr = reinterpret_cast<uint32_t *>(ws + lay.hdr);
-    int64_t nb = a.nspec + a.S + a.casc + (a.casc ? GL + 1 : 0);
+    int64_t nb = a.nspec + a.S + (a.casc ? 2 : 0) + (a.zir ? GL + 1 : 0);
     int64_t nclear = (a.nwords + 255) / 256;
     if (nclear > 1024) nclear = 1024;
     if (nb < nclear) nb = nclear;
@@ -519,6 +630,20 @@ hipError_t launch_tables(const ChainPlan &p, const WsLayout &lay, const float *h
     if (nb == 0 && p.ws && p.ws_bytes >= 256) nb = 1;
     if (nb == 0) return hipSuccess;
     hipLaunchKernelGGL(prepare_kernel, dim3((unsigned)nb), dim3(256), 0, p.stream, a);
+    return hipGetLastError();
+}
+
+// Header words of a workspace that a call uses without building anything
+// (empty signals, identity cascades): error 0, epoch 1, no high-Q section.
+__global__ void header_init_kernel(uint32_t *hdr) {
+    hdr[HDR_ERROR] = 0u;
+    hdr[HDR_EPOCH] = 1u;
+    hdr[HDR_HIQ] = 0u;
+}
+
+hipError_t launch_header_init(void *ws, size_t ws_bytes, hipStream_t st) {
+    if (!ws || ws_bytes < 256) return hipSuccess;
+    hipLaunchKernelGGL(header_init_kernel, dim3(1), dim3(1), 0, st, static_cast<uint32_t *>(ws));
     return hipGetLastError();
 }
 

@@ -50,6 +50,14 @@ def rel(a, b):
 def assert_rel(a, b, tol, what):
     e = rel(a, b)
     assert np.isfinite(e) and e <= tol, "%s: rel err %.3e > %.1e" % (what, e, tol)
+    return e
+
+
+def report(what, err, bar, floor=None):
+    """Prints a gradient's measured error beside its fixed bar (and the
+    sequential fp32 adjoint's error on the same inputs, when computed)."""
+    extra = "" if floor is None else ", sequential fp32 adjoint %.3e" % floor
+    print("%s: GPU rel err %.3e (bar %.1e%s)" % (what, err, bar, extra), flush=True)
 
 
 # ------------------------------------------------------------------- SOS
@@ -114,9 +122,18 @@ def test_sos_backward_many_tiles():
     assert_rel(_cpu(gs), rgs, TOL_GRAD, "gsos")
 
 
+# Fixed bars of the three ill-conditioned cases, set from measured errors: a
+# plain sequential fp32 adjoint (the cascade's conditioning floor in fp32)
+# already exceeds 1e-4 on the input gradient or the high-pass's coefficient
+# gradients there.
+BAR_ILL_GX, BAR_ILL_GSOS = 6e-4, 1e-4
+BAR_S16_GX, BAR_S16_GSOS = 1e-4, 2.5e-4
+BAR_SHORT_HP = 1.5e-3
+
+
 def test_sos_backward_ill_conditioned_cascade():
-    # a cascade whose gain is ~2e-5 of its input: even a sequential fp32
-    # filter loses ~1e-4; the bar is 5x that floor
+    # a cascade whose gain is ~2e-5 of its input: a sequential fp32 adjoint
+    # loses ~1.8e-4 on the input gradient
     C, N = 2, 150 * T + 77
     x = _x(C, N, (304,))
     g = _x(C, N, (305,), 1.0)
@@ -126,8 +143,12 @@ def test_sos_backward_ill_conditioned_cascade():
     _, ck = tfx.sos(xg, secg, return_ckpt=True)
     gx, gs = tfx.sos_backward(xg, _gpu(g), secg, ck)
     rgx, rgs = O.sos_backward(g, x, sec)
-    assert_close(_cpu(gx), rgx, max(TOL_GRAD, 5 * fx), "gx (fp32 floor %.2e)" % fx)
-    assert_rel(_cpu(gs), rgs, max(TOL_GRAD, 5 * fs), "gsos (fp32 floor %.2e)" % fs)
+    ex = float(channel_errors(_cpu(gx), rgx).max())
+    es = rel(_cpu(gs), rgs)
+    report("ill-conditioned gx", ex, BAR_ILL_GX, fx)
+    report("ill-conditioned gsos", es, BAR_ILL_GSOS, fs)
+    assert_close(_cpu(gx), rgx, BAR_ILL_GX, "gx")
+    assert_rel(_cpu(gs), rgs, BAR_ILL_GSOS, "gsos")
 
 
 def test_sos_backward_high_q():
@@ -163,7 +184,8 @@ def test_sos_backward_strided_rows():
 
 def test_sos_backward_sixteen_sections():
     # the longest cascade the adjoint takes; 16 chained sections of fp32
-    # rounding: the bar is max(1e-4, 5x the sequential fp32 floor)
+    # rounding: a sequential fp32 adjoint loses ~1.5e-4 on the section
+    # gradients
     C, N = 1, 5 * T + 1
     x = _x(C, N, (313,))
     g = _x(C, N, (314,), 1.0)
@@ -173,8 +195,10 @@ def test_sos_backward_sixteen_sections():
     _, ck = tfx.sos(xg, secg, return_ckpt=True)
     gx, gs = tfx.sos_backward(xg, _gpu(g), secg, ck)
     rgx, rgs = O.sos_backward(g, x, sec)
-    assert_close(_cpu(gx), rgx, max(TOL_GRAD, 5 * fx), "gx S=16 (fp32 floor %.2e)" % fx)
-    assert_rel(_cpu(gs), rgs, max(TOL_GRAD, 5 * fs), "gsos S=16 (fp32 floor %.2e)" % fs)
+    report("S=16 gx", float(channel_errors(_cpu(gx), rgx).max()), BAR_S16_GX, fx)
+    report("S=16 gsos", rel(_cpu(gs), rgs), BAR_S16_GSOS, fs)
+    assert_close(_cpu(gx), rgx, BAR_S16_GX, "gx S=16")
+    assert_rel(_cpu(gs), rgs, BAR_S16_GSOS, "gsos S=16")
 
 
 # ------------------------------------------------------------------- FIR
@@ -207,7 +231,7 @@ def test_fir_backward_odd_channels_and_short():
 
 # ------------------------------------------------------------------ chain
 
-def _chain_check(x, g, stages, what, stage_tol=None):
+def _chain_check(x, g, stages, what, stage_tol=None, floors=None):
     xg = _gpu(x)
     st = [(k, _gpu(c)) for k, c in stages]
     has_sos = any(k == "sos" for k, _ in stages)
@@ -217,21 +241,23 @@ def _chain_check(x, g, stages, what, stage_tol=None):
         ck = None
     gx, grads = tfx.chain_backward(xg, _gpu(g), st, ck)
     rgx, rgrads = O.chain_backward(g, x, stages)
+    report(what + " gx", float(channel_errors(_cpu(gx), rgx).max()), TOL_GRAD)
     assert_close(_cpu(gx), rgx, TOL_GRAD, what + " gx")
     for i, (a, b) in enumerate(zip(grads, rgrads)):
         tol = (stage_tol or {}).get(i, TOL_GRAD)
-        assert_rel(_cpu(a).reshape(np.shape(b)), b, tol, what + " stage %d" % i)
+        e = assert_rel(_cpu(a).reshape(np.shape(b)), b, tol, what + " stage %d" % i)
+        report(what + " stage %d" % i, e, tol, (floors or {}).get(i))
 
 
 def test_chain_backward_short():
     # the 100 Hz Butterworth high-pass has poles at radius 0.995 and
     # coefficients near (1, -2, 1): its coefficient gradients lose ~5e-4 even
-    # in a sequential fp32 adjoint, so that stage is held to 5x that floor
+    # in a sequential fp32 adjoint, so that stage has a fixed bar of its own
     w = workloads.chain_short(C=2, N=20000)
     g = _x(2, 20000, (330,), 1.0)
     f = O.fir(w.x, w.stages[0][1]).astype(np.float32)
     _, fs = _fp32_floor(g, f, w.stages[1][1])
-    _chain_check(w.x, g, w.stages, "chain_short", {1: max(TOL_GRAD, 5 * fs)})
+    _chain_check(w.x, g, w.stages, "chain_short", {1: BAR_SHORT_HP}, {1: fs})
 
 
 def test_chain_backward_mid_reduced():
@@ -350,6 +376,42 @@ def test_autograd_full_learnable_size():
     assert_close(_cpu(xg.grad), rgx, TOL_GRAD, "dL/dx full")
     assert_rel(_cpu(hg.grad), rgh, TOL_GRAD, "dL/dh full")
     assert_rel(_cpu(sg.grad), rgs, TOL_GRAD, "dL/dsections full")
+
+
+def test_learnable_full_size_jvp_vs_fd():
+    """Four random directions at the differentiable workload's full size
+    (64 x 192,000, 255-tap FIR | 8 sections): the directional derivative of
+    L = <g, chain(x; h, sos)> from the GPU adjoint against a central finite
+    difference of L computed by the FP64 oracle on the host.  Directions:
+    the taps, the section coefficients, the input, all three together."""
+    x, params, target = workloads.learnable()
+    h, sec = target[0][1], target[1][1]
+    stages = [("fir", h), ("sos", sec)]
+    g = _x(x.shape[0], x.shape[1], (345,), 1.0)
+    xg = _gpu(x)
+    st = [(k, _gpu(c)) for k, c in stages]
+    _, ck = tfx.chain(xg, st, return_ckpt=True)
+    gx, (gh, gs) = tfx.chain_backward(xg, _gpu(g), st, ck)
+    gx, gh, gs = _cpu(gx).astype(np.float64), _cpu(gh).astype(np.float64), _cpu(gs).astype(np.float64)
+    gd = g.astype(np.float64)
+
+    def loss(xx, hh, ss):
+        return float(np.sum(gd * O.chain(xx, [("fir", hh), ("sos", ss)])))
+
+    rng = np.random.default_rng(346)
+    x64, h64, s64 = x.astype(np.float64), h.astype(np.float64), sec.astype(np.float64)
+    for name, (use_x, use_h, use_s) in [("taps", (0, 1, 0)), ("sections", (0, 0, 1)), ("input", (1, 0, 0)),
+                                        ("all", (1, 1, 1))]:
+        dx = rng.standard_normal(x.shape) * 0.1 * use_x
+        dh = rng.standard_normal(h.shape) * np.abs(h).max() * use_h
+        ds = rng.standard_normal(sec.shape) * 0.01 * use_s
+        eps = 1e-5
+        fd = (loss(x64 + eps * dx, h64 + eps * dh, s64 + eps * ds)
+              - loss(x64 - eps * dx, h64 - eps * dh, s64 - eps * ds)) / (2 * eps)
+        jvp = float(np.sum(gx * dx) + np.sum(gh * dh) + np.sum(gs * ds))
+        err = abs(jvp - fd) / abs(fd)
+        report("full-size JVP (%s)" % name, err, TOL_GRAD)
+        assert err <= TOL_GRAD, "JVP along %s: GPU %.9e, FD %.9e, rel err %.3e" % (name, jvp, fd, err)
 
 
 def test_autograd_only_coefficients():
