@@ -195,6 +195,26 @@ tfx_status tfx_chain_run(const float *x, float *y, int64_t C, int64_t N, int64_t
                          const tfx_stage *stages, int32_t nstages, tfx_compute cmp, float *ckpt,
                          void *ws, size_t ws_bytes, void *stream);
 
+/* tfx_chain for callers that cannot allocate device memory (code under
+ * graph capture, tight serving loops, harnesses that forbid allocation): the
+ * same computation and arguments as tfx_chain, with the workspace taken from
+ * a scratch array the library holds on each device (TFX_NOALLOC_SCRATCH_BYTES,
+ * kept until the process ends) instead of a caller-owned one.  The call
+ * allocates nothing, frees nothing and does not synchronise.  A call whose
+ * workspace (tfx_chain_workspace_size) exceeds the array returns
+ * TFX_E_WORKSPACE before anything is enqueued.  Every call on a device
+ * shares that device's array: calls that may overlap in time on one device
+ * (two streams, two host threads) race and give wrong results; calls on one
+ * stream are ordered and safe.  The array keeps the last call's contents;
+ * each call initialises what it reads.
+ *   flags : NULL, or a DEVICE word into which the array's status word is
+ *           ORed after the run (as tfx_workspace_status with clear = 1),
+ *           valid once the stream is synchronised. */
+#define TFX_NOALLOC_SCRATCH_BYTES ((size_t)16 << 20)
+tfx_status tfx_chain_noalloc(const float *x, float *y, int64_t C, int64_t N, int64_t ldx, int64_t ldy,
+                             const tfx_stage *stages, int32_t nstages, tfx_compute cmp, float *ckpt,
+                             uint32_t *flags, void *stream);
+
 /* Streaming (block-by-block) form of tfx_chain (the real-time block
  * processing the paper's Sec. 5 names on its roadmap): y is the chain applied
  * to the block x[C][N] as the continuation of everything filtered before it.

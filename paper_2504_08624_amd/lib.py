@@ -65,6 +65,8 @@ _SIGS = {
     "tfx_sos": (_i32, [_vp, _vp, _i64, _i64, _i64, _i64, _vp, _i32, _vp, _vp, _vp, _vp, _sz, _vp]),
     "tfx_chain": (_i32, [_vp, _vp, _i64, _i64, _i64, _i64, ctypes.POINTER(Stage), _i32, _i32, _vp, _vp, _sz,
                          _vp]),
+    "tfx_chain_noalloc": (_i32, [_vp, _vp, _i64, _i64, _i64, _i64, ctypes.POINTER(Stage), _i32, _i32, _vp, _vp,
+                                 _vp]),
     "tfx_chain_prepare": (_i32, [_i64, _i64, ctypes.POINTER(Stage), _i32, _i32, _vp, _sz, _vp]),
     "tfx_chain_run": (_i32, [_vp, _vp, _i64, _i64, _i64, _i64, ctypes.POINTER(Stage), _i32, _i32, _vp, _vp,
                              _sz, _vp]),
