@@ -354,7 +354,9 @@ BatchLayout batch_plan(const ClipIn *clips, int32_t n, int lc, int order, ClipDe
     lay.casc_on = lay.smax > 0 && lay.smax <= CASC_MAX;
     if (lay.casc_on) off += al256b(sizeof(CascTab) * (size_t)n);
     lay.mc = off;
-    lay.mc_on = lay.casc_on && lc == L;  // 3072-sample tiles: the matrix-core form
+    // 3072-sample tiles and a longest cascade of MC_MIN_SECTIONS or more: the
+    // matrix-core form (whose cost hardly depends on the section count)
+    lay.mc_on = lay.casc_on && lc == L && lay.smax >= MC_MIN_SECTIONS;
     if (lay.mc_on) off += al256b(sizeof(McTab) * (size_t)n);
     lay.total = off;
     return lay;

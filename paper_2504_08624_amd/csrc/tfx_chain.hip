@@ -470,25 +470,34 @@ __device__ void run_section(const KArgs &a, const TB &tb, int s, float (&v)[L], 
 // the tile.  By linearity the output at sample r of chunk k gains
 // G[r] . (F^(L k) P): the entering state carried k chunks into the tile,
 // then through the cascade to its output, with no further pass per section.
+// With k = 16 a + b (a = the lane's 16-lane row), F^(L k) P = F^(L b) R_a,
+// R_a = F^(16 L a) P: lane (a, i) forms component i of R_a, each lane takes
+// the row's components by lane shuffles.  F is block lower triangular, and
+// so are its powers.
 template <int D>
 __device__ __forceinline__ void casc_zir_add(float (&v)[L], const CascZir *zt, const float *P, int k) {
-    float p[D];
+    const int a = k >> 4, b = k & 15, ri = k & 15;
+    float ra = 0.f;  // component ri of R_a
+    if (ri < D) {
 #pragma unroll
-    for (int j = 0; j < D; ++j) p[j] = P[j];
+        for (int j = 0; j < D; ++j) ra = fmaf(zt->Ma[a][ri][j], P[j], ra);
+    }
+    const int row0 = (__lane_id() & ~15);
+    float r[D];
+#pragma unroll
+    for (int j = 0; j < D; ++j) r[j] = __shfl(ra, row0 + j);
 #pragma unroll
     for (int i = 0; i < D; ++i) {
-        float zi = 0.f;  // component i of F^(L k) P; F is block lower triangular, and so are its powers
+        float zi = 0.f;  // component i of F^(L b) R_a
 #pragma unroll
-        for (int j = 0; j < (i | 1) + 1; ++j) zi = fmaf(zt->M[i][j][k], p[j], zi);
+        for (int j = 0; j < (i | 1) + 1; ++j) zi = fmaf(zt->Mb[i][j][b], r[j], zi);
 #pragma unroll
-        for (int r = 0; r < L; ++r) v[r] = fmaf(zt->G[r][i], zi, v[r]);
+        for (int q = 0; q < L; ++q) v[q] = fmaf(zt->G[q][i], zi, v[q]);
     }
 }
 
 // Cascades up to ZIR_MAX sections (larger ones would cost the kernel
 // registers, hence occupancy) use the zero-input response tables.
-constexpr int ZIR_MAX = 6;
-
 __device__ __forceinline__ void casc_zir(float (&v)[L], const CascZir *zt, const float *P, int k, int S) {
     switch (S) {
     case 1: casc_zir_add<2>(v, zt, P, k); break;
@@ -821,7 +830,7 @@ static hipError_t launch_variants(const KArgs &k, int64_t nblocks, hipStream_t s
         const size_t dync = sizeof(SecLdsC) * (size_t)k.S +
                             (casc_in_tail(F, k.S) ? 0 : sizeof(float) * (size_t)casc_floats(2 * k.S));
         constexpr bool mc = !STOUT && (F == FIR_NONE || F == FIR_FFT || F == FIR_DIRECT || is_tz<F>());
-        if (mc && k.S <= CASC_MAX) {
+        if (mc && k.S >= MC_MIN_SECTIONS && k.S <= CASC_MAX) {
             if constexpr (mc)
                 hipLaunchKernelGGL((chain_mc_kernel<F>), dim3((unsigned)nblocks), dim3(WG), 0, st, k);
         } else if (k.S <= CASC_MAX)

@@ -116,13 +116,17 @@ struct alignas(16) CascTab {
 };
 // Zero-input response of a cascade (chain path): with F the per-sample
 // transition of the cascade state (D = 2S components) and c the row that
-// maps the state to the cascade output under zero input, G[r] = c F^r and
-// M[i][j][k] = (F^(L k))[i][j].  The output of a tile is its zero-entering-
-// state response plus G[r] . (F^(L k) P) at sample r of chunk k, P being the
-// state entering the tile.
+// maps the state to the cascade output under zero input, G[r] = c F^r.  The
+// output of a tile is its zero-entering-state response plus
+// G[r] . (F^(L k) P) at sample r of chunk k, P being the state entering the
+// tile.  With k = 16 a + b, F^(L k) = F^(L b) F^(16 L a): Mb[i][j][b] =
+// (F^(L b))[i][j] (b < 16, lane-contiguous) and Ma[a][i][j] = (F^(16 L a))[i][j]
+// (a < 8), 40 KB in all, so the per-lane reads stay in the first-level cache.
+constexpr int ZIR_B = 16, ZIR_A = GL / ZIR_B;
 struct alignas(16) CascZir {
     float G[L][16];
-    float M[16][16][GL];
+    float Mb[16][16][ZIR_B];
+    float Ma[ZIR_A][16][16];
 };
 
 // Matrix-core form of a cascade of up to CASC_MAX sections (chain path).
@@ -137,6 +141,13 @@ struct alignas(16) CascZir {
 // 16 rb + (l & 15), column 4 (l >> 4) + k.  Fr[i][d] / Fsr[i][d] are row i
 // of Fc / Fs = Fc^12 at the column the DPP rotation by d brings to lane i
 // of a 16-lane row (mc_src).
+// The matrix-core form runs cascades of MC_MIN_SECTIONS .. CASC_MAX sections:
+// its cost hardly depends on the section count, while the cascade-level form
+// with zero-input-response tables (up to ZIR_MAX sections) is faster for
+// short cascades (measured on 8 x 5.76 M: equal at 6 sections, 17-25 %
+// slower at 8).
+constexpr int ZIR_MAX = 6;
+constexpr int MC_MIN_SECTIONS = ZIR_MAX + 1;
 constexpr int MC_LC = 32;            // samples per chunk
 constexpr int MC_NCH = T / MC_LC;    // chunks per channel tile (96)
 constexpr int MC_SEG = 12;           // chunks per recurrence segment
@@ -266,7 +277,7 @@ struct BatchLayout {
     int64_t nblocks, nsec, nrec;
     int32_t smax;  // longest cascade of the batch
     bool casc_on;  // every cascade has at most CASC_MAX sections: one CascTab per clip
-    bool mc_on;    // and the chunk length is L: one McTab per clip (matrix-core form)
+    bool mc_on;    // and the chunk length is L and smax >= MC_MIN_SECTIONS: one McTab per clip (matrix-core form)
 };
 
 // host-side clip record (mirrors the public tfx_clip)

@@ -179,7 +179,8 @@ __device__ void casc_table_block(Co co_at, int32_t S, int Lc, CascTab *out, int 
 
 // Zero-input response tables of the cascade (CascZir), in FP64 then
 // rounded, one block of 256 threads (one matrix element each) per entry:
-// k < GL gives F^(Lc k) by binary powering; k == GL gives the output rows
+// k < ZIR_B gives F^(Lc k), ZIR_B <= k < ZIR_B + ZIR_A gives F^(16 Lc a),
+// a = k - ZIR_B, by binary powering; k == ZIR_B + ZIR_A gives the output rows
 // G[r] = c F^r, r < Lc, where c[2s] = prod_{t>s} b0_t (the s1 register of
 // section s reaches the output through the b0 of every later section) and
 // c[2s+1] = 0.
@@ -195,12 +196,14 @@ __device__ void zir_block(Co co_at, int32_t S, int Lc, int k, CascZir *out, int 
     Fm[i][j] = cascade_f(co, D, i, j);
     P[i][j] = i == j ? 1.0 : 0.0;
     __syncthreads();
-    if (k < GL) {
-        for (int e = Lc * k; e > 0; e >>= 1) {
+    if (k < ZIR_B + ZIR_A) {
+        const int e0 = k < ZIR_B ? Lc * k : ZIR_B * Lc * (k - ZIR_B);
+        for (int e = e0; e > 0; e >>= 1) {
             if (e & 1) mm16(P, Fm, P, i, j);
             if (e > 1) mm16(Fm, Fm, Fm, i, j);
         }
-        out->M[i][j][k] = (float)P[i][j];
+        if (k < ZIR_B) out->Mb[i][j][k] = (float)P[i][j];
+        else out->Ma[k - ZIR_B][i][j] = (float)P[i][j];
         return;
     }
     if (tid < 16) {
@@ -231,8 +234,7 @@ __device__ void zir_block(Co co_at, int32_t S, int Lc, int k, CascZir *out, int 
 template <class Co>
 __device__ void mc_block(Co co_at, int32_t S, McTab *out, int tid) {
     __shared__ double co[CASC_MAX][5];
-    __shared__ double Fm[16][16], Pw[16][16], Q[16][16];
-    __shared__ double bv[16], cv[16];
+    __shared__ double Pw[16][16], Q[16][16];
     __shared__ double V[MC_LC][16];   // F^m b
     __shared__ double Gm[MC_LC][16];  // c F^r
     __shared__ double hh[MC_LC];
@@ -240,7 +242,7 @@ __device__ void mc_block(Co co_at, int32_t S, McTab *out, int tid) {
     if (tid < S * 5) co[tid / 5][tid % 5] = co_at(tid / 5, tid % 5);
     __syncthreads();
     const int D = 2 * S;
-    Fm[i][j] = cascade_f(co, D, i, j);
+    Pw[i][j] = cascade_f(co, D, i, j);
     if (tid < 16) {
         // b: section s sees the input through the b0 of every earlier
         // section; c: the s1 register of section s reaches the output
@@ -256,26 +258,28 @@ __device__ void mc_block(Co co_at, int32_t S, McTab *out, int tid) {
                 for (int t = sc + 1; t < S; ++t) cc *= co[t][0];
             }
         }
-        bv[tid] = bb;
-        cv[tid] = cc;
+        V[0][tid] = bb;
+        Gm[0][tid] = cc;
     }
     __syncthreads();
-    for (int m = 0; m < MC_LC; ++m) {
-        double nb = 0.0, nc = 0.0;
-        if (tid < 16) {
-            V[m][tid] = bv[tid];
-            Gm[m][tid] = cv[tid];
+    // doubling: with Pw = F^(2^l), V[2^l + v] = Pw V[v] and
+    // Gm[2^l + v] = Gm[v] Pw for v < 2^l (thread (i, j): component i of
+    // vector j), then Pw <- Pw^2; five levels give 32 vectors and Pw = F^32
+    for (int l = 0; l < 5; ++l) {
+        const int n = 1 << l;
+        double vv = 0.0, gg = 0.0;
+        if (j < n) {
             for (int k = 0; k < 16; ++k) {
-                nb += Fm[tid][k] * bv[k];
-                nc += cv[k] * Fm[k][tid];
+                vv += Pw[i][k] * V[j][k];
+                gg += Gm[j][k] * Pw[k][i];
             }
         }
         __syncthreads();
-        if (tid < 16) {
-            bv[tid] = nb;
-            cv[tid] = nc;
+        if (j < n) {
+            V[n + j][i] = vv;
+            Gm[n + j][i] = gg;
         }
-        __syncthreads();
+        mm16(Pw, Pw, Pw, i, j);
     }
     if (tid < MC_LC) {  // h[0] = d, h[n] = c F^(n-1) b
         double hv = 0.0;
@@ -300,12 +304,11 @@ __device__ void mc_block(Co co_at, int32_t S, McTab *out, int tid) {
         const int l = e / 8, q = e % 8, rb = q / 4, k = q % 4;
         out->Gt[l][q] = (float)Gm[16 * rb + (l & 15)][4 * (l >> 4) + k];
     }
-    for (int t = 0; t < 5; ++t) mm16(Fm, Fm, Fm, i, j);  // Fc = F^32
-    out->Fr[i][j] = (float)Fm[i][mc_src(i, j)];
-    mm16(Fm, Fm, Pw, i, j);  // Fc^2
-    mm16(Pw, Pw, Pw, i, j);  // Fc^4
-    mm16(Pw, Pw, Q, i, j);   // Fc^8
-    mm16(Q, Pw, Q, i, j);    // Fc^12
+    out->Fr[i][j] = (float)Pw[i][mc_src(i, j)];  // Fc = F^32
+    mm16(Pw, Pw, Q, i, j);  // Fc^2
+    mm16(Q, Q, Q, i, j);    // Fc^4
+    mm16(Q, Q, Pw, i, j);   // Fc^8
+    mm16(Pw, Q, Q, i, j);   // Fc^12
     out->Fsr[i][j] = (float)Q[i][mc_src(i, j)];
 }
 
@@ -485,7 +488,7 @@ __global__ __launch_bounds__(256) void prepare_kernel(PrepareArgs a) {
                 return (double)sl.ptr[st][5 * s + k];
             },
             a.S, a.mc, tid);
-    } else if (a.casc && a.zir && b > a.nspec + a.S + 1 && b <= a.nspec + a.S + 2 + GL) {
+    } else if (a.casc && a.zir && b > a.nspec + a.S + 1 && b <= a.nspec + a.S + 2 + ZIR_B + ZIR_A) {
         const StageList &sl = a.sos;
         zir_block(
             [&](int s, int k) {
@@ -613,15 +616,14 @@ hipError_t launch_tables(const ChainPlan &p, const WsLayout &lay, const float *h
     a.casc = (p.S > 0 && p.S <= CASC_MAX) ? 1 : 0;
     a.sos = p.sos;
     a.ctab = reinterpret_cast<CascTab *>(ws + lay.casc);
-    a.mc = a.casc ? reinterpret_cast<McTab *>(ws + lay.mc) : nullptr;
-    // the zero-input response tables serve only the cascade-level form of
-    // the partitioned FFT FIR (every other form with a short cascade runs
-    // the matrix-core cascade)
-    a.zir = (a.casc && fft && fft_parts(M) > 1) ? reinterpret_cast<CascZir *>(ws + lay.zir) : nullptr;
+    // cascades of up to ZIR_MAX sections take the zero-input response
+    // tables, longer ones (up to CASC_MAX) the matrix-core form
+    a.mc = (a.casc && p.S >= MC_MIN_SECTIONS) ? reinterpret_cast<McTab *>(ws + lay.mc) : nullptr;
+    a.zir = (a.casc && p.S <= ZIR_MAX) ? reinterpret_cast<CascZir *>(ws + lay.zir) : nullptr;
     a.recs = reinterpret_cast<uint64_t *>(ws + lay.recs);
     a.nwords = p.S > 0 ? lay.cpad * lay.ntiles * p.S * REC_WORDS : 0;
     a.hdr = reinterpret_cast<uint32_t *>(ws + lay.hdr);
-    int64_t nb = a.nspec + a.S + (a.casc ? 2 : 0) + (a.zir ? GL + 1 : 0);
+    int64_t nb = a.nspec + a.S + (a.casc ? 2 : 0) + (a.zir ? ZIR_B + ZIR_A + 1 : 0);
     int64_t nclear = (a.nwords + 255) / 256;
     if (nclear > 1024) nclear = 1024;
     if (nb < nclear) nb = nclear;

@@ -123,3 +123,38 @@ def test_batched_argument_validation():
     x = _gpu(np.zeros((1, 10), np.float32))
     with pytest.raises(lib.TfxError, match="INVALID_ARG"):
         tfx.sos_batched([x], [_gpu(np.zeros((1, 5), np.float32))], {"chunk": 20})
+
+
+@pytest.mark.parametrize("chunk", [16, 24])
+def test_batched_long_cascades(chunk):
+    """Clips with seven and eight sections (the longest cascade of the batch
+    decides the form: at 24-sample chunks the matrix-core cascade) beside
+    short ones, lengths across tile edges."""
+    # peaking sections across the band: long cascades of unit-circle-zero
+    # resonators have gains far below fp32 resolution (no fp32 method meets
+    # 1e-4 there), peaking cascades stay well conditioned
+    clips = []
+    for i, (C, N, S) in enumerate([(3, 3 * 3072 + 5, 8), (1, 3072, 7), (2, 20_000, 2), (5, 777, 8), (2, 9000, 0)]):
+        g = signals.rng(507, i)
+        sec = (np.concatenate([design.peaking(f, q, gd, 44100.0) for f, q, gd in
+                               zip(np.geomspace(200.0, 15000.0, S), g.uniform(0.7, 6.0, S), g.uniform(-9.0, 9.0, S))])
+               if S else np.zeros((0, 5))).astype(np.float32).reshape(S, 5)
+        x = signals.to_f32(np.stack([signals.white(N, (508, i, c)) for c in range(C)]).reshape(C, N))
+        clips.append((x, sec))
+    ys = tfx.sos_batched([_gpu(x) for x, _ in clips], [_gpu(s) for _, s in clips], {"chunk": chunk, "order": 1})
+    _check(clips, ys, "long cascades chunk=%d" % chunk)
+
+
+def test_batched_cascade_level_without_high_q():
+    """Cascades of up to six sections and no high-Q section at 24-sample
+    chunks (the cascade-level form: one look-back of the whole cascade
+    state per tile); lengths across tile edges, odd channel counts."""
+    clips = []
+    for i, (C, N, S) in enumerate([(3, 3 * 3072 + 5, 6), (1, 3072, 1), (2, 20_000, 4), (5, 777, 3), (1, 9000, 0),
+                                   (2, 40_000, 5)]):
+        sec = design.random_sections(signals.rng(509, i), S, 0.5, 0.995).astype(np.float32).reshape(S, 5)
+        x = signals.to_f32(np.stack([signals.white(N, (510, i, c)) for c in range(C)]).reshape(C, N))
+        clips.append((x, sec))
+    for order in (0, 1):
+        ys = tfx.sos_batched([_gpu(x) for x, _ in clips], [_gpu(s) for _, s in clips], {"chunk": 24, "order": order})
+        _check(clips, ys, "cascade-level order=%d" % order)

@@ -12,7 +12,7 @@ import torch
 import paper_2504_08624_amd as tfx
 from paper_2504_08624_amd import design, lib, signals, workloads
 from oracle import oracle as O
-from tests.metrics import TOL_FIR_F32, TOL_IIR_F32, assert_close
+from tests.metrics import TOL_FIR_LOWP, TOL_FIR_F32, TOL_IIR_F32, assert_close
 
 pytestmark = pytest.mark.gpu
 
@@ -366,7 +366,7 @@ def test_chain_run_replays_on_prepared_workspace():
 def test_chain_fft_every_cascade_length(S):
     """FFT FIR then S sections: up to six sections the cascade's second phase
     is the zero-input-response table form, seven and eight take the
-    per-section form; both against the oracle, over several tiles and a
+    matrix-core form; both against the oracle, over several tiles and a
     ragged tail, with poles up to radius 0.994."""
     x = _x(3, 4 * T + 17, (90, S))
     h = design.fir_lowpass(255, 5000.0, 48000.0).astype(np.float32)
@@ -390,3 +390,42 @@ def test_sos_state_in_through_the_table_form(S):
     st = signals.rng(94, S).standard_normal((2, S, 2)).astype(np.float32)
     y = _cpu(tfx.sos(_gpu(x), _gpu(sec), state_in=_gpu(st)))
     assert_close(y, O.sos(x, sec, state_in=st), TOL_IIR_F32, "state_in, %d sections" % S)
+
+
+@pytest.mark.parametrize("S", [7, 8])
+@pytest.mark.parametrize("fir", ["none", "direct", "fft", "bf16"])
+def test_chain_matrix_core_cascade_every_fir_form(S, fir):
+    """Cascades of seven and eight sections run on the matrix cores behind
+    every FIR form: odd channel count (a half-empty channel pair), several
+    tiles and a ragged tail, a state entering the first tile, and the tile
+    checkpoints, against the oracle."""
+    C, N = 3, 5 * T + 1234
+    x = _x(C, N, (140, S))
+    g = signals.rng(141, S)
+    sec = np.concatenate([design.peaking(f, q, gd, 48000.0) for f, q, gd in
+                          zip(np.geomspace(200.0, 15000.0, S), g.uniform(0.7, 6.0, S), g.uniform(-9.0, 9.0, S))])
+    sec = sec.astype(np.float32)
+    si = (0.01 * signals.rng(142, S).standard_normal((C, S, 2))).astype(np.float32)
+    stages, tol, kw = [], TOL_IIR_F32, {}
+    if fir == "direct":
+        stages = [("fir", design.fir_lowpass(17, 9000.0, 48000.0).astype(np.float32))]
+    elif fir == "fft":
+        stages = [("fir", design.fir_lowpass(255, 5000.0, 48000.0).astype(np.float32))]
+    elif fir == "bf16":
+        stages = [("fir", design.fir_lowpass(33, 9000.0, 48000.0).astype(np.float32))]
+        tol, kw = TOL_FIR_LOWP, {"compute": "bf16"}
+    xg = _gpu(x)
+    st = [(k, _gpu(c)) for k, c in stages] + [("sos", _gpu(sec))]
+    y, ck = tfx.chain(xg, st, return_ckpt=True, **kw)
+    ref = O.chain(x, stages + [("sos", sec)])
+    assert_close(_cpu(y), ref, tol, "%s FIR + %d sections" % (fir, S))
+    # checkpoints: the state entering every section at every tile start
+    f = O.chain(x, stages) if stages else x.astype(np.float64)
+    ckc = _cpu(ck)
+    for t in (1, 3, 5):
+        _, s_ref = O.sos(f[:, :t * T], sec, return_state=True)
+        assert_close(ckc[:, t].reshape(C, -1), s_ref.reshape(C, -1), 10 * tol, "checkpoint tile %d" % t)
+    if fir == "none":
+        # a state entering the first tile
+        y2 = _cpu(tfx.sos(xg, _gpu(sec), state_in=_gpu(si)))
+        assert_close(y2, O.sos(x, sec, state_in=si), TOL_IIR_F32, "state_in, %d sections" % S)

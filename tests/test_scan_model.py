@@ -242,3 +242,92 @@ def test_cascade_zero_input_response_form_equals_oracle():
         y[t * T:(t + 1) * T] = yA[0] + corr
         P = FT @ P + E.reshape(-1)
     np.testing.assert_allclose(y, O.sos(x[None, :], sec)[0], rtol=1e-9, atol=1e-11)
+
+
+# ------------------------------------------------ matrix-core cascade form
+
+def _cascade_io(sec):
+    """Input column b and output row c of the cascade's state space (same
+    state order as _cascade_transition), and its feed-through d: the output is
+    c s + d x and the next state F s + b x."""
+    S = len(sec)
+    b = np.zeros(2 * S)
+    c = np.zeros(2 * S)
+    for i, (b0, b1, b2, a1, a2) in enumerate(sec):
+        gin = np.prod([sec[l][0] for l in range(i)]) if i else 1.0
+        b[2 * i:2 * i + 2] = np.array([b1 - a1 * b0, b2 - a2 * b0]) * gin
+        c[2 * i] = np.prod([sec[l][0] for l in range(i + 1, S)]) if i + 1 < S else 1.0
+    return b, c, float(np.prod([r[0] for r in sec]))
+
+
+def model_matrix_cascade(x, sec, LC=32, NCH=96, SEG=12, state_in=None):
+    """The matrix-core decomposition over one channel, in FP64: chunks of LC
+    samples (y0 = Tc x, u = H x), chunk states in segments of SEG chunks from a
+    zero state, the tile aggregate from the segment aggregates, the tile
+    entering state P_{t+1} = Phi_T P_t + E_t, the segments' entering states,
+    the chunks' entering states S, then y = y0 + G S."""
+    F = _cascade_transition(sec)
+    b, c, d = _cascade_io(sec)
+    D = F.shape[0]
+    h = np.zeros(LC)
+    h[0] = d
+    for n in range(1, LC):
+        h[n] = c @ np.linalg.matrix_power(F, n - 1) @ b
+    Tc = np.array([[h[r - m] if r >= m else 0.0 for m in range(LC)] for r in range(LC)])
+    H = np.stack([np.linalg.matrix_power(F, LC - 1 - m) @ b for m in range(LC)], axis=1)
+    G = np.stack([c @ np.linalg.matrix_power(F, r) for r in range(LC)])
+    Fc = np.linalg.matrix_power(F, LC)
+    Fs = np.linalg.matrix_power(Fc, SEG)
+    PhiT = np.linalg.matrix_power(Fc, NCH)
+    T = LC * NCH
+    N = x.size
+    nt = -(-N // T)
+    xp = np.concatenate([x, np.zeros(nt * T - N)])
+    y = np.empty_like(xp)
+    P = np.zeros(D) if state_in is None else np.asarray(state_in, float).reshape(-1)
+    for t in range(nt):
+        X = xp[t * T:(t + 1) * T].reshape(NCH, LC).T
+        Y0, U = Tc @ X, H @ X
+        nseg = NCH // SEG
+        g = np.zeros((nseg, D))
+        for j in range(nseg):
+            s = np.zeros(D)
+            for m in range(SEG):
+                s = Fc @ s + U[:, j * SEG + m]
+            g[j] = s
+        E = np.zeros(D)
+        for j in range(nseg):
+            E = Fs @ E + g[j]
+        e = P.copy()
+        Sx = np.zeros((D, NCH))
+        for j in range(nseg):
+            s = e.copy()
+            for m in range(SEG):
+                Sx[:, j * SEG + m] = s
+                s = Fc @ s + U[:, j * SEG + m]
+            e = Fs @ e + g[j]
+        y[t * T:(t + 1) * T] = (Y0 + G @ Sx).T.reshape(-1)
+        P = PhiT @ P + E
+    return y[:N]
+
+
+@pytest.mark.parametrize("S,N", [(1, 5000), (2, 3072), (4, 3 * 3072 + 77), (6, 2 * 3072 + 1), (8, 4000)])
+def test_matrix_cascade_model_matches_oracle(S, N):
+    from paper_2504_08624_amd import design, signals
+    sec = design.random_sections(signals.rng(75, S), S, 0.5, 0.995)
+    x = signals.rng(76, S).standard_normal(N)
+    si = signals.rng(77, S).standard_normal((S, 2))
+    y = model_matrix_cascade(x, sec, state_in=si)
+    ref = O.sos(x[None], sec, state_in=si[None])[0]
+    assert np.max(np.abs(y - ref)) < 1e-9 * max(1.0, np.max(np.abs(ref)))
+
+
+def test_matrix_cascade_model_small_chunks():
+    # the algebra does not depend on the sizes: chunks of 4, segments of 3,
+    # 6 chunks a tile, many tiles
+    from paper_2504_08624_amd import design, signals
+    sec = design.random_sections(signals.rng(78), 3, 0.5, 0.99)
+    x = signals.rng(79).standard_normal(24 * 9 + 5)
+    y = model_matrix_cascade(x, sec, LC=4, NCH=6, SEG=3)
+    ref = O.sos(x[None], sec)[0]
+    assert np.max(np.abs(y - ref)) < 1e-10 * max(1.0, np.max(np.abs(ref)))
