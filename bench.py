@@ -23,12 +23,14 @@ the chain for a fixed upstream gradient: gradients of input, taps and
 sections).
 
 Unless --quick, the other workloads are measured once each (context, in
-"secondary"): the short chain, the 8191-tap FIR by FFT (fp32) and by the
-matrix-core Toeplitz product (bf16, fp16, split bf16), the ragged batch of
-256 clips (autotuned single launch, against one tfx_sos call per clip), the
-differentiable workload's forward + backward, the Wave pipe, streaming
-blocks, and the STFT / inverse STFT of the headline signal.  Low-precision errors are
-measured against the oracle on sampled outputs.
+"secondary"): the short chain (also at the headline's size), the 8191-tap
+FIR by FFT (fp32) and by the matrix-core Toeplitz product (bf16, fp16, split
+bf16), the headline's 1023-tap FIR alone in every form, the ragged batch of
+256 clips (autotuned, one hipGraph replay, against one tfx_sos call per
+clip), the differentiable workload's forward and forward + backward, the
+Wave pipe, streaming blocks, and the STFT / inverse STFT of the headline
+signal.  Errors are measured against the oracle on sampled outputs.
+`--leg NAME` runs one of these alone (for kernel profiles).
 
 The CPU baseline runs the FP64 oracle (test infrastructure: plain C, one
 OpenMP thread per channel) on a bounded sample of the headline input and
@@ -100,6 +102,8 @@ def parse():
     ap.add_argument("--quick", action="store_true", help="headline workload only")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--stft-only", action="store_true", help="only the STFT leg (for kernel profiles)")
+    ap.add_argument("--leg", action="append", choices=LEGS,
+                    help="run only this context leg (repeatable; for kernel profiles); no headline")
     ap.add_argument("--copy-probe", action="store_true",
                     help="accepted for older profile commands; the device copy of the input is always timed")
     return ap.parse_args()
@@ -126,207 +130,253 @@ def timed(torch, fn, reps, stream):
     return (time.perf_counter() - t0) / reps
 
 
-def secondary(torch, dev, stream):
+LEGS = ("chain_short", "fir_long", "fir_mid_forms", "ragged", "chain_short_large", "learnable", "wave_pipe",
+        "chain_mid_compute", "stream", "stft")
+
+
+def secondary(torch, dev, stream, only=None):
+    """The context legs; `only`: a set of leg names (None = all)."""
     import paper_2504_08624_amd as tfx
     from oracle import oracle as O
     from paper_2504_08624_amd import workloads
     out = {}
 
-    log("chain_short")
-    w = workloads.chain_short()
-    x = torch.from_numpy(w.x).to(dev)
-    st = [(k, torch.from_numpy(c).to(dev)) for k, c in w.stages]
-    s = timed(torch, lambda: tfx.chain(x, st), 20, stream)
-    y = tfx.chain(x, st).cpu().numpy()
-    out["chain_short"] = {"workload": "2 x 480,000, 101-tap FIR | Butterworth HP (2 SOS)",
-                          "Msamples_per_s": round(x.numel() / s / 1e6, 1), "ms": round(s * 1e3, 4),
-                          "rel_err": rel_err(y, O.chain(w.x, w.stages)), "tolerance": 1e-4}
-    del x, st
+    def want(name):
+        return only is None or name in only
 
-    log("fir_long")
-    w = workloads.fir_long()
-    x = torch.from_numpy(w.x).to(dev)
-    h = torch.from_numpy(w.stages[0][1]).to(dev)
-    n = x.numel()
-    M = h.numel()
-    pos = np.linspace(0, w.x.shape[1] - 1, 257).astype(np.int64)
-    chans = [0, 21, 63]
-    ref = O.fir_at(w.x[chans], w.stages[0][1], pos)
-    o_sec = O.last_seconds()
-    res = {"workload": "64 x 5,760,000, 8191-tap low-pass", "error": "rel RMS on 3 ch x 257 sampled outputs",
-           "oracle": {"Msamples_per_s": round(len(chans) * pos.size / o_sec / 1e6, 4),
-                      "cores": min(len(chans), O.threads()),
-                      "sample": "3 ch x 257 outputs by direct convolution, steady clock around the C loop"}}
-    for name, kw, tol in [("fft_f32", {}, 1e-5), ("fft4096_parts_f32", {"algo": "fft"}, 1e-5),
-                          ("toeplitz_bf16", {"compute": "bf16"}, 1e-2),
-                          ("toeplitz_f16", {"compute": "f16"}, 1e-2), ("toeplitz_bf16x3", {"compute": "bf16x3"}, None)]:
-        s = timed(torch, lambda: tfx.fir(x, h, **kw), 3, stream)
-        yy = tfx.fir(x, h, **kw)[chans][:, pos].cpu().numpy()
-        e = {"Msamples_per_s": round(n / s / 1e6, 1), "ms": round(s * 1e3, 3), "rel_err": rel_err(yy, ref)}
-        if tol:
-            e["tolerance"] = tol
-        if name.startswith("toeplitz"):
-            flops = 2.0 * n * M * (3 if name.endswith("x3") else 1)
-            e["mfma_TFLOP_per_s"] = round(flops / s / 1e12, 1)
-            e["mfma_frac"] = round(flops / s / 1e12 / MFMA_BF16_PEAK_TFS, 4)
-        res[name] = e
-    out["fir_long"] = res
-    del x, h
+    if want("chain_short"):
+        log("chain_short")
+        w = workloads.chain_short()
+        x = torch.from_numpy(w.x).to(dev)
+        st = [(k, torch.from_numpy(c).to(dev)) for k, c in w.stages]
+        s = timed(torch, lambda: tfx.chain(x, st), 20, stream)
+        y = tfx.chain(x, st).cpu().numpy()
+        out["chain_short"] = {"workload": "2 x 480,000, 101-tap FIR | Butterworth HP (2 SOS)",
+                              "Msamples_per_s": round(x.numel() / s / 1e6, 1), "ms": round(s * 1e3, 4),
+                              "rel_err": rel_err(y, O.chain(w.x, w.stages)), "tolerance": 1e-4}
+        del x, st
 
-    log("ragged batch")
-    clips = workloads.ragged()
-    xs = [torch.from_numpy(c[0]).to(dev) for c in clips]
-    ss = [torch.from_numpy(c[1]).to(dev) for c in clips]
-    n = sum(t.numel() for t in xs)
-    b = tfx.SosBatch(xs, ss)
-    cfg, _ = b.tune(reps=2)
-    s_b = timed(torch, b.run, 5, stream)
-    # the batch as one captured graph (one hipGraphLaunch per replay)
-    gs = torch.cuda.Stream()
-    gs.wait_stream(stream)
-    graph = torch.cuda.CUDAGraph()
-    with torch.cuda.stream(gs):
-        with torch.cuda.graph(graph, stream=gs):
-            b.run()
-    stream.wait_stream(gs)
-    s_g = timed(torch, graph.replay, 10, stream)
-    s_l = timed(torch, lambda: [tfx.sos(a, c) for a, c in zip(xs, ss)], 3, stream)
-    graph.replay()
-    ys = b.ys
-    errs = [rel_err(ys[i].cpu().numpy(), O.sos(clips[i][0], clips[i][1])) for i in (0, 97, 201)]
-    c0 = time.perf_counter()
-    c_sec = 0.0
-    c_n = 0
-    for i in (0, 97, 201):
-        O.sos(clips[i][0], clips[i][1])
-        c_sec += O.last_seconds()
-        c_n += clips[i][0].size
-    out["ragged_batch"] = {"workload": "256 clips @44.1 kHz, 1-30 s, 1-16 ch, 1-6 SOS each",
-                           "samples": n, "tuned": cfg, "Msamples_per_s": round(n / s_g / 1e6, 1),
-                           "ms": round(s_g * 1e3, 3), "timing": "one hipGraph replay of the batched run",
-                           "eager_run_ms": round(s_b * 1e3, 3),
-                           "hbm_frac": round(8.0 * n / s_g / 1e9 / HBM_PEAK_GBS, 4),
-                           "per_clip_calls_ms": round(s_l * 1e3, 3),
-                           "speedup_vs_per_clip": round(s_l / s_g, 2), "rel_err_3_clips": max(errs),
-                           "tolerance": 1e-4,
-                           "oracle": {"Msamples_per_s": round(c_n / c_sec / 1e6, 3), "cores": O.threads(),
-                                      "sample": "clips 0, 97 and 201 (%d samples), steady clock around the C loops"
-                                                % c_n}}
-    del xs, ss, b, ys, graph
+    if want("fir_long"):
+        log("fir_long")
+        w = workloads.fir_long()
+        x = torch.from_numpy(w.x).to(dev)
+        h = torch.from_numpy(w.stages[0][1]).to(dev)
+        n = x.numel()
+        M = h.numel()
+        pos = np.linspace(0, w.x.shape[1] - 1, 257).astype(np.int64)
+        chans = [0, 21, 63]
+        ref = O.fir_at(w.x[chans], w.stages[0][1], pos)
+        o_sec = O.last_seconds()
+        res = {"workload": "64 x 5,760,000, 8191-tap low-pass", "error": "rel RMS on 3 ch x 257 sampled outputs",
+               "oracle": {"Msamples_per_s": round(len(chans) * pos.size / o_sec / 1e6, 4),
+                          "cores": min(len(chans), O.threads()),
+                          "sample": "3 ch x 257 outputs by direct convolution, steady clock around the C loop"}}
+        for name, kw, tol in [("fft_f32", {}, 1e-5), ("fft4096_parts_f32", {"algo": "fft"}, 1e-5),
+                              ("toeplitz_bf16", {"compute": "bf16"}, 1e-2),
+                              ("toeplitz_f16", {"compute": "f16"}, 1e-2), ("toeplitz_bf16x3", {"compute": "bf16x3"}, None)]:
+            s = timed(torch, lambda: tfx.fir(x, h, **kw), 3, stream)
+            yy = tfx.fir(x, h, **kw)[chans][:, pos].cpu().numpy()
+            e = {"Msamples_per_s": round(n / s / 1e6, 1), "ms": round(s * 1e3, 3), "rel_err": rel_err(yy, ref)}
+            if tol:
+                e["tolerance"] = tol
+            if name.startswith("toeplitz"):
+                flops = 2.0 * n * M * (3 if name.endswith("x3") else 1)
+                e["mfma_TFLOP_per_s"] = round(flops / s / 1e12, 1)
+                e["mfma_frac"] = round(flops / s / 1e12 / MFMA_BF16_PEAK_TFS, 4)
+            res[name] = e
+        out["fir_long"] = res
+        del x, h
 
-    log("chain_short_large (C1-L)")
-    w = workloads.chain_mid_short_fir()
-    x = torch.from_numpy(w.x).to(dev)
-    st = [(k, torch.from_numpy(c).to(dev)) for k, c in w.stages]
-    s = timed(torch, lambda: tfx.chain(x, st), 20, stream)
-    y = tfx.chain(x, st)[:2].cpu().numpy()
-    out["chain_short_large"] = {"workload": "8 x 5,760,000, chain_short's filters (101-tap FIR | Butterworth HP, "
-                                            "2 SOS), one tfx_chain call",
-                                "Msamples_per_s": round(x.numel() / s / 1e6, 1), "ms": round(s * 1e3, 4),
-                                "hbm_frac": round(8.0 * x.numel() / s / 1e9 / HBM_PEAK_GBS, 4),
-                                "rel_err_2ch": rel_err(y, O.chain(w.x[:2], w.stages)), "tolerance": 1e-4}
-    del x, st
+    if want("fir_mid_forms"):
+        log("fir_mid_forms")
+        w = workloads.chain_mid()
+        x = torch.from_numpy(w.x).to(dev)
+        h = torch.from_numpy(w.stages[0][1]).to(dev)
+        n = x.numel()
+        M = h.numel()
+        pos = np.linspace(0, w.x.shape[1] - 1, 513).astype(np.int64)
+        chans = [0, 5]
+        ref = O.fir_at(w.x[chans], w.stages[0][1], pos)
+        res = {"workload": "chain_mid's 1023-tap band-pass FIR alone on its signal (8 x 5,760,000)",
+               "error": "rel RMS on 2 ch x 513 sampled outputs"}
+        for name, kw, tol, reps in [("direct_f32", {"algo": "direct"}, 1e-5, 3), ("fft_f32", {"algo": "fft"}, 1e-5, 10),
+                                    ("fft16k_f32", {"algo": "fft16k"}, 1e-5, 10),
+                                    ("toeplitz_bf16", {"compute": "bf16"}, 1e-2, 10),
+                                    ("toeplitz_f16", {"compute": "f16"}, 1e-2, 10),
+                                    ("toeplitz_bf16x3", {"compute": "bf16x3"}, 1e-4, 10)]:
+            s = timed(torch, lambda: tfx.fir(x, h, **kw), reps, stream)
+            yy = tfx.fir(x, h, **kw)[chans][:, pos].cpu().numpy()
+            e = {"ms": round(s * 1e3, 4), "Msamples_per_s": round(n / s / 1e6, 1), "rel_err": rel_err(yy, ref),
+                 "tolerance": tol}
+            if name.startswith("toeplitz"):
+                flops = 2.0 * n * M * (3 if name.endswith("x3") else 1)
+                e["mfma_TFLOP_per_s"] = round(flops / s / 1e12, 1)
+            res[name] = e
+        out["fir_mid_forms"] = res
+        del x, h
 
-    log("learnable: forward, forward + backward")
-    x_np, params, target = workloads.learnable()
-    x = torch.from_numpy(x_np).to(dev)
-    st = [(k, torch.from_numpy(c).to(dev)) for k, c in target]
-    gup = torch.from_numpy(np.random.default_rng(12).standard_normal(x_np.shape).astype(np.float32)).to(dev)
-    s_f = timed(torch, lambda: tfx.chain(x, st), 20, stream)
+    if want("ragged"):
+        log("ragged batch")
+        clips = workloads.ragged()
+        xs = [torch.from_numpy(c[0]).to(dev) for c in clips]
+        ss = [torch.from_numpy(c[1]).to(dev) for c in clips]
+        n = sum(t.numel() for t in xs)
+        b = tfx.SosBatch(xs, ss)
+        cfg, _ = b.tune(reps=2)
+        s_b = timed(torch, b.run, 5, stream)
+        # the batch as one captured graph (one hipGraphLaunch per replay)
+        gs = torch.cuda.Stream()
+        gs.wait_stream(stream)
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.stream(gs):
+            with torch.cuda.graph(graph, stream=gs):
+                b.run()
+        stream.wait_stream(gs)
+        s_g = timed(torch, graph.replay, 10, stream)
+        s_l = timed(torch, lambda: [tfx.sos(a, c) for a, c in zip(xs, ss)], 3, stream)
+        graph.replay()
+        ys = b.ys
+        errs = [rel_err(ys[i].cpu().numpy(), O.sos(clips[i][0], clips[i][1])) for i in (0, 97, 201)]
+        c0 = time.perf_counter()
+        c_sec = 0.0
+        c_n = 0
+        for i in (0, 97, 201):
+            O.sos(clips[i][0], clips[i][1])
+            c_sec += O.last_seconds()
+            c_n += clips[i][0].size
+        out["ragged_batch"] = {"workload": "256 clips @44.1 kHz, 1-30 s, 1-16 ch, 1-6 SOS each",
+                               "samples": n, "tuned": cfg, "Msamples_per_s": round(n / s_g / 1e6, 1),
+                               "ms": round(s_g * 1e3, 3), "timing": "one hipGraph replay of the batched run",
+                               "eager_run_ms": round(s_b * 1e3, 3),
+                               "hbm_frac": round(8.0 * n / s_g / 1e9 / HBM_PEAK_GBS, 4),
+                               "per_clip_calls_ms": round(s_l * 1e3, 3),
+                               "speedup_vs_per_clip": round(s_l / s_g, 2), "rel_err_3_clips": max(errs),
+                               "tolerance": 1e-4,
+                               "oracle": {"Msamples_per_s": round(c_n / c_sec / 1e6, 3), "cores": O.threads(),
+                                          "sample": "clips 0, 97 and 201 (%d samples), steady clock around the C loops"
+                                                    % c_n}}
+        del xs, ss, b, ys, graph
 
-    def fb():
-        yv, ck = tfx.chain(x, st, return_ckpt=True)
-        return tfx.chain_backward(x, gup, st, ck)
-    s_fb = timed(torch, fb, 20, stream)
-    out["learnable_fwd_bwd"] = {"workload": "64 x 192,000 (32 x 2 ch), 255-tap FIR | 8 SOS",
-                                "fwd_Msamples_per_s": round(x.numel() / s_f / 1e6, 1), "fwd_ms": round(s_f * 1e3, 4),
-                                "fwd_bwd_Msamples_per_s": round(x.numel() / s_fb / 1e6, 1),
-                                "fwd_bwd_ms": round(s_fb * 1e3, 4), "ratio_to_fwd": round(s_f / s_fb, 4),
-                                "step": "tfx_chain (+ checkpoints) and tfx_chain_backward for a fixed upstream "
-                                        "gradient (input, taps and section gradients)"}
-    del x, st, gup
+    if want("chain_short_large"):
+        log("chain_short_large (C1-L)")
+        w = workloads.chain_mid_short_fir()
+        x = torch.from_numpy(w.x).to(dev)
+        st = [(k, torch.from_numpy(c).to(dev)) for k, c in w.stages]
+        s = timed(torch, lambda: tfx.chain(x, st), 20, stream)
+        y = tfx.chain(x, st)[:2].cpu().numpy()
+        out["chain_short_large"] = {"workload": "8 x 5,760,000, chain_short's filters (101-tap FIR | Butterworth HP, "
+                                                "2 SOS), one tfx_chain call",
+                                    "Msamples_per_s": round(x.numel() / s / 1e6, 1), "ms": round(s * 1e3, 4),
+                                    "hbm_frac": round(8.0 * x.numel() / s / 1e9 / HBM_PEAK_GBS, 4),
+                                    "rel_err_2ch": rel_err(y, O.chain(w.x[:2], w.stages)), "tolerance": 1e-4}
+        del x, st
 
-    log("learnable fwd+bwd")
-    x_np, params, target = workloads.learnable()
-    x = torch.from_numpy(x_np).to(dev)
-    hh = torch.from_numpy(params["h"]).to(dev).requires_grad_(True)
-    sec = torch.from_numpy(target[1][1]).to(dev).requires_grad_(True)
-    tgt = torch.from_numpy(O.chain(x_np, target).astype(np.float32)).to(dev)
+    if want("learnable"):
+        log("learnable: forward, forward + backward")
+        x_np, params, target = workloads.learnable()
+        x = torch.from_numpy(x_np).to(dev)
+        st = [(k, torch.from_numpy(c).to(dev)) for k, c in target]
+        gup = torch.from_numpy(np.random.default_rng(12).standard_normal(x_np.shape).astype(np.float32)).to(dev)
+        s_f = timed(torch, lambda: tfx.chain(x, st), 20, stream)
 
-    def step():
-        yv = tfx.chain(x, [("fir", hh), ("sos", sec)])
-        loss = torch.mean((yv - tgt) ** 2)
-        loss.backward()
-    s = timed(torch, step, 10, stream)
-    out["learnable"] = {"workload": "64 x 192,000, 255-tap FIR + 8 SOS, MSE loss, grads of taps and sections",
-                        "fwd_bwd_ms": round(s * 1e3, 3), "Msamples_per_s": round(x.numel() / s / 1e6, 1)}
-    del x, hh, sec, tgt
+        def fb():
+            yv, ck = tfx.chain(x, st, return_ckpt=True)
+            return tfx.chain_backward(x, gup, st, ck)
+        s_fb = timed(torch, fb, 20, stream)
+        out["learnable_fwd_bwd"] = {"workload": "64 x 192,000 (32 x 2 ch), 255-tap FIR | 8 SOS",
+                                    "fwd_Msamples_per_s": round(x.numel() / s_f / 1e6, 1), "fwd_ms": round(s_f * 1e3, 4),
+                                    "fwd_bwd_Msamples_per_s": round(x.numel() / s_fb / 1e6, 1),
+                                    "fwd_bwd_ms": round(s_fb * 1e3, 4), "ratio_to_fwd": round(s_f / s_fb, 4),
+                                    "step": "tfx_chain (+ checkpoints) and tfx_chain_backward for a fixed upstream "
+                                            "gradient (input, taps and section gradients)"}
+        del x, st, gup
 
-    log("wave pipe")
-    w = workloads.chain_mid()
-    x = torch.from_numpy(w.x).to(dev)
-    fs = [tfx.WindowedSincFIR(300.0, num_taps=1023, cutoff_hi=6000.0), tfx.HiShelving(1000.0), tfx.LoShelving(2000.0),
-          tfx.Peaking(3000.0, q=2.0, gain_db=-3.0)]
+    if want("learnable"):
+        log("learnable fwd+bwd")
+        x_np, params, target = workloads.learnable()
+        x = torch.from_numpy(x_np).to(dev)
+        hh = torch.from_numpy(params["h"]).to(dev).requires_grad_(True)
+        sec = torch.from_numpy(target[1][1]).to(dev).requires_grad_(True)
+        tgt = torch.from_numpy(O.chain(x_np, target).astype(np.float32)).to(dev)
 
-    def piped():
-        wv = tfx.Wave(x, 48000.0)
-        for f in fs:
-            wv = wv | f
-        return wv.y
-    yp = piped()
-    st = [f.stage(x.device) for f in fs]
-    s_p = timed(torch, piped, 10, stream)
-    s_c = timed(torch, lambda: tfx.chain(x, st), 10, stream)
-    ref = O.chain(w.x[:2], [(f.kind, f.coefficients("cpu").numpy()) for f in fs])
-    out["wave_pipe"] = {"workload": "8 x 5,760,000 @48 kHz: Wave | WindowedSincFIR(1023) | HiShelving | LoShelving "
-                                    "| Peaking (one fused launch)",
-                        "Msamples_per_s": round(x.numel() / s_p / 1e6, 1), "ms": round(s_p * 1e3, 4),
-                        "direct_chain_ms": round(s_c * 1e3, 4),
-                        "rel_err_2ch": rel_err(yp[:2].cpu().numpy(), ref), "tolerance": 1e-4}
-    del x, yp
+        def step():
+            yv = tfx.chain(x, [("fir", hh), ("sos", sec)])
+            loss = torch.mean((yv - tgt) ** 2)
+            loss.backward()
+        s = timed(torch, step, 10, stream)
+        out["learnable"] = {"workload": "64 x 192,000, 255-tap FIR + 8 SOS, MSE loss, grads of taps and sections",
+                            "fwd_bwd_ms": round(s * 1e3, 3), "Msamples_per_s": round(x.numel() / s / 1e6, 1)}
+        del x, hh, sec, tgt
 
-    log("chain_mid, matrix-core FIR")
-    w = workloads.chain_mid()
-    x = torch.from_numpy(w.x).to(dev)
-    st = [(k, torch.from_numpy(c).to(dev)) for k, c in w.stages]
-    ref = O.chain(w.x[:2], w.stages)
-    res = {"workload": "chain_mid (8 x 5,760,000, 1023-tap FIR | 6 SOS), one tfx_chain call (prepare + run)"}
-    for comp in ("f32", "bf16", "f16"):
-        s_c = timed(torch, lambda: tfx.chain(x, st, compute=comp), 10, stream)
-        yc = tfx.chain(x, st, compute=comp)[:2].cpu().numpy()
-        res[comp] = {"ms": round(s_c * 1e3, 4), "Msamples_per_s": round(x.numel() / s_c / 1e6, 1),
-                     "rel_err_2ch": rel_err(yc, ref), "tolerance": 1e-4 if comp == "f32" else 1e-2}
-    out["chain_mid_compute"] = res
-    del x, st
+    if want("wave_pipe"):
+        log("wave pipe")
+        w = workloads.chain_mid()
+        x = torch.from_numpy(w.x).to(dev)
+        fs = [tfx.WindowedSincFIR(300.0, num_taps=1023, cutoff_hi=6000.0), tfx.HiShelving(1000.0), tfx.LoShelving(2000.0),
+              tfx.Peaking(3000.0, q=2.0, gain_db=-3.0)]
 
-    log("stream")
-    w = workloads.chain_mid(C=8, N=48000)
-    x = torch.from_numpy(w.x).to(dev)
-    st = [(k, torch.from_numpy(c).to(dev)) for k, c in w.stages]
-    res = {"workload": "8 ch @48 kHz, chain_mid's filters (1023-tap FIR | 6 SOS), blocks carried by tfx_chain_stream"}
-    for blk in (512, 4096):
-        sm = tfx.ChainStream(st, 8, blk)
-        nb = x.shape[1] // blk
-        blocks = [x[:, i * blk:(i + 1) * blk].contiguous() for i in range(nb)]
-        ys = [sm.process(b) for b in blocks]
-        y = torch.cat(ys, dim=1).cpu().numpy()
-        sm.reset()
-        it = iter(range(10 ** 9))
+        def piped():
+            wv = tfx.Wave(x, 48000.0)
+            for f in fs:
+                wv = wv | f
+            return wv.y
+        yp = piped()
+        st = [f.stage(x.device) for f in fs]
+        s_p = timed(torch, piped, 10, stream)
+        s_c = timed(torch, lambda: tfx.chain(x, st), 10, stream)
+        ref = O.chain(w.x[:2], [(f.kind, f.coefficients("cpu").numpy()) for f in fs])
+        out["wave_pipe"] = {"workload": "8 x 5,760,000 @48 kHz: Wave | WindowedSincFIR(1023) | HiShelving | LoShelving "
+                                        "| Peaking (one fused launch)",
+                            "Msamples_per_s": round(x.numel() / s_p / 1e6, 1), "ms": round(s_p * 1e3, 4),
+                            "direct_chain_ms": round(s_c * 1e3, 4),
+                            "rel_err_2ch": rel_err(yp[:2].cpu().numpy(), ref), "tolerance": 1e-4}
+        del x, yp
 
-        def one():
-            i = next(it) % nb
-            if i == 0:
-                sm.reset()
-            sm.process(blocks[i])
-        s = timed(torch, one, 200, stream)
-        res["block_%d" % blk] = {"us_per_block": round(s * 1e6, 1), "Msamples_per_s": round(8 * blk / s / 1e6, 1),
-                                 "realtime_factor": round(blk / 48000.0 / s, 1),
-                                 "rel_err_vs_oracle": rel_err(y, O.chain(w.x[:, :nb * blk], w.stages)),
-                                 "tolerance": 1e-4}
-    out["stream"] = res
-    del x
+    if want("chain_mid_compute"):
+        log("chain_mid, matrix-core FIR")
+        w = workloads.chain_mid()
+        x = torch.from_numpy(w.x).to(dev)
+        st = [(k, torch.from_numpy(c).to(dev)) for k, c in w.stages]
+        ref = O.chain(w.x[:2], w.stages)
+        res = {"workload": "chain_mid (8 x 5,760,000, 1023-tap FIR | 6 SOS), one tfx_chain call (prepare + run)"}
+        for comp in ("f32", "bf16", "f16"):
+            s_c = timed(torch, lambda: tfx.chain(x, st, compute=comp), 10, stream)
+            yc = tfx.chain(x, st, compute=comp)[:2].cpu().numpy()
+            res[comp] = {"ms": round(s_c * 1e3, 4), "Msamples_per_s": round(x.numel() / s_c / 1e6, 1),
+                         "rel_err_2ch": rel_err(yc, ref), "tolerance": 1e-4 if comp == "f32" else 1e-2}
+        out["chain_mid_compute"] = res
+        del x, st
 
-    out["stft"] = stft_leg(torch, dev, stream)
+    if want("stream"):
+        log("stream")
+        w = workloads.chain_mid(C=8, N=48000)
+        x = torch.from_numpy(w.x).to(dev)
+        st = [(k, torch.from_numpy(c).to(dev)) for k, c in w.stages]
+        res = {"workload": "8 ch @48 kHz, chain_mid's filters (1023-tap FIR | 6 SOS), blocks carried by tfx_chain_stream"}
+        for blk in (512, 4096):
+            sm = tfx.ChainStream(st, 8, blk)
+            nb = x.shape[1] // blk
+            blocks = [x[:, i * blk:(i + 1) * blk].contiguous() for i in range(nb)]
+            ys = [sm.process(b) for b in blocks]
+            y = torch.cat(ys, dim=1).cpu().numpy()
+            sm.reset()
+            it = iter(range(10 ** 9))
+
+            def one():
+                i = next(it) % nb
+                if i == 0:
+                    sm.reset()
+                sm.process(blocks[i])
+            s = timed(torch, one, 200, stream)
+            res["block_%d" % blk] = {"us_per_block": round(s * 1e6, 1), "Msamples_per_s": round(8 * blk / s / 1e6, 1),
+                                     "realtime_factor": round(blk / 48000.0 / s, 1),
+                                     "rel_err_vs_oracle": rel_err(y, O.chain(w.x[:, :nb * blk], w.stages)),
+                                     "tolerance": 1e-4}
+        out["stream"] = res
+        del x
+
+    if want("stft"):
+        out["stft"] = stft_leg(torch, dev, stream)
     return out
 
 
@@ -394,6 +444,9 @@ def main():
     torch.cuda.set_device(dev)
     if args.stft_only:
         print(json.dumps({"stft": stft_leg(torch, dev, torch.cuda.current_stream(dev))}))
+        return
+    if args.leg:
+        print(json.dumps(secondary(torch, dev, torch.cuda.current_stream(dev), set(args.leg))))
         return
     log("generating chain_mid inputs (8 x 5,760,000)")
     w = workloads.chain_mid()
