@@ -14,20 +14,24 @@
 //
 // The transform: 16384 = 16 x 16 x 16 x 4.  With n = 1024 a + 64 b + 4 d + e
 // and k = k1 + 16 k2 + 256 k3 + 4096 k4, W = e^{-2 pi i / 16384}:
-//   pass A  (over a, lane t = 64 b + 4 d + e):  16-point DFT, then * W^(t k1)
+//   pass A  (over a, lane L = 64 b + 4 d + e):  16-point DFT, then * W^(L k1)
 //   pass B  (over b, lane (k1, c = 4 d + e)):   16-point DFT, then * W^(16 c k2)
 //   pass C  (over d, lane (k1, k2, e)):         16-point DFT, then * W^(256 e k3)
 //   pass D  (over e, lane (k1, k2, q)):         four 4-point DFTs (k3 = 4 q + r)
-// Each of the 1024 lanes holds 16 values; the three exchanges go through one
-// LDS array of 16384 complex values (re and im planes, 128 KB).  Exchange B->C
-// and C->D rotate the 4-element groups of a 64-element row by the row index
-// k2, which makes every access pattern free of bank conflicts (checked on the
-// CPU for 64 banks per wave and 32 per half-wave, and for the 16-byte reads
-// of pass D).  The inverse runs the passes backwards with conjugate twiddles
-// and ends in pass A's layout.  The spectrum product is done in registers in
-// pass D's lane order, in which the tap spectrum is stored: it is computed by
-// this same forward transform from the zero-padded taps (fp32) and scaled by
-// 1/16384.
+// The 1024 lanes L are virtual: thread t of a 512-thread workgroup runs lanes
+// t and t + 512, each with 16 values, so a block needs 64 data registers a
+// thread and two blocks share a CU (one overlapping the other's loads,
+// barriers and LDS traffic).  The three exchanges go through one LDS plane of
+// 16384 floats (64 KB), the real parts first, then the imaginary parts.
+// Exchanges B->C and C->D rotate the 4-element groups of a 64-element row by
+// the row index k2, which makes every access pattern free of bank conflicts
+// (checked on the CPU for 64 banks per wave and 32 per half-wave, and for the
+// 16-byte reads of pass D; the lanes of a wave are 64 consecutive virtual
+// lanes either way).  The inverse runs the passes backwards with conjugate
+// twiddles and ends in pass A's layout.  The spectrum product is done in
+// registers in pass D's lane order, in which the tap spectrum is stored: it is
+// computed by this same forward transform from the zero-padded taps (fp32)
+// and scaled by 1/16384.
 #include <hip/hip_runtime.h>
 
 #include "tfx_device.h"
@@ -39,13 +43,19 @@ namespace {
 
 constexpr int NB = FFT16_POINTS;  // 16384
 constexpr int HOPB = FFT16_HOP;   // 8192 outputs per block
-constexpr int WGB = 1024;         // lanes per workgroup
+#ifndef TFX_FFT16_NV
+#define TFX_FFT16_NV 2
+#endif
+constexpr int NV = TFX_FFT16_NV;  // virtual lanes per thread: t + VS v
+constexpr int WGB = 1024 / NV;    // threads per workgroup
+constexpr int VS = WGB;           // virtual-lane stride
+
 // twiddle regions (float2): TWA [1024][16], TWB [64][16], TWC [4][16]
 constexpr int TWA_OFF = 0, TWB_OFF = 16384, TWC_OFF = 16384 + 1024;
 
 // twiddle_row with the table loads in groups of two 16-byte loads (a
 // compiler barrier between groups), so at most four twiddles sit in
-// registers beside the 32 data values.
+// registers beside the data.
 template <bool CONJ>
 __device__ __forceinline__ void twiddle_row_lean(float (&zr)[16], float (&zi)[16], const float2 *row) {
     const float4 *r4 = reinterpret_cast<const float4 *>(row);
@@ -60,153 +70,246 @@ __device__ __forceinline__ void twiddle_row_lean(float (&zr)[16], float (&zi)[16
     }
 }
 
-// Base of the imaginary plane, 64 KB into the LDS array.  The offset is
-// passed through an empty asm so it stays a register value: folded into the
-// addresses as a constant, offsets past 64 KB do not fit the 16-bit offset
-// field of the LDS instructions, and every access to the plane would need
-// an address register of its own (about twenty live registers).
-__device__ __forceinline__ float *imag_plane(float *lds) {
-    int off = NB;
-    asm volatile("" : "+s"(off));
-    return lds + off;
+// Lane coordinates of virtual lane L = t + 512 v.
+struct Lane {
+    int L, k1, c, d, e, k2, q;
+    __device__ __forceinline__ explicit Lane(int l)
+        : L(l), k1(l >> 6), c(l & 63), d((l & 63) >> 2), e(l & 3), k2((l >> 2) & 15), q(l & 3) {}
+};
+
+// Address maps of the exchanges (element j of the lane):
+//   A->B  write 1024 j + L                      read 1024 k1 + 64 j + c
+//   B->C  write rot64(1024 k1 + 4 d + e, j, d)   read rot64(rc, j, k2) (k2 = j)
+//   C->D  write rot64(rc, j, k2) (k3 = j)        read 16-byte groups in pass D
+// with rot64(base, j, r) = base + 68 j - 64 [j >= 16 - r] (row j of 64
+// elements, the group rotated by r) and rc = 1024 k1 + 68 k2 + e.
+// A Map holds the two row bases (base and base - 64) as byte offsets the
+// compiler cannot see through, so an access costs one select and its step
+// is the LDS instruction's immediate offset.
+struct Map {
+    int o0, o1, r, step;
+    __device__ __forceinline__ Map(int base, int step_, int r_) : r(r_), step(step_) {
+        o0 = 4 * base;
+        o1 = 4 * (base - 64);
+        asm volatile("" : "+v"(o0), "+v"(o1));
+    }
+    __device__ __forceinline__ float *at(float *P, int j) const {
+        return reinterpret_cast<float *>(reinterpret_cast<char *>(P) + (j >= 16 - r ? o1 : o0) + 4 * step * j);
+    }
+};
+__device__ __forceinline__ Map map_a(const Lane &l) { return Map(l.L, 1024, 0); }
+__device__ __forceinline__ Map map_b(const Lane &l) { return Map(1024 * l.k1 + l.c, 64, 0); }
+__device__ __forceinline__ Map rot_w(const Lane &l) { return Map(1024 * l.k1 + 4 * l.d + l.e, 68, l.d); }
+__device__ __forceinline__ Map rot_c(const Lane &l) { return Map(1024 * l.k1 + 68 * l.k2 + l.e, 4, l.k2); }
+
+// A copy of the thread index the compiler cannot see through: addresses
+// derived from it are recomputed where they are used instead of being kept
+// in registers from one phase of an exchange to the next.
+__device__ __forceinline__ int opaque(int t) {
+    asm volatile("" : "+v"(t));
+    return t;
 }
 
-// Forward transform.  In: lane t holds z[1024 a + t] in zr/zi[a].  Out: lane
-// L = 64 k1 + 4 k2 + q holds Z[k1 + 16 k2 + 256 (4 q + r) + 4096 k4] in
-// zr/zi[4 r + k4].  Ends with every lane past its last LDS read only after
-// the caller's next barrier.
-__device__ __forceinline__ void fft16k_forward(float (&zr)[16], float (&zi)[16], float *Lr, float *Li,
-                                               const float2 *tw, int L) {
-    const int k1 = L >> 6, c = L & 63, d = c >> 2, e = c & 3;  // pass B lane
-    const int k2 = (L >> 2) & 15, q = L & 3;                    // passes C (e = L & 3) and D
-    // pass A
-    dft16<-1>(zr, zi);
-    twiddle_row_lean<false>(zr, zi, tw + TWA_OFF + 16 * L);
-#pragma unroll
-    for (int j = 0; j < 16; ++j) {
-        Lr[1024 * j + L] = zr[j];
-        Li[1024 * j + L] = zi[j];
-    }
-    __syncthreads();
-    // pass B
-#pragma unroll
-    for (int b = 0; b < 16; ++b) {
-        zr[b] = Lr[1024 * k1 + 64 * b + c];
-        zi[b] = Li[1024 * k1 + 64 * b + c];
-    }
-    dft16<-1>(zr, zi);
-    twiddle_row_lean<false>(zr, zi, tw + TWB_OFF + 16 * c);
-    __syncthreads();
+// One LDS exchange of both virtual lanes' 16 values through the plane P:
+// value j of lane v goes to P[W(lane, j)] and comes back from P[R(lane, j)],
+// the real parts first.  The caller has passed a barrier since the last read
+// of P; the exchange ends after its own last read (no barrier).
+template <class WA, class RA>
+__device__ __forceinline__ void exchange(float (&zr)[NV][16], float (&zi)[NV][16], float *P, int t, WA wad,
+                                         RA rad) {
     {
-        // element (k1, k2 = j, d, e) at 1024 k1 + 64 j + 4 ((d + j) & 15) + e
-        const int w0 = 1024 * k1 + 4 * d + e;
+        const int u = opaque(t);
 #pragma unroll
-        for (int j = 0; j < 16; ++j) {
-            const int ad = (j >= 16 - d ? w0 - 64 : w0) + 68 * j;
-            Lr[ad] = zr[j];
-            Li[ad] = zi[j];
+        for (int v = 0; v < NV; ++v) {
+            const Map m = wad(Lane(u + VS * v));
+#pragma unroll
+            for (int j = 0; j < 16; ++j) *m.at(P, j) = zr[v][j];
         }
     }
     __syncthreads();
-    // pass C: lane (k1, k2, e); element (k1, k2, j, e) at rowc + 4 ((j + k2) & 15)
-    const int ec = L & 3, rc = 1024 * k1 + 64 * k2 + 4 * k2 + ec;
+    {
+        const int u = opaque(t);
 #pragma unroll
-    for (int j = 0; j < 16; ++j) {  // j = d
-        const int ad = (j >= 16 - k2 ? rc - 64 : rc) + 4 * j;
-        zr[j] = Lr[ad];
-        zi[j] = Li[ad];
-    }
-    dft16<-1>(zr, zi);
-    twiddle_row_lean<false>(zr, zi, tw + TWC_OFF + 16 * ec);
-    __syncthreads();
+        for (int v = 0; v < NV; ++v) {
+            const Map m = rad(Lane(u + VS * v));
 #pragma unroll
-    for (int j = 0; j < 16; ++j) {  // j = k3
-        const int ad = (j >= 16 - k2 ? rc - 64 : rc) + 4 * j;
-        Lr[ad] = zr[j];
-        Li[ad] = zi[j];
+            for (int j = 0; j < 16; ++j) zr[v][j] = *m.at(P, j);
+        }
     }
     __syncthreads();
-    // pass D: lane (k1, k2, q) reads (k3 = 4 q + r, e = 0..3) as 16-byte groups
-    const int rowd = 1024 * k1 + 64 * k2;
+    {
+        const int u = opaque(t);
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const int ad = rowd + 4 * ((4 * q + r + k2) & 15);
-        const float4 vr = *reinterpret_cast<const float4 *>(Lr + ad);
-        const float4 vi = *reinterpret_cast<const float4 *>(Li + ad);
-        zr[4 * r] = vr.x; zr[4 * r + 1] = vr.y; zr[4 * r + 2] = vr.z; zr[4 * r + 3] = vr.w;
-        zi[4 * r] = vi.x; zi[4 * r + 1] = vi.y; zi[4 * r + 2] = vi.z; zi[4 * r + 3] = vi.w;
+        for (int v = 0; v < NV; ++v) {
+            const Map m = wad(Lane(u + VS * v));
+#pragma unroll
+            for (int j = 0; j < 16; ++j) *m.at(P, j) = zi[v][j];
+        }
     }
+    __syncthreads();
+    {
+        const int u = opaque(t);
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
-        dft4<-1>(zr[4 * r], zi[4 * r], zr[4 * r + 1], zi[4 * r + 1], zr[4 * r + 2], zi[4 * r + 2], zr[4 * r + 3],
-                 zi[4 * r + 3]);
+        for (int v = 0; v < NV; ++v) {
+            const Map m = rad(Lane(u + VS * v));
+#pragma unroll
+            for (int j = 0; j < 16; ++j) zi[v][j] = *m.at(P, j);
+        }
+    }
+}
+
+// Pass D's side of the exchange C <-> D: lane (k1, k2, q) owns the 16-byte
+// groups k3 = 4 q + r (r = 0..3) of row 1024 k1 + 64 k2, rotated by k2 like
+// pass C's accesses; one plane (z = real or imaginary parts) at a time.
+__device__ __forceinline__ int group_addr(const Lane &l, int r) {
+    return 1024 * l.k1 + 64 * l.k2 + 4 * ((4 * l.q + r + l.k2) & 15);
+}
+__device__ __forceinline__ void load_groups(float (&z)[NV][16], const float *P, int t) {
+    const int u = opaque(t);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        const Lane l(u + VS * v);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const float4 w = *reinterpret_cast<const float4 *>(P + group_addr(l, r));
+            z[v][4 * r] = w.x;
+            z[v][4 * r + 1] = w.y;
+            z[v][4 * r + 2] = w.z;
+            z[v][4 * r + 3] = w.w;
+        }
+    }
+}
+__device__ __forceinline__ void store_groups(const float (&z)[NV][16], float *P, int t) {
+    const int u = opaque(t);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        const Lane l(u + VS * v);
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            *reinterpret_cast<float4 *>(P + group_addr(l, r)) =
+                make_float4(z[v][4 * r], z[v][4 * r + 1], z[v][4 * r + 2], z[v][4 * r + 3]);
+    }
+}
+// Pass C's side: element j of lane (k1, k2, e) at rot_c.
+__device__ __forceinline__ void store_rot_c(const float (&z)[NV][16], float *P, int t) {
+    const int u = opaque(t);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        const Map m = rot_c(Lane(u + VS * v));
+#pragma unroll
+        for (int j = 0; j < 16; ++j) *m.at(P, j) = z[v][j];
+    }
+}
+__device__ __forceinline__ void load_rot_c(float (&z)[NV][16], float *P, int t) {
+    const int u = opaque(t);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        const Map m = rot_c(Lane(u + VS * v));
+#pragma unroll
+        for (int j = 0; j < 16; ++j) z[v][j] = *m.at(P, j);
+    }
+}
+
+// Forward transform.  In: virtual lane L holds z[1024 a + L] in zr/zi[v][a].
+// Out: virtual lane L = 64 k1 + 4 k2 + q holds
+// Z[k1 + 16 k2 + 256 (4 q + r) + 4096 k4] in zr/zi[v][4 r + k4].  The caller
+// has passed a barrier since the last read of P; ends after the last read.
+// (Each pass derives its lane coordinates afresh from the thread index.)
+__device__ __forceinline__ void fft16k_forward(float (&zr)[NV][16], float (&zi)[NV][16], float *P, const float2 *tw,
+                                               int t) {
+    {  // pass A
+        const int u = opaque(t);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            dft16<-1>(zr[v], zi[v]);
+            twiddle_row_lean<false>(zr[v], zi[v], tw + TWA_OFF + 16 * (u + VS * v));
+        }
+    }
+    exchange(zr, zi, P, t, map_a, map_b);
+    {  // pass B
+        const int u = opaque(t);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            dft16<-1>(zr[v], zi[v]);
+            twiddle_row_lean<false>(zr[v], zi[v], tw + TWB_OFF + 16 * ((u + VS * v) & 63));
+        }
+    }
+    __syncthreads();
+    exchange(zr, zi, P, t, rot_w, rot_c);
+    {  // pass C
+        const int u = opaque(t);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            dft16<-1>(zr[v], zi[v]);
+            twiddle_row_lean<false>(zr[v], zi[v], tw + TWC_OFF + 16 * (u & 3));
+        }
+    }
+    // exchange C -> D, pass D reading (k3 = 4 q + r, e = 0..3) as 16-byte groups
+    __syncthreads();
+    store_rot_c(zr, P, t);
+    __syncthreads();
+    load_groups(zr, P, t);
+    __syncthreads();
+    store_rot_c(zi, P, t);
+    __syncthreads();
+    load_groups(zi, P, t);
+    // pass D
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            dft4<-1>(zr[v][4 * r], zi[v][4 * r], zr[v][4 * r + 1], zi[v][4 * r + 1], zr[v][4 * r + 2],
+                     zi[v][4 * r + 2], zr[v][4 * r + 3], zi[v][4 * r + 3]);
 }
 
 // Inverse of fft16k_forward without the 1/16384 factor: from its output
 // layout back to its input layout.  Begins with a barrier before its first
-// LDS write.
-__device__ __forceinline__ void fft16k_inverse(float (&zr)[16], float (&zi)[16], float *Lr, float *Li,
-                                               const float2 *tw, int L) {
-    const int k1 = L >> 6, c = L & 63, d = c >> 2, e = c & 3;
-    const int k2 = (L >> 2) & 15, q = L & 3;
-    const int rowd = 1024 * k1 + 64 * k2;
+// LDS write; ends after its last read.
+__device__ __forceinline__ void fft16k_inverse(float (&zr)[NV][16], float (&zi)[NV][16], float *P, const float2 *tw,
+                                               int t) {
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
-        dft4<1>(zr[4 * r], zi[4 * r], zr[4 * r + 1], zi[4 * r + 1], zr[4 * r + 2], zi[4 * r + 2], zr[4 * r + 3],
-                zi[4 * r + 3]);
+    for (int v = 0; v < NV; ++v)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            dft4<1>(zr[v][4 * r], zi[v][4 * r], zr[v][4 * r + 1], zi[v][4 * r + 1], zr[v][4 * r + 2],
+                    zi[v][4 * r + 2], zr[v][4 * r + 3], zi[v][4 * r + 3]);
+    // exchange D -> C: 16-byte group writes, reads in pass C's order
     __syncthreads();
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const int ad = rowd + 4 * ((4 * q + r + k2) & 15);
-        *reinterpret_cast<float4 *>(Lr + ad) = make_float4(zr[4 * r], zr[4 * r + 1], zr[4 * r + 2], zr[4 * r + 3]);
-        *reinterpret_cast<float4 *>(Li + ad) = make_float4(zi[4 * r], zi[4 * r + 1], zi[4 * r + 2], zi[4 * r + 3]);
-    }
+    store_groups(zr, P, t);
     __syncthreads();
-    // pass C inverse: lane (k1, k2, e) over k3
-    const int ec = L & 3, rc = rowd + 4 * k2 + ec;
-#pragma unroll
-    for (int j = 0; j < 16; ++j) {
-        const int ad = (j >= 16 - k2 ? rc - 64 : rc) + 4 * j;
-        zr[j] = Lr[ad];
-        zi[j] = Li[ad];
-    }
-    twiddle_row_lean<true>(zr, zi, tw + TWC_OFF + 16 * ec);
-    dft16<1>(zr, zi);
+    load_rot_c(zr, P, t);
     __syncthreads();
-#pragma unroll
-    for (int j = 0; j < 16; ++j) {  // j = d
-        const int ad = (j >= 16 - k2 ? rc - 64 : rc) + 4 * j;
-        Lr[ad] = zr[j];
-        Li[ad] = zi[j];
-    }
+    store_groups(zi, P, t);
     __syncthreads();
-    // pass B inverse: lane (k1, c) over k2
-    {
-        const int w0 = 1024 * k1 + 4 * d + e;
+    load_rot_c(zi, P, t);
+    {  // pass C inverse: lane (k1, k2, e) over k3
+        const int u = opaque(t);
 #pragma unroll
-        for (int j = 0; j < 16; ++j) {
-            const int ad = (j >= 16 - d ? w0 - 64 : w0) + 68 * j;
-            zr[j] = Lr[ad];
-            zi[j] = Li[ad];
+        for (int v = 0; v < NV; ++v) {
+            twiddle_row_lean<true>(zr[v], zi[v], tw + TWC_OFF + 16 * (u & 3));
+            dft16<1>(zr[v], zi[v]);
         }
     }
-    twiddle_row_lean<true>(zr, zi, tw + TWB_OFF + 16 * c);
-    dft16<1>(zr, zi);
     __syncthreads();
+    exchange(zr, zi, P, t, rot_c, rot_w);
+    {  // pass B inverse: lane (k1, c) over k2
+        const int u = opaque(t);
 #pragma unroll
-    for (int b = 0; b < 16; ++b) {
-        Lr[1024 * k1 + 64 * b + c] = zr[b];
-        Li[1024 * k1 + 64 * b + c] = zi[b];
+        for (int v = 0; v < NV; ++v) {
+            twiddle_row_lean<true>(zr[v], zi[v], tw + TWB_OFF + 16 * ((u + VS * v) & 63));
+            dft16<1>(zr[v], zi[v]);
+        }
     }
     __syncthreads();
-    // pass A inverse: lane t over k1
+    exchange(zr, zi, P, t, map_b, map_a);
+    {  // pass A inverse: lane L over k1
+        const int u = opaque(t);
 #pragma unroll
-    for (int j = 0; j < 16; ++j) {
-        zr[j] = Lr[1024 * j + L];
-        zi[j] = Li[1024 * j + L];
+        for (int v = 0; v < NV; ++v) {
+            twiddle_row_lean<true>(zr[v], zi[v], tw + TWA_OFF + 16 * (u + VS * v));
+            dft16<1>(zr[v], zi[v]);
+        }
     }
-    twiddle_row_lean<true>(zr, zi, tw + TWA_OFF + 16 * L);
-    dft16<1>(zr, zi);
 }
 
 struct F16Args {
@@ -230,9 +333,38 @@ __device__ __forceinline__ int64_t xcd_block(int64_t i, int64_t nb) {
     return x * per + (x < rem ? x : rem) + (i >> 3);
 }
 
-__global__ __launch_bounds__(WGB, 1) void fir16k_kernel(F16Args a) {
-    __shared__ float lds[2 * NB];
-    float *Lr = lds, *Li = imag_plane(lds);
+// Stores rows Q0 .. Q0 + 7 of the block (samples n0 + 1024 q + L) to ya and,
+// when yb is set, yb, up to N.
+template <int Q0>
+__device__ __forceinline__ void store_rows(const float (&zr)[NV][16], const float (&zi)[NV][16], float *ya,
+                                           float *yb, int64_t n0, int64_t N, int t) {
+    if (n0 + HOPB <= N) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+#pragma unroll
+            for (int q = 0; q < 8; ++q) ya[n0 + 1024 * q + VS * v + t] = zr[v][Q0 + q];
+        if (yb) {
+#pragma unroll
+            for (int v = 0; v < NV; ++v)
+#pragma unroll
+                for (int q = 0; q < 8; ++q) yb[n0 + 1024 * q + VS * v + t] = zi[v][Q0 + q];
+        }
+        return;
+    }
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int64_t n = n0 + 1024 * q + VS * v + t;
+            if (n < N) {
+                ya[n] = zr[v][Q0 + q];
+                if (yb) yb[n] = zi[v][Q0 + q];
+            }
+        }
+}
+
+__global__ __launch_bounds__(WGB, 8 / NV) void fir16k_kernel(F16Args a) {
+    __shared__ __align__(16) float P[NB];
     const int t = threadIdx.x;
     const int64_t lb = xcd_block(blockIdx.x, a.nblocks);
     const int64_t pair = lb / a.ntiles, tile = lb - pair * a.ntiles;
@@ -241,66 +373,66 @@ __global__ __launch_bounds__(WGB, 1) void fir16k_kernel(F16Args a) {
     const float *xa = a.x + ca * a.ldx, *xb = has_b ? a.x + cb * a.ldx : nullptr;
     const int64_t n0 = tile * HOPB;
     const int64_t base = a.correlate ? n0 : n0 - HOPB;
-    float zr[16], zi[16];
+    // virtual lane L = t + 512 v holds z[1024 q + L] in [v][q]
+    float zr[NV][16], zi[NV][16];
     if (base >= 0 && base + NB <= a.N) {
         const float *pa = xa + base + t;
 #pragma unroll
-        for (int q = 0; q < 16; ++q) zr[q] = pa[1024 * q];
+        for (int v = 0; v < NV; ++v)
+#pragma unroll
+            for (int q = 0; q < 16; ++q) zr[v][q] = pa[1024 * q + VS * v];
         if (has_b) {
             const float *pb = xb + base + t;
 #pragma unroll
-            for (int q = 0; q < 16; ++q) zi[q] = pb[1024 * q];
+            for (int v = 0; v < NV; ++v)
+#pragma unroll
+                for (int q = 0; q < 16; ++q) zi[v][q] = pb[1024 * q + VS * v];
         } else {
 #pragma unroll
-            for (int q = 0; q < 16; ++q) zi[q] = 0.f;
+            for (int v = 0; v < NV; ++v)
+#pragma unroll
+                for (int q = 0; q < 16; ++q) zi[v][q] = 0.f;
         }
     } else {
         const float *ha = a.hist ? a.hist + ca * a.hlen : nullptr;
         const float *hb = (a.hist && has_b) ? a.hist + cb * a.hlen : nullptr;
 #pragma unroll
-        for (int q = 0; q < 16; ++q) {
-            const int64_t n = base + 1024 * q + t;
-            const bool in = n >= 0 && n < a.N;
-            const bool inh = n < 0 && n >= -a.hlen;
-            zr[q] = in ? xa[n] : ((inh && ha) ? ha[a.hlen + n] : 0.f);
-            zi[q] = (in && has_b) ? xb[n] : ((inh && hb) ? hb[a.hlen + n] : 0.f);
-        }
+        for (int v = 0; v < NV; ++v)
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                const int64_t n = base + 1024 * q + VS * v + t;
+                const bool in = n >= 0 && n < a.N;
+                const bool inh = n < 0 && n >= -a.hlen;
+                zr[v][q] = in ? xa[n] : ((inh && ha) ? ha[a.hlen + n] : 0.f);
+                zi[v][q] = (in && has_b) ? xb[n] : ((inh && hb) ? hb[a.hlen + n] : 0.f);
+            }
     }
-    fft16k_forward(zr, zi, Lr, Li, a.tw, t);
+    fft16k_forward(zr, zi, P, a.tw, t);
     {
         const float sg = a.correlate ? -1.f : 1.f;
-        const float4 *h4 = reinterpret_cast<const float4 *>(a.hs + 16 * t);
 #pragma unroll
-        for (int g4 = 0; g4 < 4; ++g4) {
-            const float4 p = h4[2 * g4], r = h4[2 * g4 + 1];
-            const float2 w[4] = {make_float2(p.x, sg * p.y), make_float2(p.z, sg * p.w), make_float2(r.x, sg * r.y),
-                                 make_float2(r.z, sg * r.w)};
+        for (int v = 0; v < NV; ++v) {
+            const float4 *h4 = reinterpret_cast<const float4 *>(a.hs + 16 * (t + VS * v));
 #pragma unroll
-            for (int u = 0; u < 4; ++u) cmul_tw<false>(zr[4 * g4 + u], zi[4 * g4 + u], w[u]);
-            asm volatile("" ::: "memory");  // at most four bins' spectra in registers at a time
-        }
-    }
-    fft16k_inverse(zr, zi, Lr, Li, a.tw, t);
-    // rows 8..15 of the block (convolution) or 0..7 (correlation) are the tile
-    const int q0 = a.correlate ? 0 : 8;
-    float *ya = a.y + ca * a.ldy, *yb = has_b ? a.y + cb * a.ldy : nullptr;
-    if (n0 + HOPB <= a.N) {
+            for (int g4 = 0; g4 < 4; ++g4) {
+                const float4 p = h4[2 * g4], r = h4[2 * g4 + 1];
+                const float2 w[4] = {make_float2(p.x, sg * p.y), make_float2(p.z, sg * p.w),
+                                     make_float2(r.x, sg * r.y), make_float2(r.z, sg * r.w)};
 #pragma unroll
-        for (int q = 0; q < 8; ++q) ya[n0 + 1024 * q + t] = zr[q0 + q];
-        if (has_b) {
-#pragma unroll
-            for (int q = 0; q < 8; ++q) yb[n0 + 1024 * q + t] = zi[q0 + q];
-        }
-    } else {
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            const int64_t n = n0 + 1024 * q + t;
-            if (n < a.N) {
-                ya[n] = zr[q0 + q];
-                if (has_b) yb[n] = zi[q0 + q];
+                for (int u = 0; u < 4; ++u) cmul_tw<false>(zr[v][4 * g4 + u], zi[v][4 * g4 + u], w[u]);
+                asm volatile("" ::: "memory");  // at most four bins' spectra in registers at a time
             }
         }
     }
+    fft16k_inverse(zr, zi, P, a.tw, t);
+    // rows 8..15 of the block (convolution) or 0..7 (correlation) are the tile
+    // (two paths with constant row indices: a run-time index into the data
+    // arrays would move them to scratch memory)
+    float *ya = a.y + ca * a.ldy, *yb = has_b ? a.y + cb * a.ldy : nullptr;
+    if (a.correlate)
+        store_rows<0>(zr, zi, ya, yb, n0, a.N, t);
+    else
+        store_rows<8>(zr, zi, ya, yb, n0, a.N, t);
 }
 
 // Twiddle tables in fp32 from sincospi of exact arguments (2 m / 16384):
@@ -321,19 +453,23 @@ __global__ void fft16k_twiddle_kernel(float2 *tw) {
 // D's lane order, times 1/16384 (exact).  One workgroup.
 __global__ __launch_bounds__(WGB, 1) void fft16k_spectrum_kernel(const float *h, int32_t M, const float2 *tw,
                                                                  float2 *hs) {
-    __shared__ float lds[2 * NB];
+    __shared__ __align__(16) float P[NB];
     const int t = threadIdx.x;
-    float zr[16], zi[16];
+    float zr[NV][16], zi[NV][16];
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
-        const int n = 1024 * q + t;
-        zr[q] = n < M ? h[n] : 0.f;
-        zi[q] = 0.f;
-    }
-    fft16k_forward(zr, zi, lds, imag_plane(lds), tw, t);
+    for (int v = 0; v < NV; ++v)
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int n = 1024 * q + VS * v + t;
+            zr[v][q] = n < M ? h[n] : 0.f;
+            zi[v][q] = 0.f;
+        }
+    fft16k_forward(zr, zi, P, tw, t);
     const float sc = 1.0f / (float)NB;
 #pragma unroll
-    for (int j = 0; j < 16; ++j) hs[16 * t + j] = make_float2(zr[j] * sc, zi[j] * sc);
+    for (int v = 0; v < NV; ++v)
+#pragma unroll
+        for (int j = 0; j < 16; ++j) hs[16 * (t + VS * v) + j] = make_float2(zr[v][j] * sc, zi[v][j] * sc);
 }
 
 }  // namespace
