@@ -127,6 +127,7 @@ __device__ __forceinline__ float fir_input(const KArgs &a, const float *xc, int6
 // frame F0 + 32 t + r is 32 t + r + q1 - 1 - q.
 constexpr int TZ_QC = 64;
 constexpr int TZ_PF = 4;  // tap-fragment loads in flight
+constexpr int TZ_SU = 2;  // operand staging loads in flight per thread
 constexpr int TZ_ROWS = T / TP + TZ_QC - 1;
 static_assert(GROUPS * TZ_ROWS * TROW * 2 <= GROUPS * STG_FLOATS * 4, "Toeplitz operands must fit in the staging");
 // MCL: the output goes to the matrix-core cascade's chunk layout (chunk k
@@ -157,7 +158,34 @@ __device__ void tz_tile(const KArgs &a, float *lds, int64_t pair, int64_t n0, in
             const int64_t ch = 2 * pair + g;
             const float *xc = a.x + ch * a.ldx;
             Tt *ag = ast + g * TZ_ROWS * TROW;
-            for (int e = tid; e < nrows * (TP / 4); e += WG) {
+            const int total = nrows * (TP / 4);
+            const int64_t nlo = fbase * TP, nhi = (fbase + nrows) * TP;
+            if (ch < a.C && a.vec && nlo >= 0 && nhi <= a.N) {
+                // inside the signal: TZ_SU four-sample loads in flight per thread
+                for (int e0 = tid; e0 < total; e0 += TZ_SU * WG) {
+                    float4 t[TZ_SU];
+#pragma unroll
+                    for (int k = 0; k < TZ_SU; ++k) {
+                        const int e = e0 + k * WG;
+                        t[k] = e < total ? *reinterpret_cast<const float4 *>(xc + nlo + 4 * e)
+                                         : make_float4(0.f, 0.f, 0.f, 0.f);
+                    }
+#pragma unroll
+                    for (int k = 0; k < TZ_SU; ++k) {
+                        const int e = e0 + k * WG;
+                        if (e < total) {
+                            T4 t4;
+                            t4[0] = (Tt)t[k].x;
+                            t4[1] = (Tt)t[k].y;
+                            t4[2] = (Tt)t[k].z;
+                            t4[3] = (Tt)t[k].w;
+                            *reinterpret_cast<T4 *>(&ag[(e >> 3) * TROW + 4 * (e & 7)]) = t4;
+                        }
+                    }
+                }
+                continue;
+            }
+            for (int e = tid; e < total; e += WG) {
                 const int row = e >> 3, c4 = e & 7;  // TP / 4 = 8 four-sample pieces a row
                 const int64_t n = (fbase + row) * TP + 4 * c4;
                 float v4[4];

@@ -23,6 +23,8 @@
 // each) and reuses each B fragment for all four.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "tfx_device.h"
 
 namespace tfx {
@@ -31,7 +33,7 @@ constexpr int TFB = 4;                      // accumulator tiles per wave
 constexpr int TWAVES = 4;                   // waves per workgroup
 constexpr int TFRAMES = TFB * 32 * TWAVES;  // frames per workgroup tile (512)
 constexpr int TQC = 192;                    // lags per LDS stage
-constexpr int TROWS = TFRAMES + TQC;        // staged frames per stage
+constexpr int TZ_SU = 8;                    // staging loads in flight per thread
 
 // B operand table: step s = 2 q + hh, lane l, element v holds
 // h[32 q + (l % 32) - 16 hh - 8 (l / 32) - v]  (0 outside [0, M)),
@@ -72,7 +74,14 @@ __global__ __launch_bounds__(64 * TWAVES) void toeplitz_kernel(TzArgs a) {
     typedef typename O::V V;
     typedef T T4 __attribute__((ext_vector_type(4)));
     constexpr int NA = MODE == TZ_BF16X3 ? 2 : 1;  // staged A parts (hi, lo)
-    __shared__ __align__(16) T lds[NA][TROWS * TROW];
+    // [NA][rows][TROW]: one operand part in dynamic LDS with rows = TFRAMES +
+    // min(Q, TQC) - 1 (short filters stage fewer rows, so more workgroups fit
+    // a CU; at most 56 KB); the split mode's two parts statically, for TQC lags
+    constexpr int NSTAT = MODE == TZ_BF16X3 ? NA * (TFRAMES + TQC - 1) * TROW : 8;
+    __shared__ __align__(16) T lds_stat[NSTAT];
+    extern __shared__ __align__(16) unsigned char tz_dyn[];
+    T *lds_base = MODE == TZ_BF16X3 ? lds_stat : reinterpret_cast<T *>(tz_dyn);
+    const int rows_max = MODE == TZ_BF16X3 ? TFRAMES + TQC - 1 : TFRAMES + min(a.Q, TQC) - 1;
 
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int64_t ch = blockIdx.x / a.nft;
@@ -94,7 +103,36 @@ __global__ __launch_bounds__(64 * TWAVES) void toeplitz_kernel(TzArgs a) {
         const int64_t fbase = b0 - (q1 - 1);
         const int nrows = TFRAMES + (q1 - q0) - 1;
         __syncthreads();
-        for (int e = tid; e < nrows * (TP / 4); e += 64 * TWAVES) {
+        const int total = nrows * (TP / 4);
+        const int64_t nlo = fbase * TP, nhi = (fbase + nrows) * TP;
+        if (a.vec && nlo >= 0 && nhi <= a.N) {
+            // inside the signal: TZ_SU four-sample loads in flight per thread
+            for (int e0 = tid; e0 < total; e0 += TZ_SU * 64 * TWAVES) {
+                float4 t[TZ_SU];
+#pragma unroll
+                for (int k = 0; k < TZ_SU; ++k) {
+                    const int e = e0 + k * 64 * TWAVES;
+                    t[k] = e < total ? *reinterpret_cast<const float4 *>(xc + nlo + 4 * e) : make_float4(0.f, 0.f, 0.f, 0.f);
+                }
+#pragma unroll
+                for (int k = 0; k < TZ_SU; ++k) {
+                    const int e = e0 + k * 64 * TWAVES;
+                    if (e < total) {
+                        const int row = e / (TP / 4), c4 = e % (TP / 4);
+                        const float v4[4] = {t[k].x, t[k].y, t[k].z, t[k].w};
+                        T4 hi4, lo4;
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) {
+                            hi4[u] = (T)v4[u];
+                            lo4[u] = (T)(v4[u] - (float)hi4[u]);
+                        }
+                        *reinterpret_cast<T4 *>(&lds_base[row * TROW + 4 * c4]) = hi4;
+                        if (MODE == TZ_BF16X3) *reinterpret_cast<T4 *>(&lds_base[(NA - 1) * rows_max * TROW + row * TROW + 4 * c4]) = lo4;
+                    }
+                }
+            }
+        } else {
+        for (int e = tid; e < total; e += 64 * TWAVES) {
             const int row = e / (TP / 4), c4 = e % (TP / 4);
             const int64_t n = (fbase + row) * TP + 4 * c4;
             float v4[4];
@@ -118,8 +156,9 @@ __global__ __launch_bounds__(64 * TWAVES) void toeplitz_kernel(TzArgs a) {
                 hi4[u] = (T)v4[u];
                 lo4[u] = (T)(v4[u] - (float)hi4[u]);
             }
-            *reinterpret_cast<T4 *>(&lds[0][row * TROW + 4 * c4]) = hi4;
-            if (MODE == TZ_BF16X3) *reinterpret_cast<T4 *>(&lds[NA - 1][row * TROW + 4 * c4]) = lo4;
+            *reinterpret_cast<T4 *>(&lds_base[row * TROW + 4 * c4]) = hi4;
+            if (MODE == TZ_BF16X3) *reinterpret_cast<T4 *>(&lds_base[(NA - 1) * rows_max * TROW + row * TROW + 4 * c4]) = lo4;
+        }
         }
         __syncthreads();
         for (int q = q0; q < q1; ++q) {
@@ -134,10 +173,10 @@ __global__ __launch_bounds__(64 * TWAVES) void toeplitz_kernel(TzArgs a) {
                     // frame b = b0 + 32 (w * TFB + j) + r32; staged row b - q - fbase
                     const int row = 32 * (w * TFB + j) + r32 + (q1 - 1 - q);
                     const int off = row * TROW + 16 * hh + 8 * kh;
-                    const V ah = *reinterpret_cast<const V *>(&lds[0][off]);
+                    const V ah = *reinterpret_cast<const V *>(&lds_base[off]);
                     acc[j] = O::mma(ah, bh, acc[j]);
                     if (MODE == TZ_BF16X3) {
-                        const V al = *reinterpret_cast<const V *>(&lds[NA - 1][off]);
+                        const V al = *reinterpret_cast<const V *>(&lds_base[(NA - 1) * rows_max * TROW + off]);
                         acc[j] = O::mma(ah, bl, acc[j]);
                         acc[j] = O::mma(al, bh, acc[j]);
                     }
@@ -211,10 +250,11 @@ hipError_t launch_toeplitz(const float *x, float *y, int64_t C, int64_t N, int64
     a.hist = M > 1 ? hist : nullptr;
     a.ldh = M - 1;
     const dim3 grid((unsigned)(C * a.nft)), block(64 * TWAVES);
+    const size_t dyn = cmp == TZ_BF16X3 ? 0 : (TFRAMES + (size_t)std::min(a.Q, TQC) - 1) * TROW * 2;  // 2-byte operands
     switch (cmp) {
-        case TZ_BF16: hipLaunchKernelGGL(toeplitz_kernel<TZ_BF16>, grid, block, 0, st, a); break;
-        case TZ_F16: hipLaunchKernelGGL(toeplitz_kernel<TZ_F16>, grid, block, 0, st, a); break;
-        default: hipLaunchKernelGGL(toeplitz_kernel<TZ_BF16X3>, grid, block, 0, st, a); break;
+        case TZ_BF16: hipLaunchKernelGGL(toeplitz_kernel<TZ_BF16>, grid, block, dyn, st, a); break;
+        case TZ_F16: hipLaunchKernelGGL(toeplitz_kernel<TZ_F16>, grid, block, dyn, st, a); break;
+        default: hipLaunchKernelGGL(toeplitz_kernel<TZ_BF16X3>, grid, block, dyn, st, a); break;
     }
     return hipGetLastError();
 }
