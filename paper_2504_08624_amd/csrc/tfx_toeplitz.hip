@@ -34,6 +34,9 @@ constexpr int TWAVES = 4;                   // waves per workgroup
 constexpr int TFRAMES = TFB * 32 * TWAVES;  // frames per workgroup tile (512)
 constexpr int TQC = 192;                    // lags per LDS stage
 constexpr int TZ_SU = 8;                    // staging loads in flight per thread
+// Filters with more than TZ_Q3 lags stage too many rows for three
+// workgroups per CU, and take the deeper tap-fragment prefetch.
+constexpr int TZ_Q3 = 171;
 
 // B operand table: step s = 2 q + hh, lane l, element v holds
 // h[32 q + (l % 32) - 16 hh - 8 (l / 32) - v]  (0 outside [0, M)),
@@ -67,7 +70,9 @@ struct TzArgs {
 };
 
 // One workgroup: 512 consecutive frames (16384 outputs) of one channel.
-template <int MODE>
+// PF: tap-fragment steps loaded ahead (more hides more L2 latency but costs
+// registers: 8 leaves two waves per SIMD, 4 three).
+template <int MODE, int PF>
 __global__ __launch_bounds__(64 * TWAVES) void toeplitz_kernel(TzArgs a) {
     typedef Op<MODE> O;
     typedef typename O::T T;
@@ -161,24 +166,40 @@ __global__ __launch_bounds__(64 * TWAVES) void toeplitz_kernel(TzArgs a) {
         }
         }
         __syncthreads();
-        for (int q = q0; q < q1; ++q) {
+        // steps s = 2 q + hh; the tap fragments are loaded PF steps ahead
+        // (a ring of PF fragments: slot i holds step sb + i)
+        const int s0 = 2 * q0, s1 = 2 * q1;
+        V bq[PF], bl[PF];
 #pragma unroll
-            for (int hh = 0; hh < 2; ++hh) {
-                const int64_t s = 2 * (int64_t)q + hh;
-                const V bh = bhi[s * 64 + lane];
-                V bl;
-                if (MODE == TZ_BF16X3) bl = blo[s * 64 + lane];
+        for (int i = 0; i < PF; ++i) {
+            if (s0 + i < s1) {
+                bq[i] = bhi[(int64_t)(s0 + i) * 64 + lane];
+                if (MODE == TZ_BF16X3) bl[i] = blo[(int64_t)(s0 + i) * 64 + lane];
+            }
+        }
+        for (int sb = s0; sb < s1; sb += PF) {
 #pragma unroll
-                for (int j = 0; j < TFB; ++j) {
-                    // frame b = b0 + 32 (w * TFB + j) + r32; staged row b - q - fbase
-                    const int row = 32 * (w * TFB + j) + r32 + (q1 - 1 - q);
-                    const int off = row * TROW + 16 * hh + 8 * kh;
-                    const V ah = *reinterpret_cast<const V *>(&lds_base[off]);
-                    acc[j] = O::mma(ah, bh, acc[j]);
-                    if (MODE == TZ_BF16X3) {
-                        const V al = *reinterpret_cast<const V *>(&lds_base[(NA - 1) * rows_max * TROW + off]);
-                        acc[j] = O::mma(ah, bl, acc[j]);
-                        acc[j] = O::mma(al, bh, acc[j]);
+            for (int i = 0; i < PF; ++i) {
+                const int st = sb + i;
+                if (st < s1) {
+                    const int q = st >> 1, hh = st & 1;
+#pragma unroll
+                    for (int j = 0; j < TFB; ++j) {
+                        // frame b = b0 + 32 (w * TFB + j) + r32; staged row b - q - fbase
+                        const int row = 32 * (w * TFB + j) + r32 + (q1 - 1 - q);
+                        const int off = row * TROW + 16 * hh + 8 * kh;
+                        const V ah = *reinterpret_cast<const V *>(&lds_base[off]);
+                        acc[j] = O::mma(ah, bq[i], acc[j]);
+                        if (MODE == TZ_BF16X3) {
+                            const V al = *reinterpret_cast<const V *>(&lds_base[(NA - 1) * rows_max * TROW + off]);
+                            acc[j] = O::mma(ah, bl[i], acc[j]);
+                            acc[j] = O::mma(al, bq[i], acc[j]);
+                        }
+                    }
+                    // the fragment's last use is issued: refill its slot in place
+                    if (st + PF < s1) {
+                        bq[i] = bhi[(int64_t)(st + PF) * 64 + lane];
+                        if (MODE == TZ_BF16X3) bl[i] = blo[(int64_t)(st + PF) * 64 + lane];
                     }
                 }
             }
@@ -251,10 +272,17 @@ hipError_t launch_toeplitz(const float *x, float *y, int64_t C, int64_t N, int64
     a.ldh = M - 1;
     const dim3 grid((unsigned)(C * a.nft)), block(64 * TWAVES);
     const size_t dyn = cmp == TZ_BF16X3 ? 0 : (TFRAMES + (size_t)std::min(a.Q, TQC) - 1) * TROW * 2;  // 2-byte operands
+    const bool deep = a.Q > TZ_Q3;
     switch (cmp) {
-        case TZ_BF16: hipLaunchKernelGGL(toeplitz_kernel<TZ_BF16>, grid, block, dyn, st, a); break;
-        case TZ_F16: hipLaunchKernelGGL(toeplitz_kernel<TZ_F16>, grid, block, dyn, st, a); break;
-        default: hipLaunchKernelGGL(toeplitz_kernel<TZ_BF16X3>, grid, block, dyn, st, a); break;
+        case TZ_BF16:
+            if (deep) hipLaunchKernelGGL((toeplitz_kernel<TZ_BF16, 8>), grid, block, dyn, st, a);
+            else hipLaunchKernelGGL((toeplitz_kernel<TZ_BF16, 4>), grid, block, dyn, st, a);
+            break;
+        case TZ_F16:
+            if (deep) hipLaunchKernelGGL((toeplitz_kernel<TZ_F16, 8>), grid, block, dyn, st, a);
+            else hipLaunchKernelGGL((toeplitz_kernel<TZ_F16, 4>), grid, block, dyn, st, a);
+            break;
+        default: hipLaunchKernelGGL((toeplitz_kernel<TZ_BF16X3, 4>), grid, block, dyn, st, a); break;
     }
     return hipGetLastError();
 }
