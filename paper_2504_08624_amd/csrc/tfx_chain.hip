@@ -166,9 +166,9 @@ __device__ void tz_tile(const KArgs &a, float *lds, int64_t pair, int64_t n0, in
                     float4 t[TZ_SU];
 #pragma unroll
                     for (int k = 0; k < TZ_SU; ++k) {
-                        const int e = e0 + k * WG;
-                        t[k] = e < total ? *reinterpret_cast<const float4 *>(xc + nlo + 4 * e)
-                                         : make_float4(0.f, 0.f, 0.f, 0.f);
+                        // clamped, not skipped: loads inside a branch are each waited for
+                        const int e = min(e0 + k * WG, total - 1);
+                        t[k] = *reinterpret_cast<const float4 *>(xc + nlo + 4 * e);
                     }
 #pragma unroll
                     for (int k = 0; k < TZ_SU; ++k) {

@@ -116,8 +116,9 @@ __global__ __launch_bounds__(64 * TWAVES) void toeplitz_kernel(TzArgs a) {
                 float4 t[TZ_SU];
 #pragma unroll
                 for (int k = 0; k < TZ_SU; ++k) {
-                    const int e = e0 + k * 64 * TWAVES;
-                    t[k] = e < total ? *reinterpret_cast<const float4 *>(xc + nlo + 4 * e) : make_float4(0.f, 0.f, 0.f, 0.f);
+                    // clamped, not skipped: loads inside a branch are each waited for
+                    const int e = min(e0 + k * 64 * TWAVES, total - 1);
+                    t[k] = *reinterpret_cast<const float4 *>(xc + nlo + 4 * e);
                 }
 #pragma unroll
                 for (int k = 0; k < TZ_SU; ++k) {
@@ -167,40 +168,71 @@ __global__ __launch_bounds__(64 * TWAVES) void toeplitz_kernel(TzArgs a) {
         }
         __syncthreads();
         // steps s = 2 q + hh; the tap fragments are loaded PF steps ahead
-        // (a ring of PF fragments: slot i holds step sb + i)
+        // (a ring of PF fragments: slot i holds step sb + i).  Every load index
+        // is clamped to the last step instead of skipped, so the main loop has
+        // no branch (loads inside a branch are each waited for at its end).
         const int s0 = 2 * q0, s1 = 2 * q1;
+        // signal fragment of step st for accumulator tile j (part 0: hi, 1: lo)
+        auto afrag = [&](int st, int j, int part) -> V {
+            const int q = st >> 1, hh = st & 1;
+            // frame b = b0 + 32 (w * TFB + j) + r32; staged row b - q - fbase
+            const int row = 32 * (w * TFB + j) + r32 + (q1 - 1 - q);
+            return *reinterpret_cast<const V *>(&lds_base[part * rows_max * TROW + row * TROW + 16 * hh + 8 * kh]);
+        };
         V bq[PF], bl[PF];
 #pragma unroll
         for (int i = 0; i < PF; ++i) {
-            if (s0 + i < s1) {
-                bq[i] = bhi[(int64_t)(s0 + i) * 64 + lane];
-                if (MODE == TZ_BF16X3) bl[i] = blo[(int64_t)(s0 + i) * 64 + lane];
+            const int64_t si = min(s0 + i, s1 - 1);
+            bq[i] = bhi[si * 64 + lane];
+            if (MODE == TZ_BF16X3) bl[i] = blo[si * 64 + lane];
+        }
+        int sb = s0;
+        if (MODE != TZ_BF16X3) {
+            // full groups of PF steps; each step loads the next step's signal
+            // fragments before it issues its own products
+            V acur[TFB];
+#pragma unroll
+            for (int j = 0; j < TFB; ++j) acur[j] = afrag(s0, j, 0);
+            for (; sb + PF <= s1; sb += PF) {
+#pragma unroll
+                for (int i = 0; i < PF; ++i) {
+                    const int st = sb + i, sn = min(st + 1, s1 - 1);
+                    V anext[TFB];
+#pragma unroll
+                    for (int j = 0; j < TFB; ++j) anext[j] = afrag(sn, j, 0);
+#pragma unroll
+                    for (int j = 0; j < TFB; ++j) acc[j] = O::mma(acur[j], bq[i], acc[j]);
+                    bq[i] = bhi[(int64_t)min(st + PF, s1 - 1) * 64 + lane];
+#pragma unroll
+                    for (int j = 0; j < TFB; ++j) acur[j] = anext[j];
+                    // keep that order in the schedule: the next step's LDS
+                    // reads, this step's products, then the tap refill
+                    __builtin_amdgcn_sched_group_barrier(0x100, TFB, 0);
+                    __builtin_amdgcn_sched_group_barrier(0x008, TFB, 0);
+                    __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);
+                }
             }
         }
-        for (int sb = s0; sb < s1; sb += PF) {
+        // the remaining steps (all of them in split mode)
+        for (; sb < s1; sb += PF) {
 #pragma unroll
             for (int i = 0; i < PF; ++i) {
                 const int st = sb + i;
                 if (st < s1) {
-                    const int q = st >> 1, hh = st & 1;
 #pragma unroll
                     for (int j = 0; j < TFB; ++j) {
-                        // frame b = b0 + 32 (w * TFB + j) + r32; staged row b - q - fbase
-                        const int row = 32 * (w * TFB + j) + r32 + (q1 - 1 - q);
-                        const int off = row * TROW + 16 * hh + 8 * kh;
-                        const V ah = *reinterpret_cast<const V *>(&lds_base[off]);
+                        const V ah = afrag(st, j, 0);
                         acc[j] = O::mma(ah, bq[i], acc[j]);
                         if (MODE == TZ_BF16X3) {
-                            const V al = *reinterpret_cast<const V *>(&lds_base[(NA - 1) * rows_max * TROW + off]);
+                            const V al = afrag(st, j, NA - 1);
                             acc[j] = O::mma(ah, bl[i], acc[j]);
                             acc[j] = O::mma(al, bq[i], acc[j]);
                         }
                     }
                     // the fragment's last use is issued: refill its slot in place
-                    if (st + PF < s1) {
-                        bq[i] = bhi[(int64_t)(st + PF) * 64 + lane];
-                        if (MODE == TZ_BF16X3) bl[i] = blo[(int64_t)(st + PF) * 64 + lane];
-                    }
+                    const int64_t sf = min(st + PF, s1 - 1);
+                    bq[i] = bhi[sf * 64 + lane];
+                    if (MODE == TZ_BF16X3) bl[i] = blo[sf * 64 + lane];
                 }
             }
         }
