@@ -46,6 +46,8 @@
 // (records, DPP moves, FFT passes, carry engine) live in tfx_device.h.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "tfx_device.h"
 #include "tfx_mc.h"
 
@@ -207,32 +209,55 @@ __device__ void tz_tile(const KArgs &a, float *lds, int64_t pair, int64_t n0, in
         }
         __syncthreads();
         // steps st = 2 q + hh; tap fragments are loaded TZ_PF steps ahead
+        // through a ring, every load index clamped to the last step (no
+        // branch around a load), and each step reads the next step's signal
+        // fragments before it issues its own products
         const int s0 = 2 * q0, s1 = 2 * q1;
         V bq[TZ_PF];
 #pragma unroll
-        for (int i = 0; i < TZ_PF; ++i)
-            if (s0 + i < s1) bq[i] = bt[(int64_t)(s0 + i) * 64 + lane];
-        for (int sb = s0; sb < s1; sb += TZ_PF) {
+        for (int i = 0; i < TZ_PF; ++i) bq[i] = bt[(int64_t)min(s0 + i, s1 - 1) * 64 + lane];
+        auto afrag = [&](int st, int k) -> V {
+            const int q = st >> 1, hh = st & 1, u = w + 4 * k, g = u / 3, t = u % 3;
+            const int row = 32 * t + r32 + (q1 - 1 - q);
+            return *reinterpret_cast<const V *>(&ast[(g * TZ_ROWS + row) * TROW + 16 * hh + 8 * kh]);
+        };
+        // NT accumulator tiles (1 or 2, wave-uniform) over the steps
+        auto steps = [&](auto nt_c) {
+            constexpr int NT = decltype(nt_c)::value;
+            V acur[NT];
 #pragma unroll
-            for (int i = 0; i < TZ_PF; ++i) {
-                const int st = sb + i;
-                if (st < s1) {
-                    const int q = st >> 1, hh = st & 1;
+            for (int k = 0; k < NT; ++k) acur[k] = afrag(s0, k);
+            int sb = s0;
+            for (; sb + TZ_PF <= s1; sb += TZ_PF) {
 #pragma unroll
-                    for (int k = 0; k < 2; ++k) {
-                        if (k < ntl) {
-                            const int u = w + 4 * k, g = u / 3, t = u % 3;
-                            const int row = 32 * t + r32 + (q1 - 1 - q);
-                            const V av =
-                                *reinterpret_cast<const V *>(&ast[(g * TZ_ROWS + row) * TROW + 16 * hh + 8 * kh]);
-                            acc[k] = O::mma(av, bq[i], acc[k]);
-                        }
-                    }
-                    // the fragment's last use is issued: refill its slot in place
-                    if (st + TZ_PF < s1) bq[i] = bt[(int64_t)(st + TZ_PF) * 64 + lane];
+                for (int i = 0; i < TZ_PF; ++i) {
+                    const int st = sb + i, sn = min(st + 1, s1 - 1);
+                    V anext[NT];
+#pragma unroll
+                    for (int k = 0; k < NT; ++k) anext[k] = afrag(sn, k);
+#pragma unroll
+                    for (int k = 0; k < NT; ++k) acc[k] = O::mma(acur[k], bq[i], acc[k]);
+                    bq[i] = bt[(int64_t)min(st + TZ_PF, s1 - 1) * 64 + lane];
+#pragma unroll
+                    for (int k = 0; k < NT; ++k) acur[k] = anext[k];
+                    __builtin_amdgcn_sched_group_barrier(0x100, NT, 0);
+                    __builtin_amdgcn_sched_group_barrier(0x008, NT, 0);
+                    __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);
                 }
             }
-        }
+#pragma unroll
+            for (int i = 0; i < TZ_PF; ++i) {  // the remaining steps
+                const int st = sb + i;
+                if (st < s1) {
+#pragma unroll
+                    for (int k = 0; k < NT; ++k) acc[k] = O::mma(afrag(st, k), bq[i], acc[k]);
+                }
+            }
+        };
+        if (ntl == 2)
+            steps(std::integral_constant<int, 2>());
+        else
+            steps(std::integral_constant<int, 1>());
     }
     __syncthreads();  // every operand read done: the staging areas take the output
     // accumulator (row i, column c): lane c + 32 (i / 4 % 2), register
