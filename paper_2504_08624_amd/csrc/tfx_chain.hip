@@ -526,14 +526,17 @@ __device__ void run_section(const KArgs &a, const TB &tb, int s, float (&v)[L], 
 // With k = 16 a + b (a = the lane's 16-lane row), F^(L k) P = F^(L b) R_a,
 // R_a = F^(16 L a) P: lane (a, i) forms component i of R_a, each lane takes
 // the row's components by lane shuffles.  F is block lower triangular, and
-// so are its powers.
+// so are its powers.  The powers are read from LDS (zt_stage): mb[(i D + j)
+// 16 + b] = (F^(L b))[i][j] and ma[(a D + j) 16 + i] = (F^(16 L a))[i][j];
+// G, read at lane-uniform indices, from global memory.
 template <int D>
-__device__ __forceinline__ void casc_zir_add(float (&v)[L], const CascZir *zt, const float *P, int k) {
+__device__ __forceinline__ void casc_zir_add(float (&v)[L], const CascZir *zt, const float *mb, const float *P, int k) {
     const int a = k >> 4, b = k & 15, ri = k & 15;
+    const float *ma = mb + D * D * 16;
     float ra = 0.f;  // component ri of R_a
     if (ri < D) {
 #pragma unroll
-        for (int j = 0; j < D; ++j) ra = fmaf(zt->Ma[a][ri][j], P[j], ra);
+        for (int j = 0; j < D; ++j) ra = fmaf(ma[(a * D + j) * 16 + ri], P[j], ra);
     }
     const int row0 = (__lane_id() & ~15);
     float r[D];
@@ -543,22 +546,45 @@ __device__ __forceinline__ void casc_zir_add(float (&v)[L], const CascZir *zt, c
     for (int i = 0; i < D; ++i) {
         float zi = 0.f;  // component i of F^(L b) R_a
 #pragma unroll
-        for (int j = 0; j < (i | 1) + 1; ++j) zi = fmaf(zt->Mb[i][j][b], r[j], zi);
+        for (int j = 0; j < (i | 1) + 1; ++j) zi = fmaf(mb[(i * D + j) * 16 + b], r[j], zi);
 #pragma unroll
         for (int q = 0; q < L; ++q) v[q] = fmaf(zt->G[q][i], zi, v[q]);
     }
 }
 
+// Copies the rows j < D of Mb and MaT (16 floats each) into LDS at dst, in
+// 16-byte pieces, every load issued before the first store.
+__device__ __forceinline__ void zt_stage(float *dst, const CascZir *zt, int D, int tid) {
+    constexpr int PER = 4;  // pieces per thread per round
+    const int nmb = D * D * 4, n = nmb + ZIR_A * D * 4;
+    for (int e0 = tid; e0 < n; e0 += PER * WG) {
+        float4 t[PER];
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const int e = min(e0 + u * WG, n - 1), row = e >> 2, c4 = e & 3;
+            const float *src = e < nmb ? &zt->Mb[row / D][row % D][4 * c4]
+                                       : &zt->MaT[(row - D * D) / D][(row - D * D) % D][4 * c4];
+            t[u] = *reinterpret_cast<const float4 *>(src);
+        }
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const int e = e0 + u * WG;
+            if (e < n) reinterpret_cast<float4 *>(dst)[e] = t[u];
+        }
+    }
+}
+
 // Cascades up to ZIR_MAX sections (larger ones would cost the kernel
 // registers, hence occupancy) use the zero-input response tables.
-__device__ __forceinline__ void casc_zir(float (&v)[L], const CascZir *zt, const float *P, int k, int S) {
+__device__ __forceinline__ void casc_zir(float (&v)[L], const CascZir *zt, const float *mb, const float *P, int k,
+                                         int S) {
     switch (S) {
-    case 1: casc_zir_add<2>(v, zt, P, k); break;
-    case 2: casc_zir_add<4>(v, zt, P, k); break;
-    case 3: casc_zir_add<6>(v, zt, P, k); break;
-    case 4: casc_zir_add<8>(v, zt, P, k); break;
-    case 5: casc_zir_add<10>(v, zt, P, k); break;
-    default: casc_zir_add<12>(v, zt, P, k); break;
+    case 1: casc_zir_add<2>(v, zt, mb, P, k); break;
+    case 2: casc_zir_add<4>(v, zt, mb, P, k); break;
+    case 3: casc_zir_add<6>(v, zt, mb, P, k); break;
+    case 4: casc_zir_add<8>(v, zt, mb, P, k); break;
+    case 5: casc_zir_add<10>(v, zt, mb, P, k); break;
+    default: casc_zir_add<12>(v, zt, mb, P, k); break;
     }
 }
 
@@ -673,6 +699,12 @@ __global__ __launch_bounds__(WG, (chain_min_blocks<FIRM, HAS_SOS, HIQ, CASC, STO
                 cE[2 * s + 1] = E1;
             }
         }
+        // (the table form costs registers: kept to the variants where it
+        // does not lower occupancy)
+        constexpr bool ZIR = !STOUT && (FIRM == FIR_NONE || FIRM == FIR_FFT || FIRM == FIR_FFT_PARTS);
+        // its powers go to the staging areas, unused from phase A's first
+        // barrier until the output is staged (ordered by phase B's barrier)
+        if (ZIR && a.S <= ZIR_MAX) zt_stage(lds, a.zir, 2 * a.S, c.tid);
         // (B) one look-back of the cascade state (first wave of each group)
         if (c.gw == 0) {
             CascCtx cc;
@@ -688,12 +720,9 @@ __global__ __launch_bounds__(WG, (chain_min_blocks<FIRM, HAS_SOS, HIQ, CASC, STO
             if (a.ckpt && c.valid && c.lane < D) a.ckpt[(c.ch * a.ntiles + c.tile) * a.S * 2 + c.lane] = cP[c.lane];
         }
         __syncthreads();
-        // (the table form costs registers: kept to the variants where it
-        // does not lower occupancy)
-        constexpr bool ZIR = !STOUT && (FIRM == FIR_NONE || FIRM == FIR_FFT || FIRM == FIR_FFT_PARTS);
         if (ZIR && a.S <= ZIR_MAX) {
             // (C) the entering state's zero-input response added to phase A's output
-            casc_zir(v, a.zir, cP, c.gl, a.S);
+            casc_zir(v, a.zir, lds, cP, c.gl, a.S);
         } else {
         // (C') otherwise: every section from its known tile-entering state;
         //     section 0 reuses phase A's carry (its input is unchanged)

@@ -120,13 +120,14 @@ struct alignas(16) CascTab {
 // output of a tile is its zero-entering-state response plus
 // G[r] . (F^(L k) P) at sample r of chunk k, P being the state entering the
 // tile.  With k = 16 a + b, F^(L k) = F^(L b) F^(16 L a): Mb[i][j][b] =
-// (F^(L b))[i][j] (b < 16, lane-contiguous) and Ma[a][i][j] = (F^(16 L a))[i][j]
-// (a < 8), 40 KB in all, so the per-lane reads stay in the first-level cache.
+// (F^(L b))[i][j] (b < 16) and MaT[a][j][i] = (F^(16 L a))[i][j] (a < 8),
+// both with the lane's index (b, i) innermost: the kernel copies the rows
+// j < 2S of both into LDS as they are.
 constexpr int ZIR_B = 16, ZIR_A = GL / ZIR_B;
 struct alignas(16) CascZir {
     float G[L][16];
     float Mb[16][16][ZIR_B];
-    float Ma[ZIR_A][16][16];
+    float MaT[ZIR_A][16][16];
 };
 
 // Matrix-core form of a cascade of up to CASC_MAX sections (chain path).

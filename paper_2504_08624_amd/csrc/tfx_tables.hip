@@ -203,7 +203,7 @@ __device__ void zir_block(Co co_at, int32_t S, int Lc, int k, CascZir *out, int 
             if (e > 1) mm16(Fm, Fm, Fm, i, j);
         }
         if (k < ZIR_B) out->Mb[i][j][k] = (float)P[i][j];
-        else out->Ma[k - ZIR_B][i][j] = (float)P[i][j];
+        else out->MaT[k - ZIR_B][j][i] = (float)P[i][j];
         return;
     }
     if (tid < 16) {
