@@ -459,7 +459,7 @@ __global__ __launch_bounds__(WG) void fir_bwd_kernel(FirBwdArgs a) {
         asm volatile("" ::: "memory");
         __syncthreads();  // the previous tile's last LDS reads
         load_pair_block(zr, zi, a.g + chA * a.ldg, hasB ? a.g + chB * a.ldg : nullptr, n0, a.N, a.N, tid);
-        fft4096_forward(zr, zi, lds, a.twid, tid);
+        fft4096_forward<true>(zr, zi, lds, a.twid, tid);
         if (a.want_gh) {
             float br[16], bi[16];
 #pragma unroll
@@ -469,7 +469,7 @@ __global__ __launch_bounds__(WG) void fir_bwd_kernel(FirBwdArgs a) {
             }
             load_pair_block(zr, zi, a.x + chA * a.ldx, hasB ? a.x + chB * a.ldx : nullptr, n0, a.N, n0 + T, tid);
             __syncthreads();  // the B transform's last LDS reads
-            fft4096_forward(zr, zi, lds, a.twid, tid);
+            fft4096_forward<true>(zr, zi, lds, a.twid, tid);
 #pragma unroll
             for (int k = 0; k < 16; ++k) {  // += conj(X) B
                 ar[k] = fmaf(zr[k], br[k], fmaf(zi[k], bi[k], ar[k]));
@@ -479,7 +479,7 @@ __global__ __launch_bounds__(WG) void fir_bwd_kernel(FirBwdArgs a) {
             }
         }
         spectrum_product(zr, zi, a.hspec, tid, true);
-        fft4096_inverse(zr, zi, lds, a.twid, tid);
+        fft4096_inverse<true>(zr, zi, lds, a.twid, tid);
         store_pair_tile<0>(zr, zi, a.gx + chA * a.ldgx, hasB ? a.gx + chB * a.ldgx : nullptr, n0, a.N, tid);
     }
     if (a.want_gh) {

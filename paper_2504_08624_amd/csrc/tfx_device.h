@@ -327,17 +327,39 @@ __device__ __forceinline__ void twiddle_row(float (&zr)[16], float (&zi)[16], co
     }
 }
 
+// The same row fetched ahead (twiddle_fetch, then a scheduling fence so the
+// loads are issued before the pass's arithmetic) and applied later: the
+// transforms' PF form, for kernels with registers to spare (32 more).
+__device__ __forceinline__ void twiddle_fetch(float4 (&w)[8], const float2 *row) {
+    const float4 *r4 = reinterpret_cast<const float4 *>(row);
+#pragma unroll
+    for (int g = 0; g < 8; ++g) w[g] = r4[g];
+    __builtin_amdgcn_sched_barrier(0);
+}
+template <bool CONJ, bool ONE0>
+__device__ __forceinline__ void twiddle_apply(float (&zr)[16], float (&zi)[16], const float4 (&w)[8]) {
+#pragma unroll
+    for (int g = 0; g < 8; ++g) {
+        if (g > 0 || !ONE0) cmul_tw<CONJ>(zr[2 * g], zi[2 * g], make_float2(w[g].x, w[g].y));
+        cmul_tw<CONJ>(zr[2 * g + 1], zi[2 * g + 1], make_float2(w[g].z, w[g].w));
+    }
+}
+
 // Forward 4096-point DFT (e^{-2 pi i n k / 4096}) of the values held by the
 // 256 lanes of a workgroup.  In: lane t holds z[256 a + t], a = 0..15.  Out:
 // lane t holds Z[t + 256 k3], k3 = 0..15.  Three radix-16 passes with two LDS
 // exchanges through lds[0 .. 8192) floats.  Ends with the data in registers
 // and every lane past its last LDS read (callers may reuse lds after a
 // barrier).
+template <bool PF = false>
 __device__ __forceinline__ void fft4096_forward(float (&zr)[16], float (&zi)[16], float *lds, const float2 *twid,
                                                 int tid) {
     float *Lr = lds, *Li = lds + NFFT;
+    float4 tw[8];
+    if (PF) twiddle_fetch(tw, twid + TW1_OFF + 16 * tid);
     dft16<-1>(zr, zi);
-    twiddle_row<false, true>(zr, zi, twid + TW1_OFF + 16 * tid);
+    if (PF) twiddle_apply<false, true>(zr, zi, tw);
+    else twiddle_row<false, true>(zr, zi, twid + TW1_OFF + 16 * tid);
     {
         const int b = tid >> 4, c = tid & 15, w0 = 16 * b + c;
 #pragma unroll
@@ -347,6 +369,7 @@ __device__ __forceinline__ void fft4096_forward(float (&zr)[16], float (&zi)[16]
             Li[ad] = zi[k1];
         }
     }
+    if (PF) twiddle_fetch(tw, twid + TW2_OFF + 16 * (tid & 15));
     __syncthreads();
     {
         const int k1 = tid >> 4, c = tid & 15, r0 = 272 * k1 + c;
@@ -357,7 +380,8 @@ __device__ __forceinline__ void fft4096_forward(float (&zr)[16], float (&zi)[16]
             zi[b] = Li[ad];
         }
         dft16<-1>(zr, zi);
-        twiddle_row<false, true>(zr, zi, twid + TW2_OFF + 16 * c);
+        if (PF) twiddle_apply<false, true>(zr, zi, tw);
+        else twiddle_row<false, true>(zr, zi, twid + TW2_OFF + 16 * c);
         __syncthreads();
         const int w1 = 272 * k1 + ((c + k1) & 15);
 #pragma unroll
@@ -383,13 +407,17 @@ __device__ __forceinline__ void fft4096_forward(float (&zr)[16], float (&zi)[16]
 // Inverse of fft4096_forward without the 1/4096 factor (e^{+2 pi i n k /
 // 4096}): in the forward's output layout, out in its input layout.  Begins
 // with a barrier before its first LDS write.
+template <bool PF = false>
 __device__ __forceinline__ void fft4096_inverse(float (&zr)[16], float (&zi)[16], float *lds, const float2 *twid,
                                                 int tid) {
     float *Lr = lds, *Li = lds + NFFT;
+    float4 tw[8];
     {
         const int k1 = tid & 15, k2 = tid >> 4, r1 = 256 * k1 + 16 * ((k2 + k1) & 15) + k1;
+        if (PF) twiddle_fetch(tw, twid + TW2_OFF + 16 * k2);
         dft16<1>(zr, zi);
-        twiddle_row<true, true>(zr, zi, twid + TW2_OFF + 16 * k2);
+        if (PF) twiddle_apply<true, true>(zr, zi, tw);
+        else twiddle_row<true, true>(zr, zi, twid + TW2_OFF + 16 * k2);
         __syncthreads();
 #pragma unroll
         for (int c = 0; c < 16; ++c) {
@@ -398,6 +426,7 @@ __device__ __forceinline__ void fft4096_inverse(float (&zr)[16], float (&zi)[16]
             Li[ad] = zi[c];
         }
     }
+    if (PF) twiddle_fetch(tw, twid + TW3_OFF + 16 * tid);
     __syncthreads();
     {
         const int k1 = tid >> 4, c = tid & 15, w1 = 272 * k1 + ((c + k1) & 15);
@@ -408,7 +437,8 @@ __device__ __forceinline__ void fft4096_inverse(float (&zr)[16], float (&zi)[16]
             zi[k2] = Li[ad];
         }
         dft16<1>(zr, zi);
-        twiddle_row<true, false>(zr, zi, twid + TW3_OFF + 16 * tid);
+        if (PF) twiddle_apply<true, false>(zr, zi, tw);
+        else twiddle_row<true, false>(zr, zi, twid + TW3_OFF + 16 * tid);
         __syncthreads();
         const int r0 = 272 * k1 + c;
 #pragma unroll
