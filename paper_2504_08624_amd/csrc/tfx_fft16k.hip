@@ -50,24 +50,50 @@ constexpr int NV = TFX_FFT16_NV;  // virtual lanes per thread: t + VS v
 constexpr int WGB = 1024 / NV;    // threads per workgroup
 constexpr int VS = WGB;           // virtual-lane stride
 
-// twiddle regions (float2): TWA [1024][16], TWB [64][16], TWC [4][16]
-constexpr int TWA_OFF = 0, TWB_OFF = 16384, TWC_OFF = 16384 + 1024;
+// Twiddle tables (float2, rows of 16 entries padded to TWS = 18 so that the
+// 16-byte reads of 16 lanes from 16 different rows hit 64 different banks):
+//   TWB[c][k] = W^(16 c k) (c < 64), TWC[e][k] = W^(256 e k) (e < 4),
+//   TLO[c][k] = W^(c k) (c < 16).
+// Pass A's W^(L k) is formed as TWB[L >> 4][k] TLO[L & 15][k].  The whole set
+// (12 KB) is copied into LDS by each workgroup: read from global memory at
+// every pass, the twiddle loads' latency took some 40 % of the kernel's time.
+constexpr int TWS = 18;
+constexpr int TWB_ROW = 0, TWC_ROW = 64, TLO_ROW = 68, TW_ROWS = 84;
+constexpr int TW_FLOAT2 = TW_ROWS * TWS;  // 1512
 
-// twiddle_row with the table loads in groups of two 16-byte loads (a
-// compiler barrier between groups), so at most four twiddles sit in
-// registers beside the data.
+// Multiplies the lane's 16 values by a row of the twiddle table (or its
+// conjugate), the row's 16-byte pieces read from LDS as they are used.
 template <bool CONJ>
-__device__ __forceinline__ void twiddle_row_lean(float (&zr)[16], float (&zi)[16], const float2 *row) {
+__device__ __forceinline__ void twiddle_lds(float (&zr)[16], float (&zi)[16], const float2 *row) {
     const float4 *r4 = reinterpret_cast<const float4 *>(row);
 #pragma unroll
-    for (int g = 0; g < 8; g += 2) {
-        const float4 w0 = r4[g], w1 = r4[g + 1];
-        if (g > 0) cmul_tw<CONJ>(zr[2 * g], zi[2 * g], make_float2(w0.x, w0.y));
-        cmul_tw<CONJ>(zr[2 * g + 1], zi[2 * g + 1], make_float2(w0.z, w0.w));
-        cmul_tw<CONJ>(zr[2 * g + 2], zi[2 * g + 2], make_float2(w1.x, w1.y));
-        cmul_tw<CONJ>(zr[2 * g + 3], zi[2 * g + 3], make_float2(w1.z, w1.w));
-        asm volatile("" ::: "memory");
+    for (int g = 0; g < 8; ++g) {
+        const float4 w = r4[g];
+        if (g > 0) cmul_tw<CONJ>(zr[2 * g], zi[2 * g], make_float2(w.x, w.y));
+        cmul_tw<CONJ>(zr[2 * g + 1], zi[2 * g + 1], make_float2(w.z, w.w));
     }
+}
+
+// Pass A's row W^(L k) = TWB[L >> 4][k] TLO[L & 15][k], applied as its two
+// factors one after the other.
+template <bool CONJ>
+__device__ __forceinline__ void twiddle_lds_a(float (&zr)[16], float (&zi)[16], const float2 *tw, int L) {
+    twiddle_lds<CONJ>(zr, zi, tw + (TWB_ROW + (L >> 4)) * TWS);
+    twiddle_lds<CONJ>(zr, zi, tw + (TLO_ROW + (L & 15)) * TWS);
+}
+
+// Copies the twiddle tables into the workgroup's LDS copy (every load issued
+// before the first store; the caller passes a barrier before the first use).
+__device__ __forceinline__ void tw_stage(float2 *twl, const float2 *tw, int t) {
+    constexpr int N4 = TW_FLOAT2 / 2, R = (N4 + WGB - 1) / WGB;
+    const float4 *src = reinterpret_cast<const float4 *>(tw);
+    float4 *dst = reinterpret_cast<float4 *>(twl);
+    float4 w[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) w[r] = src[min(t + r * WGB, N4 - 1)];
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+        if (t + r * WGB < N4) dst[t + r * WGB] = w[r];
 }
 
 // Lane coordinates of virtual lane L = t + 512 v.
@@ -222,7 +248,7 @@ __device__ __forceinline__ void fft16k_forward(float (&zr)[NV][16], float (&zi)[
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
             dft16<-1>(zr[v], zi[v]);
-            twiddle_row_lean<false>(zr[v], zi[v], tw + TWA_OFF + 16 * (u + VS * v));
+            twiddle_lds_a<false>(zr[v], zi[v], tw, u + VS * v);
         }
     }
     exchange(zr, zi, P, t, map_a, map_b);
@@ -231,7 +257,7 @@ __device__ __forceinline__ void fft16k_forward(float (&zr)[NV][16], float (&zi)[
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
             dft16<-1>(zr[v], zi[v]);
-            twiddle_row_lean<false>(zr[v], zi[v], tw + TWB_OFF + 16 * ((u + VS * v) & 63));
+            twiddle_lds<false>(zr[v], zi[v], tw + (TWB_ROW + ((u + VS * v) & 63)) * TWS);
         }
     }
     __syncthreads();
@@ -241,7 +267,7 @@ __device__ __forceinline__ void fft16k_forward(float (&zr)[NV][16], float (&zi)[
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
             dft16<-1>(zr[v], zi[v]);
-            twiddle_row_lean<false>(zr[v], zi[v], tw + TWC_OFF + 16 * (u & 3));
+            twiddle_lds<false>(zr[v], zi[v], tw + (TWC_ROW + (u & 3)) * TWS);
         }
     }
     // exchange C -> D, pass D reading (k3 = 4 q + r, e = 0..3) as 16-byte groups
@@ -263,10 +289,12 @@ __device__ __forceinline__ void fft16k_forward(float (&zr)[NV][16], float (&zi)[
 }
 
 // Inverse of fft16k_forward without the 1/16384 factor: from its output
-// layout back to its input layout.  Begins with a barrier before its first
+// layout back to its input layout, lane v's 16 values passed to out(zr, zi, v)
+// once final.  Begins with a barrier before its first
 // LDS write; ends after its last read.
+template <class OUT>
 __device__ __forceinline__ void fft16k_inverse(float (&zr)[NV][16], float (&zi)[NV][16], float *P, const float2 *tw,
-                                               int t) {
+                                               int t, OUT out) {
 #pragma unroll
     for (int v = 0; v < NV; ++v)
 #pragma unroll
@@ -286,7 +314,7 @@ __device__ __forceinline__ void fft16k_inverse(float (&zr)[NV][16], float (&zi)[
         const int u = opaque(t);
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
-            twiddle_row_lean<true>(zr[v], zi[v], tw + TWC_OFF + 16 * (u & 3));
+            twiddle_lds<true>(zr[v], zi[v], tw + (TWC_ROW + (u & 3)) * TWS);
             dft16<1>(zr[v], zi[v]);
         }
     }
@@ -296,18 +324,20 @@ __device__ __forceinline__ void fft16k_inverse(float (&zr)[NV][16], float (&zi)[
         const int u = opaque(t);
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
-            twiddle_row_lean<true>(zr[v], zi[v], tw + TWB_OFF + 16 * ((u + VS * v) & 63));
+            twiddle_lds<true>(zr[v], zi[v], tw + (TWB_ROW + ((u + VS * v) & 63)) * TWS);
             dft16<1>(zr[v], zi[v]);
         }
     }
     __syncthreads();
     exchange(zr, zi, P, t, map_b, map_a);
-    {  // pass A inverse: lane L over k1
+    {  // pass A inverse: lane L over k1; each lane's values handed to out
+       // as soon as they are final (their registers free for the next lane)
         const int u = opaque(t);
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
-            twiddle_row_lean<true>(zr[v], zi[v], tw + TWA_OFF + 16 * (u + VS * v));
+            twiddle_lds_a<true>(zr[v], zi[v], tw, u + VS * v);
             dft16<1>(zr[v], zi[v]);
+            out(zr[v], zi[v], v);
         }
     }
 }
@@ -333,39 +363,35 @@ __device__ __forceinline__ int64_t xcd_block(int64_t i, int64_t nb) {
     return x * per + (x < rem ? x : rem) + (i >> 3);
 }
 
-// Stores rows Q0 .. Q0 + 7 of the block (samples n0 + 1024 q + L) to ya and,
-// when yb is set, yb, up to N.
+// Stores rows Q0 .. Q0 + 7 of virtual lane L's values (samples n0 + 1024 q +
+// L) to ya and, when yb is set, yb, up to N.
 template <int Q0>
-__device__ __forceinline__ void store_rows(const float (&zr)[NV][16], const float (&zi)[NV][16], float *ya,
-                                           float *yb, int64_t n0, int64_t N, int t) {
+__device__ __forceinline__ void store_rows(const float (&zr)[16], const float (&zi)[16], float *ya, float *yb,
+                                           int64_t n0, int64_t N, int L) {
     if (n0 + HOPB <= N) {
 #pragma unroll
-        for (int v = 0; v < NV; ++v)
-#pragma unroll
-            for (int q = 0; q < 8; ++q) ya[n0 + 1024 * q + VS * v + t] = zr[v][Q0 + q];
+        for (int q = 0; q < 8; ++q) ya[n0 + 1024 * q + L] = zr[Q0 + q];
         if (yb) {
 #pragma unroll
-            for (int v = 0; v < NV; ++v)
-#pragma unroll
-                for (int q = 0; q < 8; ++q) yb[n0 + 1024 * q + VS * v + t] = zi[v][Q0 + q];
+            for (int q = 0; q < 8; ++q) yb[n0 + 1024 * q + L] = zi[Q0 + q];
         }
         return;
     }
 #pragma unroll
-    for (int v = 0; v < NV; ++v)
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            const int64_t n = n0 + 1024 * q + VS * v + t;
-            if (n < N) {
-                ya[n] = zr[v][Q0 + q];
-                if (yb) yb[n] = zi[v][Q0 + q];
-            }
+    for (int q = 0; q < 8; ++q) {
+        const int64_t n = n0 + 1024 * q + L;
+        if (n < N) {
+            ya[n] = zr[Q0 + q];
+            if (yb) yb[n] = zi[Q0 + q];
         }
+    }
 }
 
 __global__ __launch_bounds__(WGB, 8 / NV) void fir16k_kernel(F16Args a) {
     __shared__ __align__(16) float P[NB];
+    __shared__ __align__(16) float2 twl[TW_FLOAT2];
     const int t = threadIdx.x;
+    tw_stage(twl, a.tw, t);
     const int64_t lb = xcd_block(blockIdx.x, a.nblocks);
     const int64_t pair = lb / a.ntiles, tile = lb - pair * a.ntiles;
     const int64_t ca = 2 * pair, cb = ca + 1;
@@ -407,43 +433,57 @@ __global__ __launch_bounds__(WGB, 8 / NV) void fir16k_kernel(F16Args a) {
                 zi[v][q] = (in && has_b) ? xb[n] : ((inh && hb) ? hb[a.hlen + n] : 0.f);
             }
     }
-    fft16k_forward(zr, zi, P, a.tw, t);
+    __syncthreads();  // the twiddle tables
+    fft16k_forward(zr, zi, P, twl, t);
+    __builtin_amdgcn_sched_barrier(0);
     {
         const float sg = a.correlate ? -1.f : 1.f;
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
+            // eight bins at a time: their 4 loads issued together, the next
+            // ones held back by a scheduling fence (registers)
             const float4 *h4 = reinterpret_cast<const float4 *>(a.hs + 16 * (t + VS * v));
 #pragma unroll
-            for (int g4 = 0; g4 < 4; ++g4) {
-                const float4 p = h4[2 * g4], r = h4[2 * g4 + 1];
-                const float2 w[4] = {make_float2(p.x, sg * p.y), make_float2(p.z, sg * p.w),
-                                     make_float2(r.x, sg * r.y), make_float2(r.z, sg * r.w)};
+            for (int hf = 0; hf < 2; ++hf) {
+                float4 hq[4];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) cmul_tw<false>(zr[v][4 * g4 + u], zi[v][4 * g4 + u], w[u]);
-                asm volatile("" ::: "memory");  // at most four bins' spectra in registers at a time
+                for (int g = 0; g < 4; ++g) hq[g] = h4[4 * hf + g];
+#pragma unroll
+                for (int g = 0; g < 4; ++g) {
+                    const int b = 8 * hf + 2 * g;
+                    cmul_tw<false>(zr[v][b], zi[v][b], make_float2(hq[g].x, sg * hq[g].y));
+                    cmul_tw<false>(zr[v][b + 1], zi[v][b + 1], make_float2(hq[g].z, sg * hq[g].w));
+                }
+                __builtin_amdgcn_sched_barrier(0);
             }
         }
     }
-    fft16k_inverse(zr, zi, P, a.tw, t);
     // rows 8..15 of the block (convolution) or 0..7 (correlation) are the tile
     // (two paths with constant row indices: a run-time index into the data
     // arrays would move them to scratch memory)
     float *ya = a.y + ca * a.ldy, *yb = has_b ? a.y + cb * a.ldy : nullptr;
-    if (a.correlate)
-        store_rows<0>(zr, zi, ya, yb, n0, a.N, t);
-    else
-        store_rows<8>(zr, zi, ya, yb, n0, a.N, t);
+    fft16k_inverse(zr, zi, P, twl, t, [&](const float (&r)[16], const float (&i)[16], int v) {
+        if (a.correlate)
+            store_rows<0>(r, i, ya, yb, n0, a.N, t + VS * v);
+        else
+            store_rows<8>(r, i, ya, yb, n0, a.N, t + VS * v);
+    });
 }
 
-// Twiddle tables in fp32 from sincospi of exact arguments (2 m / 16384):
-//   TWA[t][k] = W^(t k), TWB[c][k] = W^(16 c k), TWC[e][k] = W^(256 e k).
+// Twiddle tables in fp32 from sincospi of exact arguments (2 m / 16384), in
+// the padded row layout above (pad entries zero).
 __global__ void fft16k_twiddle_kernel(float2 *tw) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= TW_FLOAT2) return;
+    const int row = i / TWS, k = i % TWS;
+    if (k >= 16) {
+        tw[i] = make_float2(0.f, 0.f);
+        return;
+    }
     int m;
-    if (i < TWB_OFF) m = ((i >> 4) * (i & 15)) & (NB - 1);
-    else if (i < TWC_OFF) m = (16 * ((i - TWB_OFF) >> 4) * (i & 15)) & (NB - 1);
-    else if (i < TWC_OFF + 64) m = (256 * ((i - TWC_OFF) >> 4) * (i & 15)) & (NB - 1);
-    else return;
+    if (row < TWC_ROW) m = (16 * (row - TWB_ROW) * k) & (NB - 1);
+    else if (row < TLO_ROW) m = (256 * (row - TWC_ROW) * k) & (NB - 1);
+    else m = ((row - TLO_ROW) * k) & (NB - 1);
     float s, c;
     sincospif(-2.0f * (float)m / (float)NB, &s, &c);
     tw[i] = make_float2(c, s);
@@ -454,7 +494,9 @@ __global__ void fft16k_twiddle_kernel(float2 *tw) {
 __global__ __launch_bounds__(WGB, 1) void fft16k_spectrum_kernel(const float *h, int32_t M, const float2 *tw,
                                                                  float2 *hs) {
     __shared__ __align__(16) float P[NB];
+    __shared__ __align__(16) float2 twl[TW_FLOAT2];
     const int t = threadIdx.x;
+    tw_stage(twl, tw, t);
     float zr[NV][16], zi[NV][16];
 #pragma unroll
     for (int v = 0; v < NV; ++v)
@@ -464,7 +506,8 @@ __global__ __launch_bounds__(WGB, 1) void fft16k_spectrum_kernel(const float *h,
             zr[v][q] = n < M ? h[n] : 0.f;
             zi[v][q] = 0.f;
         }
-    fft16k_forward(zr, zi, P, tw, t);
+    __syncthreads();  // the twiddle tables
+    fft16k_forward(zr, zi, P, twl, t);
     const float sc = 1.0f / (float)NB;
 #pragma unroll
     for (int v = 0; v < NV; ++v)
@@ -474,12 +517,12 @@ __global__ __launch_bounds__(WGB, 1) void fft16k_spectrum_kernel(const float *h,
 
 }  // namespace
 
-size_t fft16k_table_bytes() { return (size_t)(TWC_OFF + 64) * sizeof(float2) + (size_t)NB * sizeof(float2); }
+size_t fft16k_table_bytes() { return (size_t)TW_FLOAT2 * sizeof(float2) + (size_t)NB * sizeof(float2); }
 
 hipError_t launch_fft16k_prepare(const float *h, int32_t M, void *tab, hipStream_t st) {
     float2 *tw = static_cast<float2 *>(tab);
-    float2 *hs = tw + (TWC_OFF + 64);
-    hipLaunchKernelGGL(fft16k_twiddle_kernel, dim3((TWC_OFF + 64 + 255) / 256), dim3(256), 0, st, tw);
+    float2 *hs = tw + TW_FLOAT2;
+    hipLaunchKernelGGL(fft16k_twiddle_kernel, dim3((TW_FLOAT2 + 255) / 256), dim3(256), 0, st, tw);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(fft16k_spectrum_kernel, dim3(1), dim3(WGB), 0, st, h, M, static_cast<const float2 *>(tw), hs);
@@ -499,7 +542,7 @@ hipError_t launch_fft16k(const float *x, float *y, int64_t C, int64_t N, int64_t
     a.ntiles = (N + HOPB - 1) / HOPB;
     a.nblocks = (C + 1) / 2 * a.ntiles;
     a.tw = static_cast<const float2 *>(tab);
-    a.hs = a.tw + (TWC_OFF + 64);
+    a.hs = a.tw + TW_FLOAT2;
     a.hist = (!correlate && M > 1) ? hist : nullptr;
     a.hlen = M > 1 ? M - 1 : 0;
     a.correlate = correlate ? 1 : 0;
