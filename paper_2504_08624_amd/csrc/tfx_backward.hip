@@ -29,6 +29,8 @@
 // reduced in a fixed order in FP64, so results are bit-identical run to run.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "tfx_device.h"
 
 namespace tfx {
@@ -94,6 +96,9 @@ __global__ __launch_bounds__(WG, 3) void sos_bwd_kernel(BArgs a) {
     float *stg = stg_all + grp * STG_FLOATS;
     const int mc = GL - 1 - gl;  // the chunk this lane owns in reverse time
     float2 *sig = reinterpret_cast<float2 *>(s_tab + S) + grp * S * GL;
+    // the FFT FIR's twiddles sit in the chunk-state area until step 2 (the
+    // launch sizes the area for both)
+    float2 *s_twl = reinterpret_cast<float2 *>(s_tab + S);
     stage_tables(s_tab, a.tab, 0, S, tid, WG);
 
     // 1. stage f; lanes take their forward chunk (gl) and their reverse-time
@@ -102,10 +107,12 @@ __global__ __launch_bounds__(WG, 3) void sos_bwd_kernel(BArgs a) {
         float zr[16], zi[16];
         const float *xA = a.x + 2 * pair * a.ldx;
         const float *xB = 2 * pair + 1 < a.C ? xA + a.ldx : nullptr;
+        twl_stage(s_twl, a.twid, tid, WG);
         load_pair_block(zr, zi, xA, xB, n0 - FFT_DISCARD, a.N, a.N, tid);
-        fft4096_forward(zr, zi, stg_all, a.twid, tid);
+        __syncthreads();  // the twiddles
+        fft4096_forward<TW_LDS>(zr, zi, stg_all, s_twl, tid);
         spectrum_product(zr, zi, a.hspec, tid, false);
-        fft4096_inverse(zr, zi, stg_all, a.twid, tid);
+        fft4096_inverse<TW_LDS>(zr, zi, stg_all, s_twl, tid);
         __syncthreads();  // the FFT buffers become the two staging areas
 #pragma unroll
         for (int q = 4; q < 16; ++q) {
@@ -459,7 +466,7 @@ __global__ __launch_bounds__(WG) void fir_bwd_kernel(FirBwdArgs a) {
         asm volatile("" ::: "memory");
         __syncthreads();  // the previous tile's last LDS reads
         load_pair_block(zr, zi, a.g + chA * a.ldg, hasB ? a.g + chB * a.ldg : nullptr, n0, a.N, a.N, tid);
-        fft4096_forward<true>(zr, zi, lds, a.twid, tid);
+        fft4096_forward<TW_PREFETCH>(zr, zi, lds, a.twid, tid);
         if (a.want_gh) {
             float br[16], bi[16];
 #pragma unroll
@@ -469,7 +476,7 @@ __global__ __launch_bounds__(WG) void fir_bwd_kernel(FirBwdArgs a) {
             }
             load_pair_block(zr, zi, a.x + chA * a.ldx, hasB ? a.x + chB * a.ldx : nullptr, n0, a.N, n0 + T, tid);
             __syncthreads();  // the B transform's last LDS reads
-            fft4096_forward<true>(zr, zi, lds, a.twid, tid);
+            fft4096_forward<TW_PREFETCH>(zr, zi, lds, a.twid, tid);
 #pragma unroll
             for (int k = 0; k < 16; ++k) {  // += conj(X) B
                 ar[k] = fmaf(zr[k], br[k], fmaf(zi[k], bi[k], ar[k]));
@@ -479,7 +486,7 @@ __global__ __launch_bounds__(WG) void fir_bwd_kernel(FirBwdArgs a) {
             }
         }
         spectrum_product(zr, zi, a.hspec, tid, true);
-        fft4096_inverse<true>(zr, zi, lds, a.twid, tid);
+        fft4096_inverse<TW_PREFETCH>(zr, zi, lds, a.twid, tid);
         store_pair_tile<0>(zr, zi, a.gx + chA * a.ldgx, hasB ? a.gx + chB * a.ldgx : nullptr, n0, a.N, tid);
     }
     if (a.want_gh) {
@@ -720,7 +727,9 @@ hipError_t launch_backward(const BwdPlan &bp) {
         b.vecf = (reinterpret_cast<uintptr_t>(b.f) % 16 == 0 && b.ldf % 4 == 0) ? 1 : 0;
         b.vecg = (reinterpret_cast<uintptr_t>(b.g) % 16 == 0 && b.ldg % 4 == 0) ? 1 : 0;
         b.veco = (reinterpret_cast<uintptr_t>(b.gf) % 16 == 0 && b.ldo % 4 == 0) ? 1 : 0;
-        const size_t dyn = (size_t)p.S * (sizeof(SecLds) + GROUPS * GL * sizeof(float2));
+        const size_t dyn = (size_t)p.S * sizeof(SecLds) +
+                           std::max((size_t)p.S * GROUPS * GL * sizeof(float2),
+                                    fuse ? sizeof(float2) * TWL_ENTRIES : (size_t)0);
         const dim3 grid((unsigned)(npairs * ntiles)), block(WG);
         if (fuse) {
             b.x = p.x;

@@ -46,6 +46,7 @@
 // (records, DPP moves, FFT passes, carry engine) live in tfx_device.h.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <type_traits>
 
 #include "tfx_device.h"
@@ -294,11 +295,11 @@ __device__ void tz_tile(const KArgs &a, float *lds, int64_t pair, int64_t n0, in
 // 1025) filters its own input block, shifted by 1025 p samples (earlier for
 // the convolution, later for the correlation); the products with the
 // partition spectra are summed in the frequency domain and inverted once.
-// PF: twiddle rows fetched ahead of each pass (the FIR-only kernels, which
-// have the registers).
-template <bool PARTS, bool PF = false>
+// TWM: the transforms' twiddle source (TW_LDS: tw is the workgroup's LDS copy
+// of the tables, staged by the caller; otherwise tw is a.twid).
+template <bool PARTS, int TWM = TW_GLOBAL>
 __device__ void fft_block(const KArgs &a, float *lds, int64_t pair, int64_t n0, int tid, float (&zr)[16],
-                          float (&zi)[16]) {
+                          float (&zi)[16], const float2 *tw) {
     const int64_t chA = 2 * pair, chB = 2 * pair + 1;
     const float *xA = a.x + chA * a.ldx;
     const float *xB = chB < a.C ? a.x + chB * a.ldx : nullptr;
@@ -308,7 +309,7 @@ __device__ void fft_block(const KArgs &a, float *lds, int64_t pair, int64_t n0, 
     const int64_t base = a.correlate ? n0 : n0 - FFT_DISCARD;
     if (!PARTS) {
         load_pair_block(zr, zi, xA, xB, base, a.N, a.N, tid, hA, hB, hlen);
-        fft4096_forward<PF>(zr, zi, lds, a.twid, tid);
+        fft4096_forward<TWM>(zr, zi, lds, tw, tid);
         spectrum_product(zr, zi, a.hspec, tid, a.correlate != 0);
     } else {
         // spectrum accumulator: lane t owns bins t + 256 k3 (no sharing, no
@@ -319,7 +320,7 @@ __device__ void fft_block(const KArgs &a, float *lds, int64_t pair, int64_t n0, 
             const int64_t shift = (int64_t)FFT_PART * p;
             __syncthreads();  // the previous pass's last LDS reads
             load_pair_block(zr, zi, xA, xB, a.correlate ? base + shift : base - shift, a.N, a.N, tid, hA, hB, hlen);
-            fft4096_forward<PF>(zr, zi, lds, a.twid, tid);
+            fft4096_forward<TWM>(zr, zi, lds, tw, tid);
             const float2 *hs = a.hspec + (int64_t)p * NFFT;
             const float sg = a.correlate ? -1.f : 1.f;
 #pragma unroll 4
@@ -339,7 +340,7 @@ __device__ void fft_block(const KArgs &a, float *lds, int64_t pair, int64_t n0, 
             zi[k3] = s.y;
         }
     }
-    fft4096_inverse<PF>(zr, zi, lds, a.twid, tid);
+    fft4096_inverse<TWM>(zr, zi, lds, tw, tid);
     if (a.correlate) {  // move the tile to a = 4..15 like the convolution case
 #pragma unroll
         for (int q = 15; q >= 4; --q) {
@@ -603,12 +604,17 @@ __global__ __launch_bounds__(WG, (chain_min_blocks<FIRM, HAS_SOS, HIQ, CASC, STO
     __shared__ double s_agg[2 * GROUPS][GWAVES][2];
     __shared__ double s_pre[2 * GROUPS][2];
     __shared__ uint32_t s_epoch;
+    constexpr bool FFT = FIRM == FIR_FFT || FIRM == FIR_FFT_PARTS;
     // dynamic: the fp32 tables (LDS_SECTIONS sections at a time, or all of a
     // cascade-level cascade without their look-back powers), then the
     // cascade look-back area unless it sits in the FFT buffers' tail
     extern __shared__ __align__(16) unsigned char s_dyn[];
     SecLds *s_tab = reinterpret_cast<SecLds *>(s_dyn);
     SecLdsC *s_tabc = reinterpret_cast<SecLdsC *>(s_dyn);
+    // with the FFT FIR the same area first holds the transforms' twiddles
+    // (the tables go there once the FIR is done; the launch sizes the area
+    // for both)
+    float2 *s_twl = reinterpret_cast<float2 *>(s_dyn);
 
     if (HAS_SOS && (a.hdr[HDR_HIQ] != 0u) != HIQ) {  // the other variant runs
         advance_epoch(a.hdr);
@@ -622,7 +628,14 @@ __global__ __launch_bounds__(WG, (chain_min_blocks<FIRM, HAS_SOS, HIQ, CASC, STO
     c.gw = c.gl >> 6;
     const uint64_t id = blockIdx.x;
     c.epoch = 0;
-    if (HAS_SOS) {
+    if (FFT) {
+        // the section tables are staged once the FIR is done: its twiddles
+        // hold their LDS area until then
+        twl_stage(s_twl, a.twid, c.tid, WG);
+        if (HAS_SOS && c.tid == 0) s_epoch = load_epoch(a.hdr, HDR_EPOCH);
+        __syncthreads();
+        if (HAS_SOS) c.epoch = s_epoch;
+    } else if (HAS_SOS) {
         if (c.tid == 0) s_epoch = load_epoch(a.hdr, HDR_EPOCH);
         // the tables' loads overlap the FIR part of the tile
         if (CASC)
@@ -652,13 +665,17 @@ __global__ __launch_bounds__(WG, (chain_min_blocks<FIRM, HAS_SOS, HIQ, CASC, STO
         direct_tile(a, stg, c.ch, c.valid, c.gl, n0, v);
     } else {  // FIR_FFT
         float zr[16], zi[16];
-        fft_block<FIRM == FIR_FFT_PARTS, !HAS_SOS>(a, lds, pair, n0, c.tid, zr, zi);
+        fft_block<FIRM == FIR_FFT_PARTS, TW_LDS>(a, lds, pair, n0, c.tid, zr, zi, s_twl);
         if (!HAS_SOS) {
             const int64_t chA = 2 * pair, chB = chA + 1;
             store_pair_tile<4>(zr, zi, a.y + chA * a.ldy, chB < a.C ? a.y + chB * a.ldy : nullptr, n0, a.N, c.tid);
             return;
         }
-        __syncthreads();  // FFT buffers become the two staging areas
+        __syncthreads();  // FFT buffers become the two staging areas, the twiddles' area the tables
+        if (CASC)
+            stage_tables(s_tabc, a.tab, 0, a.S, c.tid, WG);
+        else
+            stage_tables(s_tab, a.tab, 0, min(a.S, LDS_SECTIONS), c.tid, WG);
         float *stA = lds, *stB = lds + STG_FLOATS;
 #pragma unroll
         for (int q = 4; q < 16; ++q) {
@@ -791,6 +808,7 @@ template <int FIRM>
 __global__ __launch_bounds__(WG, 4) void chain_mc_kernel(KArgs a) {
     __shared__ __align__(16) float lds[mc_lds_floats<FIRM>()];
     __shared__ uint32_t s_epoch;
+    __shared__ __align__(16) float2 s_twl[FIRM == FIR_FFT ? TWL_ENTRIES : 2];  // the transforms' twiddles
     if (a.hdr[HDR_HIQ] != 0u) {  // the FP64-carry variant runs
         advance_epoch(a.hdr);
         return;
@@ -807,7 +825,9 @@ __global__ __launch_bounds__(WG, 4) void chain_mc_kernel(KArgs a) {
     // ---- FIR (or the input) into X
     if constexpr (FIRM == FIR_FFT) {
         float zr[16], zi[16];
-        fft_block<false>(a, lds, pair, n0, tid, zr, zi);
+        twl_stage(s_twl, a.twid, tid, WG);
+        __syncthreads();
+        fft_block<false, TW_LDS>(a, lds, pair, n0, tid, zr, zi, s_twl);
         __syncthreads();  // the FFT buffers become X
 #pragma unroll
         for (int q = 4; q < 16; ++q) {
@@ -909,10 +929,12 @@ hipError_t launch_state_passthrough(const float *in, float *out, int64_t n, hipS
 
 template <int F, bool S, bool STOUT>
 static hipError_t launch_variants(const KArgs &k, int64_t nblocks, hipStream_t st) {
-    const size_t dyn = S ? sizeof(SecLds) * (size_t)(k.S < LDS_SECTIONS ? k.S : LDS_SECTIONS) : 0;
+    // (with the FFT FIR the dynamic area first holds the twiddles)
+    constexpr size_t twl = (F == FIR_FFT || F == FIR_FFT_PARTS) ? sizeof(float2) * TWL_ENTRIES : 0;
+    const size_t dyn = std::max(twl, S ? sizeof(SecLds) * (size_t)(k.S < LDS_SECTIONS ? k.S : LDS_SECTIONS) : 0);
     if constexpr (S) {
-        const size_t dync = sizeof(SecLdsC) * (size_t)k.S +
-                            (casc_in_tail(F, k.S) ? 0 : sizeof(float) * (size_t)casc_floats(2 * k.S));
+        const size_t dync = std::max(twl, sizeof(SecLdsC) * (size_t)k.S +
+                                              (casc_in_tail(F, k.S) ? 0 : sizeof(float) * (size_t)casc_floats(2 * k.S)));
         constexpr bool mc = !STOUT && (F == FIR_NONE || F == FIR_FFT || F == FIR_DIRECT || is_tz<F>());
         if (mc && k.S >= MC_MIN_SECTIONS && k.S <= CASC_MAX) {
             if constexpr (mc)

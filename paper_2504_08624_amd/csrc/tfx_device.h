@@ -345,21 +345,55 @@ __device__ __forceinline__ void twiddle_apply(float (&zr)[16], float (&zi)[16], 
     }
 }
 
+// The LDS form (TW_LDS): every twiddle from the 32 rows of TWL copied into
+// LDS by the workgroup (twl_stage), since global twiddle loads left the
+// transforms waiting on L2 at every pass.  TW1 and TW3 are formed from two
+// factors each: W^(t k) = W^(16 (t >> 4) k) W^((t & 15) k) and
+// W^((16 b + c) k1) = W^(16 k1 b) W^(c k1).  Row r of TWL read 16 bytes at a
+// time as the products are made.
+template <bool CONJ>
+__device__ __forceinline__ void twiddle_lds(float (&zr)[16], float (&zi)[16], const float2 *twl, int r) {
+    const float4 *r4 = reinterpret_cast<const float4 *>(twl + r * TWL_S);
+#pragma unroll
+    for (int g = 0; g < 8; ++g) {
+        const float4 w = r4[g];
+        if (g > 0) cmul_tw<CONJ>(zr[2 * g], zi[2 * g], make_float2(w.x, w.y));  // entry 0 is 1
+        cmul_tw<CONJ>(zr[2 * g + 1], zi[2 * g + 1], make_float2(w.z, w.w));
+    }
+}
+// Copies TWL (global, twid + TWL_OFF) into the workgroup's LDS copy; the
+// caller passes a barrier before the first transform.
+__device__ __forceinline__ void twl_stage(float2 *twl, const float2 *twid, int tid, int nthreads) {
+    const float4 *src = reinterpret_cast<const float4 *>(twid + TWL_OFF);
+    float4 *dst = reinterpret_cast<float4 *>(twl);
+    for (int e = tid; e < TWL_ENTRIES / 2; e += nthreads) dst[e] = src[e];
+}
+constexpr int TW_GLOBAL = 0, TW_PREFETCH = 1, TW_LDS = 2;
+
 // Forward 4096-point DFT (e^{-2 pi i n k / 4096}) of the values held by the
 // 256 lanes of a workgroup.  In: lane t holds z[256 a + t], a = 0..15.  Out:
 // lane t holds Z[t + 256 k3], k3 = 0..15.  Three radix-16 passes with two LDS
 // exchanges through lds[0 .. 8192) floats.  Ends with the data in registers
 // and every lane past its last LDS read (callers may reuse lds after a
 // barrier).
-template <bool PF = false>
+// TWM: where the twiddles come from (TW_GLOBAL rows read at use, TW_PREFETCH
+// rows fetched ahead of each pass, TW_LDS the LDS copy of TWL at twid).
+template <int TWM = TW_GLOBAL>
 __device__ __forceinline__ void fft4096_forward(float (&zr)[16], float (&zi)[16], float *lds, const float2 *twid,
                                                 int tid) {
     float *Lr = lds, *Li = lds + NFFT;
+    constexpr bool PF = TWM == TW_PREFETCH;
     float4 tw[8];
     if (PF) twiddle_fetch(tw, twid + TW1_OFF + 16 * tid);
     dft16<-1>(zr, zi);
-    if (PF) twiddle_apply<false, true>(zr, zi, tw);
-    else twiddle_row<false, true>(zr, zi, twid + TW1_OFF + 16 * tid);
+    if (TWM == TW_LDS) {
+        twiddle_lds<false>(zr, zi, twid, tid >> 4);
+        twiddle_lds<false>(zr, zi, twid, 16 + (tid & 15));
+    } else if (PF) {
+        twiddle_apply<false, true>(zr, zi, tw);
+    } else {
+        twiddle_row<false, true>(zr, zi, twid + TW1_OFF + 16 * tid);
+    }
     {
         const int b = tid >> 4, c = tid & 15, w0 = 16 * b + c;
 #pragma unroll
@@ -380,7 +414,8 @@ __device__ __forceinline__ void fft4096_forward(float (&zr)[16], float (&zi)[16]
             zi[b] = Li[ad];
         }
         dft16<-1>(zr, zi);
-        if (PF) twiddle_apply<false, true>(zr, zi, tw);
+        if (TWM == TW_LDS) twiddle_lds<false>(zr, zi, twid, c);
+        else if (PF) twiddle_apply<false, true>(zr, zi, tw);
         else twiddle_row<false, true>(zr, zi, twid + TW2_OFF + 16 * c);
         __syncthreads();
         const int w1 = 272 * k1 + ((c + k1) & 15);
@@ -407,16 +442,18 @@ __device__ __forceinline__ void fft4096_forward(float (&zr)[16], float (&zi)[16]
 // Inverse of fft4096_forward without the 1/4096 factor (e^{+2 pi i n k /
 // 4096}): in the forward's output layout, out in its input layout.  Begins
 // with a barrier before its first LDS write.
-template <bool PF = false>
+template <int TWM = TW_GLOBAL>
 __device__ __forceinline__ void fft4096_inverse(float (&zr)[16], float (&zi)[16], float *lds, const float2 *twid,
                                                 int tid) {
     float *Lr = lds, *Li = lds + NFFT;
+    constexpr bool PF = TWM == TW_PREFETCH;
     float4 tw[8];
     {
         const int k1 = tid & 15, k2 = tid >> 4, r1 = 256 * k1 + 16 * ((k2 + k1) & 15) + k1;
         if (PF) twiddle_fetch(tw, twid + TW2_OFF + 16 * k2);
         dft16<1>(zr, zi);
-        if (PF) twiddle_apply<true, true>(zr, zi, tw);
+        if (TWM == TW_LDS) twiddle_lds<true>(zr, zi, twid, k2);
+        else if (PF) twiddle_apply<true, true>(zr, zi, tw);
         else twiddle_row<true, true>(zr, zi, twid + TW2_OFF + 16 * k2);
         __syncthreads();
 #pragma unroll
@@ -437,8 +474,16 @@ __device__ __forceinline__ void fft4096_inverse(float (&zr)[16], float (&zi)[16]
             zi[k2] = Li[ad];
         }
         dft16<1>(zr, zi);
-        if (PF) twiddle_apply<true, false>(zr, zi, tw);
-        else twiddle_row<true, false>(zr, zi, twid + TW3_OFF + 16 * tid);
+        if (TWM == TW_LDS) {
+            twiddle_lds<true>(zr, zi, twid, k1);  // W^(16 k1 b)
+            const float2 wc = twid[(16 + c) * TWL_S + k1];  // W^(c k1), the lane's constant
+#pragma unroll
+            for (int b = 0; b < 16; ++b) cmul_tw<true>(zr[b], zi[b], wc);
+        } else if (PF) {
+            twiddle_apply<true, false>(zr, zi, tw);
+        } else {
+            twiddle_row<true, false>(zr, zi, twid + TW3_OFF + 16 * tid);
+        }
         __syncthreads();
         const int r0 = 272 * k1 + c;
 #pragma unroll
