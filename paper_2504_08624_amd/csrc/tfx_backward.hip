@@ -110,9 +110,9 @@ __global__ __launch_bounds__(WG, 3) void sos_bwd_kernel(BArgs a) {
         twl_stage(s_twl, a.twid, tid, WG);
         load_pair_block(zr, zi, xA, xB, n0 - FFT_DISCARD, a.N, a.N, tid);
         __syncthreads();  // the twiddles
-        fft4096_forward<TW_LDS>(zr, zi, stg_all, s_twl, tid);
+        fft4096_forward(zr, zi, stg_all, s_twl, tid);
         spectrum_product(zr, zi, a.hspec, tid, false);
-        fft4096_inverse<TW_LDS>(zr, zi, stg_all, s_twl, tid);
+        fft4096_inverse(zr, zi, stg_all, s_twl, tid);
         __syncthreads();  // the FFT buffers become the two staging areas
 #pragma unroll
         for (int q = 4; q < 16; ++q) {
@@ -402,14 +402,14 @@ __global__ __launch_bounds__(WG) void fir_gh_part_kernel(GhArgs a) {
     // g tile [n0, n0 + 3072), zero past it
     load_pair_block(zr, zi, a.g + chA * a.ldg, chB < a.C ? a.g + chB * a.ldg : nullptr, n0, a.N, n0 + T, tid);
     __syncthreads();  // the twiddle table
-    fft4096_forward<TW_LDS>(zr, zi, lds, s_twl, tid);
+    fft4096_forward(zr, zi, lds, s_twl, tid);
 #pragma unroll
     for (int k = 0; k < 16; ++k) wspec[tid + 256 * k] = make_float2(zr[k], zi[k]);
     // x block [n0 - 1024 - k0, n0 + 3072 - k0)
     load_pair_block(zr, zi, a.x + chA * a.ldx, chB < a.C ? a.x + chB * a.ldx : nullptr, n0 - FFT_DISCARD - k0,
                     a.N, a.N, tid);
     __syncthreads();  // the first FFT's last LDS reads
-    fft4096_forward<TW_LDS>(zr, zi, lds, s_twl, tid);
+    fft4096_forward(zr, zi, lds, s_twl, tid);
 #pragma unroll
     for (int k = 0; k < 16; ++k) {  // conj(W) Z
         const float2 w = wspec[tid + 256 * k];
@@ -418,7 +418,7 @@ __global__ __launch_bounds__(WG) void fir_gh_part_kernel(GhArgs a) {
         zr[k] = r;
         zi[k] = i;
     }
-    fft4096_inverse<TW_LDS>(zr, zi, lds, s_twl, tid);
+    fft4096_inverse(zr, zi, lds, s_twl, tid);
     // lane tid holds d = 256 q + tid; lag k = k0 + 1024 - d
     float *out = a.part + ((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * FFT_PART;
 #pragma unroll
@@ -471,7 +471,7 @@ __global__ __launch_bounds__(WG) void fir_bwd_kernel(FirBwdArgs a) {
         asm volatile("" ::: "memory");
         __syncthreads();  // the previous tile's last LDS reads
         load_pair_block(zr, zi, a.g + chA * a.ldg, hasB ? a.g + chB * a.ldg : nullptr, n0, a.N, a.N, tid);
-        fft4096_forward<TW_LDS>(zr, zi, lds, s_twl, tid);
+        fft4096_forward(zr, zi, lds, s_twl, tid);
         if (a.want_gh) {
             float br[16], bi[16];
 #pragma unroll
@@ -481,7 +481,7 @@ __global__ __launch_bounds__(WG) void fir_bwd_kernel(FirBwdArgs a) {
             }
             load_pair_block(zr, zi, a.x + chA * a.ldx, hasB ? a.x + chB * a.ldx : nullptr, n0, a.N, n0 + T, tid);
             __syncthreads();  // the B transform's last LDS reads
-            fft4096_forward<TW_LDS>(zr, zi, lds, s_twl, tid);
+            fft4096_forward(zr, zi, lds, s_twl, tid);
 #pragma unroll
             for (int k = 0; k < 16; ++k) {  // += conj(X) B
                 ar[k] = fmaf(zr[k], br[k], fmaf(zi[k], bi[k], ar[k]));
@@ -491,7 +491,7 @@ __global__ __launch_bounds__(WG) void fir_bwd_kernel(FirBwdArgs a) {
             }
         }
         spectrum_product(zr, zi, a.hspec, tid, true);
-        fft4096_inverse<TW_LDS>(zr, zi, lds, s_twl, tid);
+        fft4096_inverse(zr, zi, lds, s_twl, tid);
         store_pair_tile<0>(zr, zi, a.gx + chA * a.ldgx, hasB ? a.gx + chB * a.ldgx : nullptr, n0, a.N, tid);
     }
     if (a.want_gh) {

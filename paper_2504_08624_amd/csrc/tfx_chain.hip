@@ -295,9 +295,8 @@ __device__ void tz_tile(const KArgs &a, float *lds, int64_t pair, int64_t n0, in
 // 1025) filters its own input block, shifted by 1025 p samples (earlier for
 // the convolution, later for the correlation); the products with the
 // partition spectra are summed in the frequency domain and inverted once.
-// TWM: the transforms' twiddle source (TW_LDS: tw is the workgroup's LDS copy
-// of the tables, staged by the caller; otherwise tw is a.twid).
-template <bool PARTS, int TWM = TW_GLOBAL>
+// tw: the workgroup's LDS copy of the twiddle table, staged by the caller.
+template <bool PARTS>
 __device__ void fft_block(const KArgs &a, float *lds, int64_t pair, int64_t n0, int tid, float (&zr)[16],
                           float (&zi)[16], const float2 *tw) {
     const int64_t chA = 2 * pair, chB = 2 * pair + 1;
@@ -309,7 +308,7 @@ __device__ void fft_block(const KArgs &a, float *lds, int64_t pair, int64_t n0, 
     const int64_t base = a.correlate ? n0 : n0 - FFT_DISCARD;
     if (!PARTS) {
         load_pair_block(zr, zi, xA, xB, base, a.N, a.N, tid, hA, hB, hlen);
-        fft4096_forward<TWM>(zr, zi, lds, tw, tid);
+        fft4096_forward(zr, zi, lds, tw, tid);
         spectrum_product(zr, zi, a.hspec, tid, a.correlate != 0);
     } else {
         // spectrum accumulator: lane t owns bins t + 256 k3 (no sharing, no
@@ -320,7 +319,7 @@ __device__ void fft_block(const KArgs &a, float *lds, int64_t pair, int64_t n0, 
             const int64_t shift = (int64_t)FFT_PART * p;
             __syncthreads();  // the previous pass's last LDS reads
             load_pair_block(zr, zi, xA, xB, a.correlate ? base + shift : base - shift, a.N, a.N, tid, hA, hB, hlen);
-            fft4096_forward<TWM>(zr, zi, lds, tw, tid);
+            fft4096_forward(zr, zi, lds, tw, tid);
             const float2 *hs = a.hspec + (int64_t)p * NFFT;
             const float sg = a.correlate ? -1.f : 1.f;
 #pragma unroll 4
@@ -340,7 +339,7 @@ __device__ void fft_block(const KArgs &a, float *lds, int64_t pair, int64_t n0, 
             zi[k3] = s.y;
         }
     }
-    fft4096_inverse<TWM>(zr, zi, lds, tw, tid);
+    fft4096_inverse(zr, zi, lds, tw, tid);
     if (a.correlate) {  // move the tile to a = 4..15 like the convolution case
 #pragma unroll
         for (int q = 15; q >= 4; --q) {
@@ -665,7 +664,7 @@ __global__ __launch_bounds__(WG, (chain_min_blocks<FIRM, HAS_SOS, HIQ, CASC, STO
         direct_tile(a, stg, c.ch, c.valid, c.gl, n0, v);
     } else {  // FIR_FFT
         float zr[16], zi[16];
-        fft_block<FIRM == FIR_FFT_PARTS, TW_LDS>(a, lds, pair, n0, c.tid, zr, zi, s_twl);
+        fft_block<FIRM == FIR_FFT_PARTS>(a, lds, pair, n0, c.tid, zr, zi, s_twl);
         if (!HAS_SOS) {
             const int64_t chA = 2 * pair, chB = chA + 1;
             store_pair_tile<4>(zr, zi, a.y + chA * a.ldy, chB < a.C ? a.y + chB * a.ldy : nullptr, n0, a.N, c.tid);
@@ -827,7 +826,7 @@ __global__ __launch_bounds__(WG, 4) void chain_mc_kernel(KArgs a) {
         float zr[16], zi[16];
         twl_stage(s_twl, a.twid, tid, WG);
         __syncthreads();
-        fft_block<false, TW_LDS>(a, lds, pair, n0, tid, zr, zi, s_twl);
+        fft_block<false>(a, lds, pair, n0, tid, zr, zi, s_twl);
         __syncthreads();  // the FFT buffers become X
 #pragma unroll
         for (int q = 4; q < 16; ++q) {

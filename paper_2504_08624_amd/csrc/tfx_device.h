@@ -309,48 +309,13 @@ __device__ __forceinline__ void cmul_tw(float &r, float &i, float2 w) {
 // are one lane constant plus the loop's immediate step, minus 256 (or 16)
 // once the rotation wraps, so an access costs a compare and a select.
 //
-// Twiddles come from three per-lane tables (fp32, built in FP64 by the
-// prepare step), each lane reading 16 consecutive entries as float4:
-//   TW1[t][k]       = w^(t k)            (forward pass 1, lane t = tid)
-//   TW2[c][k]       = w^(16 c k)         (forward pass 2 row c; inverse pass 1 row k2)
-//   TW3[k1][c][b]   = w^((16 b + c) k1)  (inverse pass 2, lane (k1, c))
-// with w = e^{-2 pi i / 4096}; the inverse uses the conjugates.
-// ONE0: the row's entry 0 is 1 (TW1, TW2) and is skipped.
-template <bool CONJ, bool ONE0>
-__device__ __forceinline__ void twiddle_row(float (&zr)[16], float (&zi)[16], const float2 *row) {
-    const float4 *r4 = reinterpret_cast<const float4 *>(row);
-#pragma unroll
-    for (int g = 0; g < 8; ++g) {
-        const float4 w = r4[g];
-        if (g > 0 || !ONE0) cmul_tw<CONJ>(zr[2 * g], zi[2 * g], make_float2(w.x, w.y));
-        cmul_tw<CONJ>(zr[2 * g + 1], zi[2 * g + 1], make_float2(w.z, w.w));
-    }
-}
-
-// The same row fetched ahead (twiddle_fetch, then a scheduling fence so the
-// loads are issued before the pass's arithmetic) and applied later: the
-// transforms' PF form, for kernels with registers to spare (32 more).
-__device__ __forceinline__ void twiddle_fetch(float4 (&w)[8], const float2 *row) {
-    const float4 *r4 = reinterpret_cast<const float4 *>(row);
-#pragma unroll
-    for (int g = 0; g < 8; ++g) w[g] = r4[g];
-    __builtin_amdgcn_sched_barrier(0);
-}
-template <bool CONJ, bool ONE0>
-__device__ __forceinline__ void twiddle_apply(float (&zr)[16], float (&zi)[16], const float4 (&w)[8]) {
-#pragma unroll
-    for (int g = 0; g < 8; ++g) {
-        if (g > 0 || !ONE0) cmul_tw<CONJ>(zr[2 * g], zi[2 * g], make_float2(w[g].x, w[g].y));
-        cmul_tw<CONJ>(zr[2 * g + 1], zi[2 * g + 1], make_float2(w[g].z, w[g].w));
-    }
-}
-
-// The LDS form (TW_LDS): every twiddle from the 32 rows of TWL copied into
-// LDS by the workgroup (twl_stage), since global twiddle loads left the
-// transforms waiting on L2 at every pass.  TW1 and TW3 are formed from two
-// factors each: W^(t k) = W^(16 (t >> 4) k) W^((t & 15) k) and
-// W^((16 b + c) k1) = W^(16 k1 b) W^(c k1).  Row r of TWL read 16 bytes at a
-// time as the products are made.
+// Twiddles (w = e^{-2 pi i / 4096}; the inverse uses the conjugates) come
+// from the 32 rows of TWL, copied into LDS by the workgroup (twl_stage):
+// global twiddle loads left the transforms waiting on L2 at every pass.  Pass
+// twiddles that are not a row entry are the product of two:
+// w^(t k) = w^(16 (t >> 4) k) w^((t & 15) k) and
+// w^((16 b + c) k1) = w^(16 k1 b) w^(c k1).  Row r is read 16 bytes at a
+// time; its entry 0 is 1 and is skipped.
 template <bool CONJ>
 __device__ __forceinline__ void twiddle_lds(float (&zr)[16], float (&zi)[16], const float2 *twl, int r) {
     const float4 *r4 = reinterpret_cast<const float4 *>(twl + r * TWL_S);
@@ -361,14 +326,13 @@ __device__ __forceinline__ void twiddle_lds(float (&zr)[16], float (&zi)[16], co
         cmul_tw<CONJ>(zr[2 * g + 1], zi[2 * g + 1], make_float2(w.z, w.w));
     }
 }
-// Copies TWL (global, twid + TWL_OFF) into the workgroup's LDS copy; the
-// caller passes a barrier before the first transform.
+// Copies TWL (the workspace's twiddle region) into the workgroup's LDS copy;
+// the caller passes a barrier before the first transform.
 __device__ __forceinline__ void twl_stage(float2 *twl, const float2 *twid, int tid, int nthreads) {
-    const float4 *src = reinterpret_cast<const float4 *>(twid + TWL_OFF);
+    const float4 *src = reinterpret_cast<const float4 *>(twid);
     float4 *dst = reinterpret_cast<float4 *>(twl);
     for (int e = tid; e < TWL_ENTRIES / 2; e += nthreads) dst[e] = src[e];
 }
-constexpr int TW_GLOBAL = 0, TW_PREFETCH = 1, TW_LDS = 2;
 
 // Forward 4096-point DFT (e^{-2 pi i n k / 4096}) of the values held by the
 // 256 lanes of a workgroup.  In: lane t holds z[256 a + t], a = 0..15.  Out:
@@ -376,24 +340,13 @@ constexpr int TW_GLOBAL = 0, TW_PREFETCH = 1, TW_LDS = 2;
 // exchanges through lds[0 .. 8192) floats.  Ends with the data in registers
 // and every lane past its last LDS read (callers may reuse lds after a
 // barrier).
-// TWM: where the twiddles come from (TW_GLOBAL rows read at use, TW_PREFETCH
-// rows fetched ahead of each pass, TW_LDS the LDS copy of TWL at twid).
-template <int TWM = TW_GLOBAL>
-__device__ __forceinline__ void fft4096_forward(float (&zr)[16], float (&zi)[16], float *lds, const float2 *twid,
+// twl: the workgroup's LDS copy of TWL.
+__device__ __forceinline__ void fft4096_forward(float (&zr)[16], float (&zi)[16], float *lds, const float2 *twl,
                                                 int tid) {
     float *Lr = lds, *Li = lds + NFFT;
-    constexpr bool PF = TWM == TW_PREFETCH;
-    float4 tw[8];
-    if (PF) twiddle_fetch(tw, twid + TW1_OFF + 16 * tid);
     dft16<-1>(zr, zi);
-    if (TWM == TW_LDS) {
-        twiddle_lds<false>(zr, zi, twid, tid >> 4);
-        twiddle_lds<false>(zr, zi, twid, 16 + (tid & 15));
-    } else if (PF) {
-        twiddle_apply<false, true>(zr, zi, tw);
-    } else {
-        twiddle_row<false, true>(zr, zi, twid + TW1_OFF + 16 * tid);
-    }
+    twiddle_lds<false>(zr, zi, twl, tid >> 4);
+    twiddle_lds<false>(zr, zi, twl, 16 + (tid & 15));
     {
         const int b = tid >> 4, c = tid & 15, w0 = 16 * b + c;
 #pragma unroll
@@ -403,7 +356,6 @@ __device__ __forceinline__ void fft4096_forward(float (&zr)[16], float (&zi)[16]
             Li[ad] = zi[k1];
         }
     }
-    if (PF) twiddle_fetch(tw, twid + TW2_OFF + 16 * (tid & 15));
     __syncthreads();
     {
         const int k1 = tid >> 4, c = tid & 15, r0 = 272 * k1 + c;
@@ -414,9 +366,7 @@ __device__ __forceinline__ void fft4096_forward(float (&zr)[16], float (&zi)[16]
             zi[b] = Li[ad];
         }
         dft16<-1>(zr, zi);
-        if (TWM == TW_LDS) twiddle_lds<false>(zr, zi, twid, c);
-        else if (PF) twiddle_apply<false, true>(zr, zi, tw);
-        else twiddle_row<false, true>(zr, zi, twid + TW2_OFF + 16 * c);
+        twiddle_lds<false>(zr, zi, twl, c);
         __syncthreads();
         const int w1 = 272 * k1 + ((c + k1) & 15);
 #pragma unroll
@@ -442,19 +392,13 @@ __device__ __forceinline__ void fft4096_forward(float (&zr)[16], float (&zi)[16]
 // Inverse of fft4096_forward without the 1/4096 factor (e^{+2 pi i n k /
 // 4096}): in the forward's output layout, out in its input layout.  Begins
 // with a barrier before its first LDS write.
-template <int TWM = TW_GLOBAL>
-__device__ __forceinline__ void fft4096_inverse(float (&zr)[16], float (&zi)[16], float *lds, const float2 *twid,
+__device__ __forceinline__ void fft4096_inverse(float (&zr)[16], float (&zi)[16], float *lds, const float2 *twl,
                                                 int tid) {
     float *Lr = lds, *Li = lds + NFFT;
-    constexpr bool PF = TWM == TW_PREFETCH;
-    float4 tw[8];
     {
         const int k1 = tid & 15, k2 = tid >> 4, r1 = 256 * k1 + 16 * ((k2 + k1) & 15) + k1;
-        if (PF) twiddle_fetch(tw, twid + TW2_OFF + 16 * k2);
         dft16<1>(zr, zi);
-        if (TWM == TW_LDS) twiddle_lds<true>(zr, zi, twid, k2);
-        else if (PF) twiddle_apply<true, true>(zr, zi, tw);
-        else twiddle_row<true, true>(zr, zi, twid + TW2_OFF + 16 * k2);
+        twiddle_lds<true>(zr, zi, twl, k2);
         __syncthreads();
 #pragma unroll
         for (int c = 0; c < 16; ++c) {
@@ -463,7 +407,6 @@ __device__ __forceinline__ void fft4096_inverse(float (&zr)[16], float (&zi)[16]
             Li[ad] = zi[c];
         }
     }
-    if (PF) twiddle_fetch(tw, twid + TW3_OFF + 16 * tid);
     __syncthreads();
     {
         const int k1 = tid >> 4, c = tid & 15, w1 = 272 * k1 + ((c + k1) & 15);
@@ -474,16 +417,10 @@ __device__ __forceinline__ void fft4096_inverse(float (&zr)[16], float (&zi)[16]
             zi[k2] = Li[ad];
         }
         dft16<1>(zr, zi);
-        if (TWM == TW_LDS) {
-            twiddle_lds<true>(zr, zi, twid, k1);  // W^(16 k1 b)
-            const float2 wc = twid[(16 + c) * TWL_S + k1];  // W^(c k1), the lane's constant
+        twiddle_lds<true>(zr, zi, twl, k1);  // w^(16 k1 b)
+        const float2 wc = twl[(16 + c) * TWL_S + k1];  // w^(c k1), the lane's constant
 #pragma unroll
-            for (int b = 0; b < 16; ++b) cmul_tw<true>(zr[b], zi[b], wc);
-        } else if (PF) {
-            twiddle_apply<true, false>(zr, zi, tw);
-        } else {
-            twiddle_row<true, false>(zr, zi, twid + TW3_OFF + 16 * tid);
-        }
+        for (int b = 0; b < 16; ++b) cmul_tw<true>(zr[b], zi[b], wc);
         __syncthreads();
         const int r0 = 272 * k1 + c;
 #pragma unroll

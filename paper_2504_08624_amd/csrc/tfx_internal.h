@@ -34,10 +34,8 @@ constexpr int FFT_PART = FFT_DISCARD + 1;  // taps per partition of a long filte
 // rows 16 + c hold W^(c k) (W = e^{-2 pi i / 4096}, k < 16), each padded to
 // TWL_S entries so that 16 lanes reading 16 different rows hit 64 banks.
 constexpr int TWL_S = 18, TWL_ROWS = 32, TWL_ENTRIES = TWL_ROWS * TWL_S;
-// fp32 twiddle tables of the FFT, one region: TW1 [256][16], TW2 [16][16],
-// TW3 [16][16][16], and TWL [32][TWL_S] (float2 entries)
-constexpr int TW1_OFF = 0, TW2_OFF = NFFT, TW3_OFF = NFFT + 256, TWL_OFF = 2 * NFFT + 256;
-constexpr int TWID_ENTRIES = TWL_OFF + TWL_ENTRIES;
+// The fp32 twiddle region of the workspace holds TWL alone (float2 entries).
+constexpr int TWID_ENTRIES = TWL_ENTRIES;
 __host__ __device__ constexpr int fft_parts(int M) { return (M + FFT_PART - 1) / FFT_PART; }
 // One 16384-point FFT per block of 8192 outputs (tfx_fft16k.hip): filters of
 // up to 8193 taps.

@@ -345,30 +345,17 @@ __global__ void merge_taps_kernel(MergeArgs a) {
 }
 
 // Entry i of the twiddle tables (i < 4096), each e^{-2 pi i e / 4096} for an
-// exact integer e mod 4096, in FP64 and rounded once: tw64[i] (e = i), and
-// the fp32 per-lane tables of the FFT kernels, TW1[t][k] (e = t k), TW3[k1][c][b]
-// (e = (16 b + c) k1), for i < 256 TW2[c][k] (e = 16 c k) and for i < 576 the
-// padded LDS tables TWL.
+// exact integer e mod 4096, in FP64 and rounded once: tw64[i] (e = i) and,
+// for i < TWL_ENTRIES, the padded fp32 table TWL of the FFT kernels.
 __device__ void write_twiddle(float2 *twid, double2 *tw64, int i) {
     double sn, cs;
     sincospi(-2.0 * (double)i / NFFT, &sn, &cs);
     tw64[i] = make_double2(cs, sn);
-    const int e1 = ((i >> 4) * (i & 15)) & (NFFT - 1);
-    sincospi(-2.0 * (double)e1 / NFFT, &sn, &cs);
-    twid[TW1_OFF + i] = make_float2((float)cs, (float)sn);
-    const int e3 = ((16 * (i & 15) + ((i >> 4) & 15)) * (i >> 8)) & (NFFT - 1);
-    sincospi(-2.0 * (double)e3 / NFFT, &sn, &cs);
-    twid[TW3_OFF + i] = make_float2((float)cs, (float)sn);
-    if (i < 256) {
-        const int e2 = (16 * (i >> 4) * (i & 15)) & (NFFT - 1);
-        sincospi(-2.0 * (double)e2 / NFFT, &sn, &cs);
-        twid[TW2_OFF + i] = make_float2((float)cs, (float)sn);
-    }
     if (i < TWL_ENTRIES) {  // TWL[r][k]: e = 16 r k (r < 16), (r - 16) k; pads zero
         const int r = i / TWL_S, k = i % TWL_S;
         const int eL = ((r < 16 ? 16 * r : r - 16) * k) & (NFFT - 1);
         sincospi(-2.0 * (double)eL / NFFT, &sn, &cs);
-        twid[TWL_OFF + i] = k < 16 ? make_float2((float)cs, (float)sn) : make_float2(0.f, 0.f);
+        twid[i] = k < 16 ? make_float2((float)cs, (float)sn) : make_float2(0.f, 0.f);
     }
 }
 
