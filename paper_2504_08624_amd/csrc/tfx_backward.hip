@@ -51,6 +51,7 @@ struct BArgs {
     uint32_t *hdr;
     int64_t ntiles, cpad;
     int32_t vecf, vecg, veco;
+    uint32_t xcd_ks;  // block order (xcd_order)
 };
 
 // TDF-II section over a lane's chunk from state (s1, s2), in place.
@@ -86,9 +87,10 @@ __global__ __launch_bounds__(WG, 3) void sos_bwd_kernel(BArgs a) {
     const int tid = threadIdx.x, lane = tid & 63, grp = tid / GL, gl = tid % GL, gw = gl >> 6;
     if (tid == 0) s_epoch = load_epoch(a.hdr, HDR_EPOCH);
     const uint64_t npairs = (uint64_t)(a.cpad / 2);
-    const int64_t pos = (int64_t)(blockIdx.x / npairs);  // reverse-time processing position
+    const uint64_t id = xcd_order(blockIdx.x, gridDim.x, a.xcd_ks);
+    const int64_t pos = (int64_t)(id / npairs);  // reverse-time processing position
     const int64_t tile = a.ntiles - 1 - pos;
-    const int64_t pair = (int64_t)(blockIdx.x % npairs);
+    const int64_t pair = (int64_t)(id % npairs);
     const int64_t ch = 2 * pair + grp;
     const bool valid = ch < a.C;
     const int64_t n0 = tile * T;
@@ -437,8 +439,9 @@ __global__ __launch_bounds__(WG) void fir_gh_part_kernel(GhArgs a) {
 //   sum_{m in tile} x[m] g[m + k] = Re IFFT(conj(FFT(X)) FFT(B))[k], k <= 1024,
 // for both channels of the pair at once (the two packed channels' cross
 // terms are purely imaginary, so the real part is the sum of the two
-// correlations).  One FFT of B serves both.  A workgroup walks tiles
-// blockIdx.x, + gridDim.x, ... and sums conj(FFT(X)) FFT(B) over them in
+// correlations).  One FFT of B serves both.  A workgroup walks the (tile,
+// pair) items xcd_order maps blockIdx.x, + gridDim.x, ... to (neighbouring
+// tiles on one XCD) and sums conj(FFT(X)) FFT(B) over them in
 // fp32 registers (lane t keeps bins t + 256 k3); its sum is written once, and
 // FP64 reductions in a fixed order plus one inverse DFT per lag give dL/dh.
 struct FirBwdArgs {
@@ -449,6 +452,7 @@ struct FirBwdArgs {
     const float2 *twid, *hspec;
     float2 *spart;  // [workgroup][16][256] summed spectra, bin 256 k3 + t at [k3][t]
     int32_t want_gh;
+    uint32_t xcd_ks;  // item order (xcd_order over the item index)
 };
 
 __global__ __launch_bounds__(WG) void fir_bwd_kernel(FirBwdArgs a) {
@@ -460,7 +464,8 @@ __global__ __launch_bounds__(WG) void fir_bwd_kernel(FirBwdArgs a) {
     float ar[16], ai[16];
 #pragma unroll
     for (int k = 0; k < 16; ++k) ar[k] = ai[k] = 0.f;
-    for (int64_t it = blockIdx.x; it < nitems; it += gridDim.x) {
+    for (int64_t ip = blockIdx.x; ip < nitems; ip += gridDim.x) {
+        const int64_t it = xcd_order((uint32_t)ip, (uint32_t)nitems, a.xcd_ks);
         const int64_t tile = it / npairs, pair = it % npairs;
         const int64_t chA = 2 * pair, chB = chA + 1;
         const int64_t n0 = tile * T;
@@ -732,6 +737,7 @@ hipError_t launch_backward(const BwdPlan &bp) {
         b.vecf = (reinterpret_cast<uintptr_t>(b.f) % 16 == 0 && b.ldf % 4 == 0) ? 1 : 0;
         b.vecg = (reinterpret_cast<uintptr_t>(b.g) % 16 == 0 && b.ldg % 4 == 0) ? 1 : 0;
         b.veco = (reinterpret_cast<uintptr_t>(b.gf) % 16 == 0 && b.ldo % 4 == 0) ? 1 : 0;
+        b.xcd_ks = xcd_window();
         const size_t dyn = (size_t)p.S * sizeof(SecLds) +
                            std::max((size_t)p.S * GROUPS * GL * sizeof(float2),
                                     fuse ? sizeof(float2) * TWL_ENTRIES : (size_t)0);
@@ -788,6 +794,7 @@ hipError_t launch_backward(const BwdPlan &bp) {
         fb.hspec = reinterpret_cast<const float2 *>(ws + lay.fwd.hspec);
         fb.spart = reinterpret_cast<float2 *>(ws + lay.part_gh);
         fb.want_gh = any ? 1 : 0;
+        fb.xcd_ks = lay.spec_wg % 8 == 0 ? xcd_window() : 0;  // item ip runs on XCD ip % 8
         hipLaunchKernelGGL(fir_bwd_kernel, dim3((unsigned)lay.spec_wg), dim3(WG), 0, st, fb);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         if (!any) return hipSuccess;

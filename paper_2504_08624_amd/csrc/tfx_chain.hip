@@ -47,6 +47,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <type_traits>
 
 #include "tfx_device.h"
@@ -109,6 +110,7 @@ struct KArgs {
     int32_t tzQ;          // its frame lags Q
     const float *hist;    // streaming: the M - 1 FIR inputs before the block, [C][M - 1] (null = zeros)
     int64_t ldh;          // M - 1
+    uint32_t xcd_ks;      // block order: xcd_order's log2 K (0 = block ids in order)
 };
 
 // FIR input x[ch][n] of the block, n < N, with the streaming history for
@@ -625,7 +627,6 @@ __global__ __launch_bounds__(WG, (chain_min_blocks<FIRM, HAS_SOS, HIQ, CASC, STO
     c.grp = c.tid / GL;
     c.gl = c.tid % GL;
     c.gw = c.gl >> 6;
-    const uint64_t id = blockIdx.x;
     c.epoch = 0;
     if (FFT) {
         // the section tables are staged once the FIR is done: its twiddles
@@ -645,6 +646,7 @@ __global__ __launch_bounds__(WG, (chain_min_blocks<FIRM, HAS_SOS, HIQ, CASC, STO
         c.epoch = s_epoch;
     }
     const uint64_t npairs = (uint64_t)(a.cpad / 2);
+    const uint64_t id = xcd_order(blockIdx.x, gridDim.x, a.xcd_ks);
     c.tile = (int64_t)(id / npairs);
     const int64_t pair = (int64_t)(id % npairs);
     c.ch = 2 * pair + c.grp;
@@ -815,8 +817,9 @@ __global__ __launch_bounds__(WG, 4) void chain_mc_kernel(KArgs a) {
     const int tid = threadIdx.x;
     if (tid == 0) s_epoch = load_epoch(a.hdr, HDR_EPOCH);
     const uint64_t npairs = (uint64_t)(a.cpad / 2);
-    const int64_t tile = (int64_t)(blockIdx.x / npairs);
-    const int64_t pair = (int64_t)(blockIdx.x % npairs);
+    const uint64_t id = xcd_order(blockIdx.x, gridDim.x, a.xcd_ks);
+    const int64_t tile = (int64_t)(id / npairs);
+    const int64_t pair = (int64_t)(id % npairs);
     const int64_t n0 = tile * T;
     const int64_t rem = a.N - n0;  // samples of the tile inside the signal (> 0)
     float *X = lds;                // [192][MC_XS]: sample j of channel g at g * 96 * 36 + 36 (j / 32) + j % 32
@@ -962,6 +965,21 @@ static hipError_t launch_main(const KArgs &k, int64_t nblocks, hipStream_t st) {
     return launch_variants<F, S, false>(k, nblocks, st);
 }
 
+// xcd_order's log2 K for the current device: 32 block ids per XCD on the
+// whole 256-CU chip (32 CUs per XCD, each holding at least one block), block
+// ids in order on anything smaller (a partitioned device).
+uint32_t xcd_window() {
+    static std::atomic<int> cus[64];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 0;
+    int n = cus[dev].load(std::memory_order_relaxed);
+    if (n == 0) {
+        if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) n = -1;
+        cus[dev].store(n, std::memory_order_relaxed);
+    }
+    return n >= 256 ? 5u : 0u;
+}
+
 int32_t merged_taps(const StageList &f) {
     int32_t Mtot = 0;
     for (int i = 0; i < f.n; ++i) Mtot += (i == 0) ? f.len[i] : f.len[i] - 1;
@@ -1067,6 +1085,7 @@ hipError_t launch_run(const ChainPlan &p) {
     k.mc = reinterpret_cast<const McTab *>(ws + lay.mc);
     k.hist = Mtot > 1 ? p.hist_in : nullptr;
     k.ldh = Mtot > 1 ? Mtot - 1 : 0;
+    k.xcd_ks = xcd_window();
     const int64_t nblocks = (lay.cpad / 2) * k.ntiles;
     const bool s = p.S > 0;
     if (tz_fused) {
@@ -1116,6 +1135,7 @@ hipError_t launch_fir_pass(const ChainPlan &p, const WsLayout &lay, const float 
     k.twid = reinterpret_cast<const float2 *>(ws + lay.twid);
     k.hspec = reinterpret_cast<const float2 *>(ws + lay.hspec);
     k.nparts = fft_parts(Mtot);
+    k.xcd_ks = xcd_window();
     const int64_t nblocks = (lay.cpad / 2) * lay.ntiles;
     if (p.fir_mode == FIR_FFT && k.nparts > 1) return launch_main<FIR_FFT_PARTS, false>(k, nblocks, p.stream);
     return p.fir_mode == FIR_FFT ? launch_main<FIR_FFT, false>(k, nblocks, p.stream)

@@ -43,6 +43,22 @@ __device__ __forceinline__ void advance_epoch(uint32_t *hdr) {
     }
 }
 
+// Logical block id of block b for L2 reuse across the chip's 8 XCDs, which
+// take block ids round robin (block b runs on XCD b % 8) and each have their
+// own L2.  Within every window of 8 K block ids (K = 2^ks), XCD x takes the
+// K consecutive logical ids x K .. x K + K - 1, so neighbouring tiles of a
+// channel pair, whose input blocks overlap, read through one L2; ks = 0 and
+// the last, partial window keep b.  The look-back stays free of deadlock
+// while an XCD can hold K blocks at once: if every resident block waited,
+// the lowest unfinished logical tile would not be resident, so its XCD
+// would be full of unfinished blocks dispatched before it, all from its own
+// window (earlier windows' blocks have lower logical ids) -- at most K - 1.
+// (readfirstlane keeps the result in scalar registers.)
+__device__ __forceinline__ uint32_t xcd_order(uint32_t b, uint32_t nblocks, uint32_t ks) {
+    const uint32_t W = 8u << ks, w0 = b & ~(W - 1u), r = b & (W - 1u);
+    return __builtin_amdgcn_readfirstlane(w0 + W > nblocks ? b : w0 + ((r & 7u) << ks) + (r >> 3));
+}
+
 // Lanes 0, 1 of a wave store the tagged pair (f0, f1) (wave-uniform) into
 // slot 0 (aggregate) or 1 (inclusive prefix) of record r.
 __device__ __forceinline__ void publish(uint64_t *recs, int64_t r, int slot, uint32_t epoch, float f0, float f1,
