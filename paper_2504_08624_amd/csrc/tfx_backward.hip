@@ -737,7 +737,7 @@ hipError_t launch_backward(const BwdPlan &bp) {
         b.vecf = (reinterpret_cast<uintptr_t>(b.f) % 16 == 0 && b.ldf % 4 == 0) ? 1 : 0;
         b.vecg = (reinterpret_cast<uintptr_t>(b.g) % 16 == 0 && b.ldg % 4 == 0) ? 1 : 0;
         b.veco = (reinterpret_cast<uintptr_t>(b.gf) % 16 == 0 && b.ldo % 4 == 0) ? 1 : 0;
-        b.xcd_ks = xcd_window();
+        b.xcd_ks = xcd_window(npairs);
         const size_t dyn = (size_t)p.S * sizeof(SecLds) +
                            std::max((size_t)p.S * GROUPS * GL * sizeof(float2),
                                     fuse ? sizeof(float2) * TWL_ENTRIES : (size_t)0);
@@ -794,7 +794,7 @@ hipError_t launch_backward(const BwdPlan &bp) {
         fb.hspec = reinterpret_cast<const float2 *>(ws + lay.fwd.hspec);
         fb.spart = reinterpret_cast<float2 *>(ws + lay.part_gh);
         fb.want_gh = any ? 1 : 0;
-        fb.xcd_ks = lay.spec_wg % 8 == 0 ? xcd_window() : 0;  // item ip runs on XCD ip % 8
+        fb.xcd_ks = lay.spec_wg % 8 == 0 ? xcd_window(npairs) : 0;  // item ip runs on XCD ip % 8
         hipLaunchKernelGGL(fir_bwd_kernel, dim3((unsigned)lay.spec_wg), dim3(WG), 0, st, fb);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         if (!any) return hipSuccess;

@@ -965,10 +965,13 @@ static hipError_t launch_main(const KArgs &k, int64_t nblocks, hipStream_t st) {
     return launch_variants<F, S, false>(k, nblocks, st);
 }
 
-// xcd_order's log2 K for the current device: 32 block ids per XCD on the
-// whole 256-CU chip (32 CUs per XCD, each holding at least one block), block
-// ids in order on anything smaller (a partitioned device).
-uint32_t xcd_window() {
+// xcd_order's log2 K for the current device and a grid of npairs channel
+// pairs per tile: 32 block ids per XCD on the whole 256-CU chip (32 CUs per
+// XCD, each holding at least one block).  Block ids stay in order on anything
+// smaller (a partitioned device), and when npairs is a multiple of 8: then
+// every tile of pair p already runs on XCD p % 8.
+uint32_t xcd_window(int64_t npairs) {
+    if (npairs % 8 == 0) return 0;
     static std::atomic<int> cus[64];
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 0;
@@ -1085,7 +1088,7 @@ hipError_t launch_run(const ChainPlan &p) {
     k.mc = reinterpret_cast<const McTab *>(ws + lay.mc);
     k.hist = Mtot > 1 ? p.hist_in : nullptr;
     k.ldh = Mtot > 1 ? Mtot - 1 : 0;
-    k.xcd_ks = xcd_window();
+    k.xcd_ks = xcd_window(lay.cpad / 2);
     const int64_t nblocks = (lay.cpad / 2) * k.ntiles;
     const bool s = p.S > 0;
     if (tz_fused) {
@@ -1135,7 +1138,7 @@ hipError_t launch_fir_pass(const ChainPlan &p, const WsLayout &lay, const float 
     k.twid = reinterpret_cast<const float2 *>(ws + lay.twid);
     k.hspec = reinterpret_cast<const float2 *>(ws + lay.hspec);
     k.nparts = fft_parts(Mtot);
-    k.xcd_ks = xcd_window();
+    k.xcd_ks = xcd_window(lay.cpad / 2);
     const int64_t nblocks = (lay.cpad / 2) * lay.ntiles;
     if (p.fir_mode == FIR_FFT && k.nparts > 1) return launch_main<FIR_FFT_PARTS, false>(k, nblocks, p.stream);
     return p.fir_mode == FIR_FFT ? launch_main<FIR_FFT, false>(k, nblocks, p.stream)

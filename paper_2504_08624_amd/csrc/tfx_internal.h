@@ -236,9 +236,9 @@ hipError_t launch_ws_status(void *ws, uint32_t *flags, int32_t clear, hipStream_
 hipError_t launch_prepare(const ChainPlan &p);
 // The filtering itself; may be repeated on a prepared workspace.
 hipError_t launch_run(const ChainPlan &p);
-// log2 of the block-order window K per XCD for the current device (0: block
-// ids in order); see xcd_order
-uint32_t xcd_window();
+// log2 of the block-order window K per XCD for the current device and a
+// grid of npairs channel pairs per tile (0: block ids in order); see xcd_order
+uint32_t xcd_window(int64_t npairs);
 
 // Merged tap count of the FIR stages (each extra stage adds len - 1).
 int32_t merged_taps(const StageList &f);
