@@ -442,9 +442,12 @@ __global__ __launch_bounds__(WGB, 8 / NV) void fir16k_kernel(F16Args a) {
         for (int v = 0; v < NV; ++v) {
             // eight bins at a time: their 4 loads issued together, the next
             // ones held back by a scheduling fence (registers)
-            const float4 *h4 = reinterpret_cast<const float4 *>(a.hs + 16 * (t + VS * v));
 #pragma unroll
             for (int hf = 0; hf < 2; ++hf) {
+                // (the lane index laundered per group, and the products pinned
+                // below: otherwise all 16 loads are issued first and hold 64
+                // registers)
+                const float4 *h4 = reinterpret_cast<const float4 *>(a.hs + 16 * (opaque(t) + VS * v));
                 float4 hq[4];
 #pragma unroll
                 for (int g = 0; g < 4; ++g) hq[g] = h4[4 * hf + g];
@@ -453,6 +456,8 @@ __global__ __launch_bounds__(WGB, 8 / NV) void fir16k_kernel(F16Args a) {
                     const int b = 8 * hf + 2 * g;
                     cmul_tw<false>(zr[v][b], zi[v][b], make_float2(hq[g].x, sg * hq[g].y));
                     cmul_tw<false>(zr[v][b + 1], zi[v][b + 1], make_float2(hq[g].z, sg * hq[g].w));
+                    // the products made here, before the next group's loads
+                    asm volatile("" : "+v"(zr[v][b]), "+v"(zi[v][b]), "+v"(zr[v][b + 1]), "+v"(zi[v][b + 1]));
                 }
                 __builtin_amdgcn_sched_barrier(0);
             }
