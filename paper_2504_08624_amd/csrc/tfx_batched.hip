@@ -235,13 +235,8 @@ __global__ __launch_bounds__(WG, 4) void batch_mc_kernel(BatchArgs a) {
     const int64_t tile = local / npairs, pair = local % npairs;
     const int64_t n0 = tile * T, rem = d.N - n0;
     const float *src[GROUPS];
-    float *dst[GROUPS];
 #pragma unroll
-    for (int g = 0; g < GROUPS; ++g) {
-        const bool valid = 2 * pair + g < d.C;
-        src[g] = valid ? d.x + (2 * pair + g) * d.ldx + n0 : nullptr;
-        dst[g] = valid ? d.y + (2 * pair + g) * d.ldy + n0 : nullptr;
-    }
+    for (int g = 0; g < GROUPS; ++g) src[g] = 2 * pair + g < d.C ? d.x + (2 * pair + g) * d.ldx + n0 : nullptr;
     mc_stage_pair(lds, src, rem, d.vec != 0, tid);
     if (d.S > 0) {  // block-uniform
         McCtx m;
@@ -261,6 +256,10 @@ __global__ __launch_bounds__(WG, 4) void batch_mc_kernel(BatchArgs a) {
     } else {
         __syncthreads();
     }
+    // (the output pointers formed here, not held across the cascade)
+    float *dst[GROUPS];
+#pragma unroll
+    for (int g = 0; g < GROUPS; ++g) dst[g] = 2 * pair + g < d.C ? d.y + (2 * pair + g) * d.ldy + n0 : nullptr;
     mc_store_pair(lds, dst, rem, d.vec != 0, tid);
 }
 

@@ -82,6 +82,7 @@ __device__ __forceinline__ void mc_load16(float (&f)[16], const float *src) {
 // The cascade part of a tile (phases (1) to (5)) on a channel pair whose
 // input chunks are in X (LDS, [192][MC_XS]); leaves the output chunks in X.
 // Every lane of the workgroup calls it.
+static_assert(GROUPS == 2, "McCtx users select between the two groups");
 struct McCtx {
     const McTab *mt;
     const CascTab *ct;
@@ -178,13 +179,16 @@ static __device__ void mc_cascade_tile(float *lds, const McCtx &m, int tid) {
         cc.lane = lane;
         cc.D = D;
         cc.depth = m.ct->depth;
-        cc.rec = m.rec[grp];
+        // (the per-group pointers selected, not indexed: a run-time index
+        // into the context's arrays would move them to scratch memory)
+        cc.rec = grp == 0 ? m.rec[0] : m.rec[1];
         cc.pos = m.pos;
         cc.epoch = m.epoch;
         cc.hdr = m.hdr;
-        cc.known = m.known[grp];
+        cc.known = grp == 0 ? m.known[0] : m.known[1];
         casc_lookback(cc, cT, cE, cP, cM);
-        if (m.ckpt[grp] && lane < D) m.ckpt[grp][lane] = cP[lane];
+        float *ck = grp == 0 ? m.ckpt[0] : m.ckpt[1];
+        if (ck && lane < D) ck[lane] = cP[lane];
         ev = ri < D ? cP[ri] : 0.f;
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
