@@ -122,6 +122,22 @@ def test_sos_backward_many_tiles():
     assert_rel(_cpu(gs), rgs, TOL_GRAD, "gsos")
 
 
+def test_sos_backward_xcd_window_order():
+    # 3 channel pairs x 120 tiles = 360 workgroups: on the whole 256-CU chip
+    # the cascade adjoint takes the XCD window order (one full window of 256
+    # workgroup ids, then a partial one)
+    C, N = 5, 120 * T + 77
+    x = _x(C, N, (306,))
+    g = _x(C, N, (307,), 1.0)
+    sec = _sections(3, (308,), r_hi=0.995)
+    xg, secg = _gpu(x), _gpu(sec)
+    _, ck = tfx.sos(xg, secg, return_ckpt=True)
+    gx, gs = tfx.sos_backward(xg, _gpu(g), secg, ck)
+    rgx, rgs = O.sos_backward(g, x, sec)
+    assert_close(_cpu(gx), rgx, TOL_GRAD, "gx")
+    assert_rel(_cpu(gs), rgs, TOL_GRAD, "gsos")
+
+
 # Fixed bars of the three ill-conditioned cases, set from measured errors: a
 # plain sequential fp32 adjoint (the cascade's conditioning floor in fp32)
 # already exceeds 1e-4 on the input gradient or the high-pass's coefficient

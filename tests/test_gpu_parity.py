@@ -81,6 +81,26 @@ def test_sos_slow_decay_deep_lookback(S, nres, r_lo, r_hi):
     assert_close(y, O.sos(x, sec), TOL_IIR_F32, "sos S=%d r in [%g, %g]" % (S, r_lo, r_hi))
 
 
+@pytest.mark.parametrize("S,fir", [(3, False), (7, False), (3, True)])
+def test_xcd_window_order_deep_lookback(S, fir):
+    # 3 channel pairs x 400 tiles = 1200 workgroups: on the whole 256-CU chip
+    # the forward kernels take the XCD window order (4 full windows of 256
+    # workgroup ids and a partial one), with slowly decaying sections whose
+    # tiles look several predecessors back (S = 7: the matrix-core cascade)
+    C, N = 5, 400 * T + 19
+    x = _x(C, N, (107, S))
+    x[:, ::7000] += 1.0
+    sec = _mixed_sections((108, S), S, 2, 0.997, 0.999)
+    if fir:
+        stages = [("fir", workloads.chain_short(C=1, N=16).stages[0][1]), ("sos", sec)]
+        y = _cpu(tfx.chain(_gpu(x), [(k, _gpu(c)) for k, c in stages]))
+        ref = O.chain(x, stages)
+    else:
+        y = _cpu(tfx.sos(_gpu(x), _gpu(sec)))
+        ref = O.sos(x, sec)
+    assert_close(y, ref, TOL_IIR_F32, "xcd order S=%d fir=%s" % (S, fir))
+
+
 def test_sos_many_tiles_lookback_windows():
     # 200 tiles per channel: look-back crosses several 64-tile windows
     C, N = 2, 200 * T + 5
