@@ -5,8 +5,8 @@
 // numbered clip by clip in a chosen clip order, tile-major within a clip, so a
 // tile's predecessors in time always have lower block ids and the decoupled
 // look-back of the chain kernel carries over unchanged.  A block finds its
-// clip by a binary search over the clips' first block ids in the descriptor
-// table the prepare step leaves in the workspace; every clip has its own
+// clip in the block map the prepare step leaves in the workspace (one read;
+// a 64-way search over the descriptor table took two dependent rounds); every clip has its own
 // section tables and look-back records.  The chunk length LC (and with it
 // the tile length 128 LC) is a template parameter, chosen per batch by the
 // autotuner among 16, 24 and 32.
@@ -44,6 +44,7 @@ __device__ void batch_section(const TB &tb, float (&v)[LC], const CarryCtx &cc, 
 
 struct BatchArgs {
     const ClipDesc *desc;
+    const int32_t *map;  // block id -> clip (written by the prepare step)
     int32_t nclips;
     const SecTab *tab;
     const CascTab *ctab;  // per clip (cascade-level variant)
@@ -52,25 +53,12 @@ struct BatchArgs {
     uint32_t *hdr;
 };
 
-// The last clip whose first block is <= id (first blocks never decrease):
-// a 64-way search by the first wave, two rounds for up to 4096 clips; thread
-// 0 writes it and the look-back epoch to LDS (the caller synchronises).
+// The block's clip (from the prepare step's block map) and the look-back
+// epoch, written to LDS by thread 0 (the caller synchronises).
 __device__ __forceinline__ void find_clip(const BatchArgs &a, int64_t id, int tid, int *s_clip, uint32_t *s_epoch) {
-    if (tid < 64) {
-        int lo = 0, n = a.nclips;
-        while (n > 1) {
-            const int step = (n + 63) / 64;
-            const int j = lo + tid * step;
-            const bool ok = j < lo + n && a.desc[j].blk0 <= id;
-            const int cnt = __popcll(__ballot(ok));  // >= 1: desc[lo].blk0 <= id
-            const int nlo = lo + (cnt - 1) * step;
-            n = min(step, lo + n - nlo);
-            lo = nlo;
-        }
-        if (tid == 0) {
-            *s_clip = lo;
-            *s_epoch = load_epoch(a.hdr, HDR_EPOCH);
-        }
+    if (tid == 0) {
+        *s_clip = a.map[id];
+        *s_epoch = load_epoch(a.hdr, HDR_EPOCH);
     }
 }
 
@@ -345,6 +333,8 @@ BatchLayout batch_plan(const ClipIn *clips, int32_t n, int lc, int order, ClipDe
     off += 256;
     lay.desc = off;
     off += al256b(sizeof(ClipDesc) * (size_t)(n > 0 ? n : 1));
+    lay.map = off;
+    off += al256b(sizeof(int32_t) * (size_t)(blk > 0 ? blk : 1));
     lay.tab = off;
     off += al256b(sizeof(SecTab) * (size_t)tab);
     lay.recs = off;
@@ -366,6 +356,7 @@ hipError_t launch_batch_run(const BatchLayout &lay, int lc, int32_t nclips, void
     char *w = static_cast<char *>(ws);
     BatchArgs a;
     a.desc = reinterpret_cast<const ClipDesc *>(w + lay.desc);
+    a.map = reinterpret_cast<const int32_t *>(w + lay.map);
     a.nclips = nclips;
     a.tab = reinterpret_cast<const SecTab *>(w + lay.tab);
     a.recs = reinterpret_cast<uint64_t *>(w + lay.recs);

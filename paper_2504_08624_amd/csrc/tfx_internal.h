@@ -280,7 +280,7 @@ struct alignas(16) ClipDesc {
 };
 
 struct BatchLayout {
-    size_t hdr, desc, tab, recs, casc, mc, total;
+    size_t hdr, desc, map, tab, recs, casc, mc, total;
     int64_t nblocks, nsec, nrec;
     int32_t smax;  // longest cascade of the batch
     bool casc_on;  // every cascade has at most CASC_MAX sections: one CascTab per clip

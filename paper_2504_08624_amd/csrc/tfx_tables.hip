@@ -502,8 +502,8 @@ __global__ void state_passthrough_kernel(const float *in, float *out, int64_t n)
     if (i < n) out[i] = in ? in[i] : 0.f;
 }
 
-// Batched clips: section tables of every clip (chunk length lc), cleared
-// look-back records, epoch 1.  Thread g < nsec builds section g, found by a
+// Batched clips: section tables of every clip (chunk length lc), the block
+// map, cleared look-back records, epoch 1.  Thread g < nsec builds section g, found by a
 // binary search over the clips' first table index.
 struct BatchPrepArgs {
     const ClipDesc *desc;
@@ -516,6 +516,8 @@ struct BatchPrepArgs {
     int32_t lc;
     CascTab *ctab;  // per clip, or null
     McTab *mtab;    // per clip, or null
+    int32_t *map;   // block id -> clip, nblocks entries
+    int64_t nblocks;
 };
 
 // Blocks g < nsec build section g; blocks nsec + c build clip c's cascade
@@ -523,6 +525,17 @@ struct BatchPrepArgs {
 __global__ __launch_bounds__(256) void batch_prep_kernel(BatchPrepArgs a) {
     const int tid = threadIdx.x;
     for (int64_t i = (int64_t)blockIdx.x * 256 + tid; i < a.nwords; i += (int64_t)gridDim.x * 256) a.recs[i] = 0ull;
+    // block map: the last clip whose first block is <= b (first blocks never
+    // decrease; a clip without blocks shares its first block with the next)
+    for (int64_t b = (int64_t)blockIdx.x * 256 + tid; b < a.nblocks; b += (int64_t)gridDim.x * 256) {
+        int lo = 0, hi = a.nclips - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) / 2;
+            if (a.desc[mid].blk0 <= b) lo = mid;
+            else hi = mid - 1;
+        }
+        a.map[b] = lo;
+    }
     if (blockIdx.x == 0 && tid == 0) {
         a.hdr[HDR_ERROR] = 0u;
         a.hdr[HDR_EPOCH] = 1u;
@@ -576,6 +589,8 @@ hipError_t launch_batch_prepare(const BatchLayout &lay, int lc, int32_t nclips, 
     a.lc = lc;
     a.ctab = lay.casc_on ? reinterpret_cast<CascTab *>(w + lay.casc) : nullptr;
     a.mtab = lay.mc_on ? reinterpret_cast<McTab *>(w + lay.mc) : nullptr;
+    a.map = reinterpret_cast<int32_t *>(w + lay.map);
+    a.nblocks = lay.nblocks;
     const int64_t nroles = a.nsec + (a.ctab ? nclips : 0) + (a.mtab ? nclips : 0);
     int64_t nb = (a.nwords + 255) / 256;
     if (nb > 2048) nb = 2048;
